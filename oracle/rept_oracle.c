@@ -1,0 +1,411 @@
+/*
+ * CPU oracle for REPT (Wang et al., "REPT: A Streaming Algorithm of Approximating Global and
+ * Local Triangle Counts in Parallel", arXiv:1811.09136).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, single-threaded statement of what
+ * the device path must compute.  It shares no code, header, table or helper with the device
+ * library; only the test suite, the smoke check and the bench's CPU-baseline leg use it.
+ *
+ * Conventions (the readings of the paper this oracle fixes):
+ *  - processors, groups and slots are 0-based: processor i belongs to group k = i / m and
+ *    owns slot j = i % m of that group's hash h_k : E -> [0, m) (Algorithm 2 uses this
+ *    floor/modulo mapping; Algorithm 1 is its one-group case);
+ *  - edges are undirected: h_k hashes the unordered pair (min, max);
+ *  - when a group has fewer than m processors (c < m, or the last group when m does not
+ *    divide c), an edge whose slot has no processor is stored by no processor of that group;
+ *  - an edge is counted before it is inserted (Algorithm 1: UpdateTriangleCNT precedes the
+ *    insertion), so N_u^(i) at time t holds only edges that arrived strictly earlier;
+ *  - counters are 64-bit integers.
+ *
+ * Hash family.  Section III-A asks for a uniform map with P(h(e)=i, h(e')=i') = 1/m^2; the
+ * variance of Theorem 3 also uses the joint behaviour of the first two edges of two triangles
+ * (up to four edges), so this oracle uses a 4-wise independent family: a degree-3 polynomial
+ * over the prime field GF(p), p = 2^61 - 1 (Carter and Wegman 1979; Wegman and Carter 1981).
+ * For group k the coefficients a_0..a_3 are SplitMix64 outputs 4k..4k+3 of the user seed
+ * (Steele, Lea, Flood, OOPSLA 2014), each shifted right by 3 and reduced mod p.  The edge
+ * key is x = lo * 2^32 + hi (lo = min(u,v), hi = max(u,v); x < p for ids below 2^29),
+ * h = a_3 x^3 + a_2 x^2 + a_1 x + a_0 mod p, and slot = floor(h * m / 2^61).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ERANGE (-2)
+#define OR_ESELFLOOP (-3)
+#define OR_EDUP (-4)
+#define OR_ENOMEM (-5)
+#define OR_ENOTSUP (-7)
+
+/* ------------------------------------------------------------------ hash ---------------- */
+
+/* SplitMix64: the state advances by the golden gamma, the output is the state mixed by two
+ * xor-shift-multiply rounds and a final xor-shift (Steele, Lea, Flood 2014). */
+static uint64_t splitmix64_next(uint64_t *state) {
+    uint64_t z = (*state += 0x9e3779b97f4a7c15ULL);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t oracle_splitmix64(uint64_t seed, uint64_t index) {
+    uint64_t s = seed, r = 0;
+    for (uint64_t i = 0; i <= index; ++i) r = splitmix64_next(&s);
+    return r;
+}
+
+#define P61 ((((uint64_t)1) << 61) - 1)
+
+/* group k's coefficients (a_0, a_1, a_2, a_3), written to params[4k .. 4k+3] */
+void oracle_hash_params(uint64_t seed, uint32_t G, uint64_t *params) {
+    uint64_t s = seed;
+    for (uint32_t i = 0; i < 4 * G; ++i) params[i] = (splitmix64_next(&s) >> 3) % P61;
+}
+
+uint32_t oracle_slot(const uint64_t *a, uint32_t m, uint32_t u, uint32_t v) {
+    const unsigned __int128 p = P61;
+    const uint64_t lo = u < v ? u : v, hi = u < v ? v : u;
+    const unsigned __int128 x = (unsigned __int128)((lo << 32) | hi) % p;
+    /* a_3 x^3 + a_2 x^2 + a_1 x + a_0 in GF(p), each power formed explicitly */
+    const unsigned __int128 x2 = (x * x) % p, x3 = (x2 * x) % p;
+    const unsigned __int128 h = (a[3] * x3 % p + a[2] * x2 % p + a[1] * x % p + a[0]) % p;
+    return (uint32_t)((h * m) >> 61);
+}
+
+/* slots of every edge for every group: out[k*E + t] = h_k(edge t) */
+void oracle_slots(uint64_t seed, uint32_t m, uint32_t G, const uint32_t *edges, uint64_t E,
+                  uint32_t *out) {
+    uint64_t *params = (uint64_t *)malloc(sizeof(uint64_t) * 4 * (G ? G : 1));
+    if (!params) return;
+    oracle_hash_params(seed, G, params);
+    for (uint32_t k = 0; k < G; ++k)
+        for (uint64_t t = 0; t < E; ++t)
+            out[(uint64_t)k * E + t] = oracle_slot(params + 4 * k, m, edges[2 * t], edges[2 * t + 1]);
+    free(params);
+}
+
+/* ------------------------------------------------------------------ edge set ------------ */
+
+typedef struct {
+    uint64_t *key; /* canonical pair + 1; 0 = empty */
+    uint64_t *val;
+    uint64_t mask, count;
+} edgeset;
+
+static uint64_t mix(uint64_t x) {
+    x ^= x >> 31;
+    x *= 0x7fb5d329728ea185ULL;
+    x ^= x >> 27;
+    x *= 0x81dadef4bc2dd44dULL;
+    x ^= x >> 33;
+    return x;
+}
+
+static int es_init(edgeset *s, uint64_t expect) {
+    uint64_t cap = 16;
+    while (cap < 2 * expect + 2) cap <<= 1;
+    s->key = (uint64_t *)calloc(cap, sizeof(uint64_t));
+    s->val = (uint64_t *)calloc(cap, sizeof(uint64_t));
+    s->mask = cap - 1;
+    s->count = 0;
+    return (s->key && s->val) ? 0 : -1;
+}
+static void es_free(edgeset *s) {
+    free(s->key);
+    free(s->val);
+    s->key = s->val = NULL;
+}
+static uint64_t pairkey(uint32_t u, uint32_t v) {
+    uint64_t lo = u < v ? u : v, hi = u < v ? v : u;
+    return (lo << 32) | hi;
+}
+/* 1 if inserted, 0 if present */
+static int es_put(edgeset *s, uint64_t k, uint64_t val) {
+    uint64_t h = mix(k) & s->mask, k1 = k + 1;
+    while (s->key[h]) {
+        if (s->key[h] == k1) return 0;
+        h = (h + 1) & s->mask;
+    }
+    s->key[h] = k1;
+    s->val[h] = val;
+    s->count++;
+    return 1;
+}
+static int es_get(const edgeset *s, uint64_t k, uint64_t *val) {
+    uint64_t h = mix(k) & s->mask, k1 = k + 1;
+    while (s->key[h]) {
+        if (s->key[h] == k1) {
+            if (val) *val = s->val[h];
+            return 1;
+        }
+        h = (h + 1) & s->mask;
+    }
+    return 0;
+}
+
+/* Section II: a simple undirected stream over nodes [0, n) */
+int oracle_validate(uint32_t n, const uint32_t *edges, uint64_t E) {
+    if (n > (1u << 29)) return OR_EINVAL; /* hash keys lo * 2^32 + hi must stay below 2^61 - 1 */
+    for (uint64_t t = 0; t < E; ++t) {
+        if (edges[2 * t] >= n || edges[2 * t + 1] >= n) return OR_ERANGE;
+    }
+    for (uint64_t t = 0; t < E; ++t) {
+        if (edges[2 * t] == edges[2 * t + 1]) return OR_ESELFLOOP;
+    }
+    edgeset s;
+    if (es_init(&s, E)) return OR_ENOMEM;
+    int rc = OR_OK;
+    for (uint64_t t = 0; t < E && rc == OR_OK; ++t) {
+        if (!es_put(&s, pairkey(edges[2 * t], edges[2 * t + 1]), t)) rc = OR_EDUP;
+    }
+    es_free(&s);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ Algorithm 1 ---------- */
+
+/* growable adjacency list of one processor's sampled graph */
+typedef struct {
+    uint32_t *nbr;
+    uint32_t len, cap;
+} adjlist;
+
+static int adj_push(adjlist *a, uint32_t w) {
+    if (a->len == a->cap) {
+        uint32_t nc = a->cap ? 2 * a->cap : 4;
+        uint32_t *p = (uint32_t *)realloc(a->nbr, nc * sizeof(uint32_t));
+        if (!p) return -1;
+        a->nbr = p;
+        a->cap = nc;
+    }
+    a->nbr[a->len++] = w;
+    return 0;
+}
+
+/*
+ * REPT per Algorithm 1, extended to c > m by independent groups (Section III-B).
+ *
+ * For every group k and every processor i = k*m + j of that group (j < c_k), the stream is
+ * replayed in order; for each edge (u, v) at time t:
+ *   UpdateTriangleCNT: N = N_u^(i) intersect N_v^(i); tau^(i) += |N|; tau_u^(i) += |N|;
+ *                      tau_v^(i) += |N|; tau_w^(i) += 1 for each w in N;
+ *   then, if h_k(u, v) == j, (u, v) joins E^(i).
+ * The counter updates are applied only for t in [t0, t1) (a window of stream positions); the
+ * insertions always happen, so a window's counts are the per-edge updates of that window.
+ *
+ * Outputs (accumulated, +=):
+ *   global[i]                    = tau^(i)                              (c entries)
+ *   local[k*n + v]               = sum over processors i of group k of tau_v^(i)   (per_proc = 0)
+ *   local[i*n + v]               = tau_v^(i)                                       (per_proc = 1)
+ * slot_override (optional, [G][E] uint16): replaces h_k(edge t) by slot_override[k*E + t].
+ */
+int oracle_rept(uint32_t n, uint32_t m, uint32_t c, uint64_t seed, int per_proc,
+                const uint32_t *edges, uint64_t E, uint64_t t0, uint64_t t1,
+                const uint16_t *slot_override, int64_t *global, int64_t *local) {
+    if (n == 0 || m == 0 || c == 0 || !edges || !global || !local) return OR_EINVAL;
+    if (t0 > t1 || t1 > E) return OR_EINVAL;
+    int rc = oracle_validate(n, edges, E);
+    if (rc) return rc;
+    const uint32_t G = (c + m - 1) / m;
+    uint64_t *params = (uint64_t *)malloc(sizeof(uint64_t) * 4 * G);
+    adjlist *adj = (adjlist *)calloc(n, sizeof(adjlist));
+    uint32_t *slot = (uint32_t *)malloc(sizeof(uint32_t) * (E ? E : 1));
+    if (!params || !adj || !slot) {
+        free(params);
+        free(adj);
+        free(slot);
+        return OR_ENOMEM;
+    }
+    oracle_hash_params(seed, G, params);
+
+    for (uint32_t k = 0; k < G && rc == OR_OK; ++k) {
+        const uint32_t ck = (k + 1 < G) ? m : c - (G - 1) * m; /* processors in group k */
+        for (uint64_t t = 0; t < E; ++t) {
+            slot[t] = slot_override ? slot_override[(uint64_t)k * E + t]
+                                    : oracle_slot(params + 4 * k, m, edges[2 * t], edges[2 * t + 1]);
+        }
+        for (uint32_t j = 0; j < ck && rc == OR_OK; ++j) {
+            const uint32_t i = k * m + j;
+            int64_t *loc = local + (uint64_t)(per_proc ? i : k) * n;
+            uint64_t mine = 0; /* |E^(i)| at the end of the stream */
+            for (uint64_t t = 0; t < E; ++t) mine += (slot[t] == j);
+            edgeset Ei; /* E^(i), for membership tests */
+            if (es_init(&Ei, mine)) {
+                rc = OR_ENOMEM;
+                break;
+            }
+            for (uint32_t x = 0; x < n; ++x) adj[x].len = 0;
+            for (uint64_t t = 0; t < E; ++t) {
+                const uint32_t u = edges[2 * t], v = edges[2 * t + 1];
+                if (t >= t0 && t < t1) {
+                    /* N_{u,v}^(i) = N_u^(i) intersect N_v^(i): walk the smaller set, test the other */
+                    const adjlist *small = adj[u].len <= adj[v].len ? &adj[u] : &adj[v];
+                    const uint32_t other = adj[u].len <= adj[v].len ? v : u;
+                    int64_t cnt = 0;
+                    for (uint32_t q = 0; q < small->len; ++q) {
+                        const uint32_t w = small->nbr[q];
+                        if (es_get(&Ei, pairkey(other, w), NULL)) {
+                            ++cnt;
+                            loc[w] += 1; /* tau_w^(i) += 1 */
+                        }
+                    }
+                    global[i] += cnt; /* tau^(i) += |N| */
+                    loc[u] += cnt;    /* tau_u^(i) += |N| */
+                    loc[v] += cnt;    /* tau_v^(i) += |N| */
+                }
+                if (slot[t] == j) { /* h_k(u,v) selects processor i: insert into E^(i) */
+                    es_put(&Ei, pairkey(u, v), t);
+                    if (adj_push(&adj[u], v) || adj_push(&adj[v], u)) {
+                        rc = OR_ENOMEM;
+                        break;
+                    }
+                }
+            }
+            es_free(&Ei);
+        }
+    }
+    for (uint32_t x = 0; x < n; ++x) free(adj[x].nbr);
+    free(adj);
+    free(slot);
+    free(params);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ per-edge form -------- */
+
+/*
+ * The per-edge update of Algorithm 1 evaluated directly from its definition, for all
+ * processors at once, for the stream positions listed in `ts` (any order, no repeats).
+ *
+ * At time t, N_u^(i) is the set of w such that edge {u, w} arrived before t and
+ * h_k({u, w}) selected processor i.  So for the edge (u, v) at time t, processor
+ * i = k*m + j gains one semi-triangle for every common neighbour w of u and v (in the whole
+ * stream graph) whose two edges {u, w}, {v, w} both arrived before t and both hash to slot j
+ * of group k, with j < c_k.  Counts are accumulated (+=) exactly as oracle_rept does for a
+ * window, so the two must agree; this form needs no replay of the stream and is what makes
+ * sampled checks possible on large streams.
+ *
+ * The static adjacency (neighbour, arrival time) is built once per call with a counting
+ * sort by vertex; each neighbour list is then searched linearly (plain, not fast).
+ */
+typedef struct {
+    uint32_t w;
+    uint32_t t;
+} nbr_t;
+
+static int cmp_nbr(const void *a, const void *b) {
+    const nbr_t *x = (const nbr_t *)a, *y = (const nbr_t *)b;
+    return (x->w > y->w) - (x->w < y->w);
+}
+
+int oracle_edge_updates(uint32_t n, uint32_t m, uint32_t c, uint64_t seed, int per_proc,
+                        const uint32_t *edges, uint64_t E, const uint64_t *ts, uint64_t nts,
+                        int64_t *global, int64_t *local) {
+    if (n == 0 || m == 0 || c == 0 || !edges || !global || !local) return OR_EINVAL;
+    for (uint64_t q = 0; q < nts; ++q)
+        if (ts[q] >= E) return OR_EINVAL;
+    int rc = oracle_validate(n, edges, E);
+    if (rc) return rc;
+    const uint32_t G = (c + m - 1) / m;
+    uint64_t *params = (uint64_t *)malloc(sizeof(uint64_t) * 4 * G);
+    uint64_t *off = (uint64_t *)calloc((uint64_t)n + 1, sizeof(uint64_t));
+    nbr_t *nb = (nbr_t *)malloc(sizeof(nbr_t) * 2 * (E ? E : 1));
+    uint64_t *fill = (uint64_t *)calloc((uint64_t)n, sizeof(uint64_t));
+    if (!params || !off || !nb || !fill) {
+        free(params);
+        free(off);
+        free(nb);
+        free(fill);
+        return OR_ENOMEM;
+    }
+    oracle_hash_params(seed, G, params);
+    for (uint64_t t = 0; t < E; ++t) {
+        off[edges[2 * t] + 1]++;
+        off[edges[2 * t + 1] + 1]++;
+    }
+    for (uint32_t x = 0; x < n; ++x) off[x + 1] += off[x];
+    for (uint64_t t = 0; t < E; ++t) {
+        const uint32_t u = edges[2 * t], v = edges[2 * t + 1];
+        nb[off[u] + fill[u]++] = (nbr_t){v, (uint32_t)t};
+        nb[off[v] + fill[v]++] = (nbr_t){u, (uint32_t)t};
+    }
+    for (uint32_t x = 0; x < n; ++x) qsort(nb + off[x], off[x + 1] - off[x], sizeof(nbr_t), cmp_nbr);
+
+    for (uint64_t q = 0; q < nts; ++q) {
+        const uint64_t t = ts[q];
+        const uint32_t u = edges[2 * t], v = edges[2 * t + 1];
+        /* common neighbours of u and v by a merge of the two id-sorted lists */
+        uint64_t a = off[u], ae = off[u + 1], b = off[v], be = off[v + 1];
+        while (a < ae && b < be) {
+            if (nb[a].w < nb[b].w) {
+                ++a;
+            } else if (nb[a].w > nb[b].w) {
+                ++b;
+            } else {
+                const uint32_t w = nb[a].w;
+                if (nb[a].t < t && nb[b].t < t) { /* both edges arrived before t */
+                    for (uint32_t k = 0; k < G; ++k) {
+                        const uint32_t ck = (k + 1 < G) ? m : c - (G - 1) * m;
+                        const uint32_t su = oracle_slot(params + 4 * k, m, u, w);
+                        const uint32_t sv = oracle_slot(params + 4 * k, m, v, w);
+                        if (su == sv && su < ck) {
+                            const uint32_t i = k * m + su;
+                            int64_t *loc = local + (uint64_t)(per_proc ? i : k) * n;
+                            global[i] += 1;
+                            loc[u] += 1;
+                            loc[v] += 1;
+                            loc[w] += 1;
+                        }
+                    }
+                }
+                ++a;
+                ++b;
+            }
+        }
+    }
+    free(params);
+    free(off);
+    free(nb);
+    free(fill);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ estimators ----------- */
+
+/*
+ * Estimators for c <= m (Algorithm 1, Section III-A) and for c > m with m dividing c
+ * (Section III-B, case c2 = 0):
+ *   tau_hat   = m^2 / c * sum_i tau^(i)          (equals m / c1 * sum when c = c1 * m)
+ *   tau_v_hat = m^2 / c * sum_i tau_v^(i)
+ * evaluated as ((double)S * (double)(m*m)) / (double)c in IEEE binary64, round to nearest.
+ * The sum S is exact in 64-bit integers; S >= 2^53 is refused (the conversion would round).
+ * c > m with c % m != 0 (Algorithm 2) is not handled here.
+ * local_rows: rows of `local` (G group sums, or c per-processor rows); all rows are summed.
+ */
+int oracle_estimate(uint32_t n, uint32_t m, uint32_t c, uint32_t local_rows,
+                    const int64_t *global, const int64_t *local, double *tau_hat, double *tau_v_hat) {
+    if (n == 0 || m == 0 || c == 0 || !global || !tau_hat) return OR_EINVAL;
+    if (c > m && c % m != 0) return OR_ENOTSUP;
+    const int64_t lim = (int64_t)1 << 53;
+    const double scale_num = (double)((uint64_t)m * (uint64_t)m);
+    const double denom = (double)c;
+    int64_t S = 0;
+    for (uint32_t i = 0; i < c; ++i) {
+        if (global[i] < 0 || global[i] >= lim - S) return OR_ERANGE;
+        S += global[i];
+    }
+    *tau_hat = ((double)S * scale_num) / denom;
+    if (tau_v_hat && local) {
+        for (uint32_t v = 0; v < n; ++v) {
+            int64_t Sv = 0;
+            for (uint32_t r = 0; r < local_rows; ++r) {
+                const int64_t x = local[(uint64_t)r * n + v];
+                if (x < 0 || x >= lim - Sv) return OR_ERANGE;
+                Sv += x;
+            }
+            tau_v_hat[v] = ((double)Sv * scale_num) / denom;
+        }
+    }
+    return OR_OK;
+}

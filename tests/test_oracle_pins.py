@@ -1,0 +1,318 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (CPU only).
+
+Each test checks the oracle against something other than itself: closed-form counts, a
+definition-level brute force, invariants of Algorithm 1's updates, the sampling probabilities
+of Theorem 1, the unbiasedness and variance of Theorem 3, published generator outputs, and a
+hand-built stream.  A plausible slip in the oracle (a dropped counter update, counting after
+insertion instead of before, a wrong processor index, a transposed edge, a wrong estimator
+scale) fails at least one of them.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    expects, rows = {}, []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if line.startswith("# expect"):
+            k, *vals = line[len("# expect"):].split()
+            expects[k] = [int(v) for v in vals]
+        elif line and not line.startswith("#"):
+            rows.append([int(x) for x in line.split()])
+    return expects, rows
+
+
+# ---------------------------------------------------------------------------- P5 hand-built
+
+def test_k4_hand_built_stream():
+    exp, rows = _golden("k4_stream.txt")
+    e = np.array(rows, dtype=np.uint32)
+    g, l = oracle.rept(e, 4, 1, 1, 0)
+    assert g.tolist() == exp["global"]
+    assert l[0].tolist() == exp["local"]
+    # per-edge updates 0,0,1,0,1,2 (counted before insertion)
+    per_edge = [int(oracle.edge_updates(e, 4, 1, 1, 0, [t])[0][0]) for t in range(6)]
+    assert per_edge == [0, 0, 1, 0, 1, 2]
+
+
+# ---------------------------------------------------------------------------- hash pins
+
+def test_splitmix64_reference_outputs():
+    _, rows = _golden("splitmix64_seed1234567.txt")
+    for idx, val in rows:
+        assert oracle.splitmix64(1234567, idx) == val
+
+
+def test_hash_params_are_consecutive_splitmix_draws():
+    hp = oracle.hash_params(42, 3)
+    p = 2**61 - 1
+    assert [int(x) for x in hp.ravel()] == [(oracle.splitmix64(42, i) >> 3) % p for i in range(12)]
+
+
+def test_hash_basic_properties():
+    e = synth.config1_stream()
+    s = oracle.slots(e, 10, 4, 7)
+    assert s.shape == (4, len(e)) and s.max() < 10
+    flipped = np.ascontiguousarray(e[:, ::-1])
+    assert np.array_equal(oracle.slots(flipped, 10, 4, 7), s)  # undirected: h(u,v) = h(v,u)
+    assert (oracle.slots(e, 1, 2, 7) == 0).all()  # m = 1: one slot
+    # groups use independent parameters: their slot sequences differ
+    assert (s[0] != s[1]).mean() > 0.8
+
+
+def test_hash_uniform_and_collision_rates():
+    """Theorem 1: r given edges land in one given processor with probability 1/m^r, so two
+    distinct edges share a slot with probability 1/m and three with probability 1/m^2."""
+    m = 10
+    e = synth.er(5000, 200000, 3, 4)
+    s = oracle.slots(e, m, 1, 2024)[0].astype(np.int64)
+    counts = np.bincount(s, minlength=m)
+    expected = len(s) / m
+    chi2 = ((counts - expected) ** 2 / expected).sum()
+    assert chi2 < 40.0  # chi^2 with 9 dof: 40 is far beyond the 0.9999 quantile (~33.7)
+    rng = np.random.default_rng(5)
+    i = rng.integers(0, len(s), size=(400000, 3))
+    i = i[(i[:, 0] != i[:, 1]) & (i[:, 1] != i[:, 2]) & (i[:, 0] != i[:, 2])]
+    pair = (s[i[:, 0]] == s[i[:, 1]]).mean()
+    triple = ((s[i[:, 0]] == s[i[:, 1]]) & (s[i[:, 1]] == s[i[:, 2]])).mean()
+    assert abs(pair - 1 / m) < 0.004
+    assert abs(triple - 1 / m**2) < 0.0012
+
+
+# ---------------------------------------------------------------------------- P1/P4 closed forms
+
+@pytest.mark.parametrize("n", [3, 4, 7, 12])
+def test_complete_graph(n):
+    e = synth.shuffled(synth.complete(n), 10 + n, 20 + n)
+    g, l = oracle.rept(e, n, 1, 1, 0)
+    assert g[0] == math.comb(n, 3)
+    assert (l[0] == math.comb(n - 1, 2)).all()
+
+
+@pytest.mark.parametrize("n", [4, 5, 9])
+def test_cycle_and_bipartite_have_none(n):
+    e = synth.shuffled(synth.cycle(n), 1, 2)
+    g, l = oracle.rept(e, n, 1, 1, 0)
+    assert g[0] == 0 and l.sum() == 0
+    e = synth.shuffled(synth.complete_bipartite(n, n + 1), 3, 4)
+    g, l = oracle.rept(e, 2 * n + 1, 1, 1, 0)
+    assert g[0] == 0 and l.sum() == 0
+
+
+@pytest.mark.parametrize("n", [4, 6, 11])
+def test_wheel(n):
+    e = synth.shuffled(synth.wheel(n), 5, 6)
+    g, l = oracle.rept(e, n + 1, 1, 1, 0)
+    assert g[0] == n
+    assert l[0, 0] == n and (l[0, 1:] == 2).all()
+
+
+@pytest.mark.parametrize("k", [1, 3, 8])
+def test_friendship(k):
+    e = synth.shuffled(synth.friendship(k), 7, 8)
+    g, l = oracle.rept(e, 2 * k + 1, 1, 1, 0)
+    assert g[0] == k
+    assert l[0, 0] == k and (l[0, 1:] == 1).all()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_m1_equals_exact_triangle_counts(seed):
+    """m = 1: every edge is stored, each triangle is counted once (at its last edge), so
+    tau^(0) = tau and tau_v^(0) = tau_v; checked against trace(A^3)/6 and diag(A^3)/2."""
+    n = 40 + 7 * seed
+    e = synth.er(n, 4 * n, 100 + seed, 200 + seed)
+    tau, tau_v = brute.exact_counts(e, n)
+    g, l = oracle.rept(e, n, 1, 1, seed)
+    assert g[0] == tau and np.array_equal(l[0], tau_v)
+    # c > m = 1: every group is a full copy
+    g, l = oracle.rept(e, n, 1, 3, seed)
+    assert (g == tau).all() and all(np.array_equal(l[k], tau_v) for k in range(3))
+
+
+def test_m1_config1_exact():
+    e = synth.config1_stream()
+    tau, tau_v = brute.exact_counts(e, 2000)
+    g, l = oracle.rept(e, 2000, 1, 1, 0)
+    assert g[0] == tau and np.array_equal(l[0], tau_v)
+
+
+# ---------------------------------------------------------------------------- P3 definition
+
+@pytest.mark.parametrize("seed", range(3))
+def test_algorithm1_matches_semi_triangle_definition(seed):
+    """Algorithm 1's counters equal the semi-triangle counts of Section III: a triangle counts
+    on processor i iff its first two edges are stored by i (any last edge)."""
+    n = 24
+    e = synth.er(n, 110, 300 + seed, 400 + seed)
+    for m in range(1, 7):
+        for c in range(1, 3 * m + 1):
+            hs = 1000 * seed + 10 * m + c
+            sl = oracle.slots(e, m, -(-c // m), hs)
+            for per_proc in (False, True):
+                g, l = oracle.rept(e, n, m, c, hs, per_proc=per_proc)
+                bg, bl = brute.semi_triangle_counts(e, n, m, c, lambda k, t: int(sl[k, t]), per_proc)
+                assert np.array_equal(g, bg), (m, c)
+                assert np.array_equal(l, bl), (m, c)
+
+
+def test_slot_override_matches_definition():
+    """Arbitrary slot assignments (not from the hash): the replay and the definition agree."""
+    rng = np.random.default_rng(9)
+    n = 20
+    e = synth.er(n, 90, 5, 6)
+    for m, c in [(2, 2), (3, 5), (4, 9)]:
+        G = -(-c // m)
+        for _ in range(5):
+            ov = rng.integers(0, m, size=(G, len(e))).astype(np.uint16)
+            g, l = oracle.rept(e, n, m, c, 0, slot_override=ov)
+            bg, bl = brute.semi_triangle_counts(e, n, m, c, lambda k, t: int(ov[k, t]))
+            assert np.array_equal(g, bg) and np.array_equal(l, bl)
+
+
+def test_semi_triangle_order_semantics():
+    """Stream (0,1),(1,2),(0,2) with slots (s1, s2, s3): processor j counts the triangle iff
+    s1 = s2 = j, whatever s3 is (its last edge need not be stored)."""
+    e = np.array([(0, 1), (1, 2), (0, 2)], dtype=np.uint32)
+    for s1, s2, s3 in itertools.product(range(2), repeat=3):
+        ov = np.array([[s1, s2, s3]], dtype=np.uint16)
+        g, l = oracle.rept(e, 3, 2, 2, 0, slot_override=ov, per_proc=True)
+        for j in range(2):
+            want = int(s1 == s2 == j)
+            assert g[j] == want and (l[j] == want).all()
+        g1, _ = oracle.rept(e, 3, 2, 1, 0, slot_override=ov)  # c = 1 < m: only slot 0 exists
+        assert g1[0] == int(s1 == s2 == 0)
+
+
+# ---------------------------------------------------------------------------- P2/P9 invariants
+
+def test_local_sum_is_three_times_global():
+    e = synth.config1_stream()
+    for m, c, pp in [(10, 10, False), (10, 40, False), (4, 3, True), (3, 11, True)]:
+        g, l = oracle.rept(e, 2000, m, c, 77, per_proc=pp)
+        if pp:
+            assert np.array_equal(l.sum(axis=1), 3 * g)
+        else:
+            G = -(-c // m)
+            for k in range(G):
+                assert l[k].sum() == 3 * g[k * m:(k + 1) * m].sum()
+
+
+def test_windows_are_additive_and_match_per_edge_form():
+    e = synth.er(400, 5000, 13, 14)
+    n, m, c, s = 400, 3, 7, 5
+    full = oracle.rept(e, n, m, c, s)
+    cuts = [0, 700, 701, 3000, 5000]
+    acc = [np.zeros_like(full[0]), np.zeros_like(full[1])]
+    for t0, t1 in zip(cuts[:-1], cuts[1:]):
+        w = oracle.rept(e, n, m, c, s, t0=t0, t1=t1)
+        pe = oracle.edge_updates(e, n, m, c, s, np.arange(t0, t1))
+        assert np.array_equal(w[0], pe[0]) and np.array_equal(w[1], pe[1])
+        acc[0] += w[0]
+        acc[1] += w[1]
+    assert np.array_equal(acc[0], full[0]) and np.array_equal(acc[1], full[1])
+    rng = np.random.default_rng(3)
+    ts = rng.choice(len(e), 300, replace=False)
+    pe = oracle.edge_updates(e, n, m, c, s, ts, per_proc=True)
+    tot = [np.zeros(c, np.int64), np.zeros((c, n), np.int64)]
+    for t in ts:
+        w = oracle.rept(e, n, m, c, s, per_proc=True, t0=int(t), t1=int(t) + 1)
+        tot[0] += w[0]
+        tot[1] += w[1]
+    assert np.array_equal(pe[0], tot[0]) and np.array_equal(pe[1], tot[1])
+
+
+def test_orientation_and_order_independence_of_inputs():
+    """Edges are undirected: flipping every pair changes nothing; reordering the stream
+    changes the counts only through which edge is last (m = 1 totals are order-free)."""
+    e = synth.er(300, 2500, 1, 2)
+    a = oracle.rept(e, 300, 4, 8, 3)
+    b = oracle.rept(np.ascontiguousarray(e[:, ::-1]), 300, 4, 8, 3)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    r = synth.shuffled(e, 9)
+    assert oracle.rept(r, 300, 1, 1, 0)[0][0] == oracle.rept(e, 300, 1, 1, 0)[0][0]
+
+
+def test_validation_codes():
+    e = synth.er(30, 60, 1, 2)
+    assert oracle.validate(30, e) == oracle.OK
+    bad = e.copy(); bad[5] = (4, 4)
+    assert oracle.validate(30, bad) == oracle.ESELFLOOP
+    bad = e.copy(); bad[9] = e[3][::-1]
+    assert oracle.validate(30, bad) == oracle.EDUP
+    bad = e.copy(); bad[0] = (0, 30)
+    assert oracle.validate(30, bad) == oracle.ERANGE
+    with pytest.raises(oracle.OracleError):
+        oracle.rept(bad, 30, 2, 2, 0)
+
+
+# ---------------------------------------------------------------------------- P10 estimator
+
+def test_estimator_special_cases():
+    # m = 1, c = 1: the count itself
+    assert oracle.estimate(3, 1, 1, [1349])[0] == 1349.0
+    # c = m: m^2/c = m exactly
+    th, tv = oracle.estimate(3, 10, 10, [13] * 10, np.array([[1, 2, 3]]))
+    assert th == 1300.0 and tv.tolist() == [10.0, 20.0, 30.0]
+    # c = 4m (c2 = 0): m / c1 = m^2 / c
+    th, _ = oracle.estimate(3, 10, 40, [1] * 40)
+    assert th == 100.0
+    # c < m: m^2 / c
+    th, _ = oracle.estimate(3, 8, 3, [1, 1, 1])
+    assert th == 64.0
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.estimate(3, 10, 15, [0] * 15)  # c > m, c % m != 0: Algorithm 2's estimator
+    assert ei.value.code == oracle.ENOTSUP
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.estimate(3, 2, 2, [2**52, 2**52])  # sum reaches 2^53
+    assert ei.value.code == oracle.ERANGE
+    with pytest.raises(oracle.OracleError):
+        oracle.estimate(3, 2, 2, [-1, 0])
+
+
+@pytest.mark.parametrize("m,c", [(4, 4), (4, 2), (3, 6)])
+def test_estimator_unbiased_with_theorem3_variance(m, c):
+    """Theorem 3 (and Section III-B for m | c): E[tau_hat] = tau and
+    Var[tau_hat] = (tau (m^2 - c) + 2 eta (m - c)) / c for c <= m, tau (m - 1) / c1 for c = c1 m.
+    Checked over R independent hash seeds on a graph with many edge-sharing triangles."""
+    n = 30
+    e = synth.shuffled(synth.er(n, 160, 41, 42), 43)
+    tau, tau_v = brute.exact_counts(e, n)
+    eta = brute.eta(e, n)
+    if c <= m:
+        var = (tau * (m * m - c) + 2 * eta * (m - c)) / c
+    else:
+        var = tau * (m - 1) / (c // m)
+    R = 1500
+    seeds = synth.u64(7, m * 100 + c, R)
+    est = np.empty(R)
+    for r in range(R):
+        g, _ = oracle.rept(e, n, m, c, int(seeds[r]))
+        est[r] = oracle.estimate(n, m, c, g)[0]
+    assert abs(est.mean() - tau) < 4.0 * math.sqrt(var / R)
+    ratio = est.var(ddof=1) / var
+    assert 0.8 < ratio < 1.25, (ratio, tau, eta)
+
+
+def test_local_estimator_unbiased():
+    n = 30
+    e = synth.shuffled(synth.er(n, 160, 41, 42), 43)
+    tau, tau_v = brute.exact_counts(e, n)
+    m, c, R = 3, 3, 1200
+    acc = np.zeros(n)
+    for r in range(R):
+        g, l = oracle.rept(e, n, m, c, 5000 + r)
+        acc += oracle.estimate(n, m, c, g, l)[1]
+    v = int(np.argmax(tau_v))
+    sd = math.sqrt(tau_v[v] * (m - 1) / R)  # Var(tau_v_hat) = tau_v (m - 1) when c = m
+    assert abs(acc[v] / R - tau_v[v]) < 4 * sd
