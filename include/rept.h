@@ -1,0 +1,229 @@
+/*
+ * rept.h -- C ABI of the MI355X (gfx950) REPT semi-triangle counting library.
+ *
+ * REPT (Wang, Jia, Qi, Sun, Tao, Guan, arXiv:1811.09136) estimates the global and local
+ * triangle counts of an undirected edge stream (Section II).  Processor i of c keeps the
+ * edges its hash selects (sampling probability p = 1/m; c > m uses ceil(c/m) groups with
+ * independent hashes, Section III-B).  For every stream edge (u, v) at time t it counts the
+ * common neighbours w of u and v among its own edges that arrived before t, adds that count
+ * to its global counter tau^(i) and to the local counters of u and v, and adds one to the
+ * local counter of each w (Algorithm 1, UpdateTriangleCNT).  The estimators scale the sums
+ * of these counters (Sections III-A, III-B).
+ *
+ * This library computes those integer counters exactly, for all processors at once, on the
+ * GPU; `rept_estimate` forms the estimators on the host.
+ *
+ * Conventions shared by every call:
+ *  - ids are 0-based: nodes in [0, n); processor i in [0, c) is slot j = i % m of group
+ *    k = i / m (the mapping Algorithm 2 states); group k has c_k = m processors, except the
+ *    last, which has c - (G-1)*m, G = ceil(c/m).  An edge whose slot has no processor in a
+ *    group is stored by no processor of that group.
+ *  - the stream is an array of `num_edges` pairs (u, v) of uint32, row t = the edge arriving
+ *    at time t.  Edges are undirected; the stream must be simple: u != v, u < n, v < n, no
+ *    unordered pair twice.  num_edges < 2^31.
+ *  - an edge is counted before it is inserted (Algorithm 1), so an edge never closes a
+ *    triangle with itself and "before t" is strict.
+ *  - hash: a 4-wise independent family (Section III-A asks for uniform, independent slots;
+ *    Theorem 3's variance involves up to four edges at once): for group k the coefficients
+ *    a_0..a_3 are SplitMix64 outputs 4k..4k+3 of the state `seed` (Steele, Lea, Flood 2014),
+ *    each >> 3 and reduced mod p = 2^61 - 1; with x = lo * 2^32 + hi (lo = min(u, v),
+ *    hi = max(u, v)), h = a_3 x^3 + a_2 x^2 + a_1 x + a_0 mod p and slot = floor(h * m / 2^61).
+ *    Node ids are limited to n <= 2^29 so that distinct edges have distinct keys x < p.
+ *  - "device" pointers are HIP device memory of the current device; "host" pointers are
+ *    ordinary host memory.  `stream` is a hipStream_t passed as void* (NULL = null stream).
+ *  - the library never allocates device memory: the caller owns every device byte.
+ *  - every call returns a rept_status; nothing throws.  On an error return, no output and
+ *    no handle is produced.
+ */
+#ifndef REPT_H
+#define REPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rept_status {
+    REPT_OK = 0,
+    REPT_EINVAL = -1,     /* bad argument: zero n/m/c, null pointer, size too small, ... */
+    REPT_ERANGE = -2,     /* node id >= n, or an estimator sum >= 2^53 */
+    REPT_ESELFLOOP = -3,  /* an edge (u, u) */
+    REPT_EDUP = -4,       /* an unordered pair appears twice */
+    REPT_ENOMEM = -5,     /* a caller-provided buffer is smaller than required */
+    REPT_EDEVICE = -6,    /* a HIP runtime call failed */
+    REPT_ENOTSUP = -7     /* outside what this library implements (see each call) */
+} rept_status;
+
+/* rept_params.flags */
+#define REPT_LOCAL_PER_PROC 1u /* local counters per processor [c][n] instead of per group [G][n] */
+
+/* REPT sampling parameters (Table I: p = 1/m, c processors; plus the hash seed). */
+typedef struct rept_params {
+    uint32_t m;     /* 1/p, 1 <= m <= 65536 (m = 1 counts every triangle once per group) */
+    uint32_t c;     /* processors, 1 <= c <= 8*m (at most 8 hash groups) */
+    uint64_t seed;  /* seed of the hash parameters */
+    uint32_t flags; /* REPT_LOCAL_PER_PROC or 0 */
+    uint32_t reserved; /* must be 0 */
+} rept_params;
+
+/* Opaque host-side handle to a built graph.  It points into the caller's persistent device
+ * buffer, which must outlive it.  Use from one host thread at a time. */
+typedef struct rept_graph rept_graph;
+
+typedef struct rept_graph_info {
+    uint32_t n;             /* nodes */
+    uint64_t num_edges;     /* stream edges */
+    uint32_t num_apex;      /* nodes with at least two higher-ranked neighbours */
+    uint32_t max_out_degree;/* largest oriented out-degree */
+    uint64_t oriented_work; /* sum over oriented edges (a->b) of outdeg(b): entries the count reads */
+    uint64_t sum_out_sq;    /* sum over nodes of outdeg^2 */
+} rept_graph_info;
+
+/* Number of local-counter rows for `params`: G = ceil(c/m), or c with REPT_LOCAL_PER_PROC.
+ * The local output of every count call is int64[rows][n], row-major.  Returns 0 on bad
+ * params. */
+uint32_t rept_local_rows(const rept_params* params);
+
+/*
+ * Device bytes needed to build a graph of n nodes and num_edges stream edges.
+ *   persistent_bytes: kept by the built graph (oriented adjacency: 8 bytes per edge plus
+ *                     8 bytes per node, rounded up);
+ *   scratch_bytes:    needed only during rept_build.
+ * Host only, no device work.  EINVAL if n == 0, n > 2^29 or num_edges >= 2^31.
+ */
+rept_status rept_query_sizes(uint32_t n, uint64_t num_edges, size_t* persistent_bytes,
+                             size_t* scratch_bytes);
+
+/*
+ * Validate the stream (Section II: a simple undirected graph) and build the device data the
+ * counting pass reads: every edge oriented from its lower- to its higher-ranked endpoint
+ * (rank = (degree, id)), grouped by the lower endpoint and sorted by neighbour id, with each
+ * entry holding (neighbour id, arrival time t).
+ *
+ * edges:      device, uint32[num_edges][2], read only, not retained after return.
+ * persistent: device, >= persistent_bytes from rept_query_sizes, 256-byte aligned; owned by the
+ *             caller, must stay allocated and unmodified while the handle is used.
+ * scratch:    device, >= scratch_bytes, 256-byte aligned; free to reuse after return.
+ * stream:     hipStream_t; the call enqueues its work there and synchronises that stream
+ *             once, to read the validation result.
+ * out:        receives a new handle on success.
+ * Errors: EINVAL (bad sizes/pointers), ERANGE, ESELFLOOP, EDUP (invalid stream),
+ *         ENOMEM (buffers too small), EDEVICE.
+ */
+rept_status rept_build(uint32_t n, const uint32_t* edges, uint64_t num_edges, void* persistent,
+                       size_t persistent_bytes, void* scratch, size_t scratch_bytes, void* stream,
+                       rept_graph** out);
+
+/* Statistics of a built graph (host only). */
+rept_status rept_graph_get_info(const rept_graph* graph, rept_graph_info* info);
+
+/*
+ * The counting pass of Algorithm 1 (Section III-A), for every processor at once: all per-edge
+ * updates of the whole stream.  Overwrites the outputs (idempotent).
+ *   global: device int64[c]      -- global[i] = tau^(i)
+ *   local:  device int64[rows][n] -- rows = rept_local_rows(params): per group k the sum over
+ *           its processors of tau_v^(i), or tau_v^(i) per processor with REPT_LOCAL_PER_PROC.
+ * Asynchronous on `stream`.  Errors: EINVAL, ENOTSUP (more than 8 groups or m > 65536), EDEVICE.
+ */
+rept_status rept_count(const rept_graph* graph, const rept_params* params, int64_t* global,
+                       int64_t* local, void* stream);
+
+/*
+ * The per-edge updates of the stream edges at times t in [t0, t1) only, ADDED (+=) to the
+ * outputs.  Counts are additive over disjoint windows (Algorithm 1 updates per edge), so
+ * windows that tile [0, num_edges) sum to rept_count.  Same layout and errors as rept_count;
+ * EINVAL if t0 > t1 or t1 > num_edges.
+ */
+rept_status rept_count_range(const rept_graph* graph, const rept_params* params, uint64_t t0,
+                             uint64_t t1, int64_t* global, int64_t* local, void* stream);
+
+/*
+ * Estimators (host, FP64).  For c <= m (Algorithm 1) and for c > m with m | c (Section III-B,
+ * c2 = 0) both reduce to
+ *     tau_hat   = ((double)S   * (double)(m*m)) / (double)c,   S   = sum_i tau^(i)
+ *     tau_v_hat = ((double)S_v * (double)(m*m)) / (double)c,   S_v = sum of the local rows at v
+ * with the sums exact in int64 and one rounding each for the product and the quotient.
+ *   global: host int64[c]; local: host int64[rows][n] or NULL; tau_v_hat: host double[n] or NULL.
+ * Errors: EINVAL; ENOTSUP for c > m with c % m != 0 (Algorithm 2's combined estimator);
+ *         ERANGE if a sum is negative or >= 2^53.
+ */
+rept_status rept_estimate(uint32_t n, const rept_params* params, const int64_t* global,
+                          const int64_t* local, double* tau_hat, double* tau_v_hat);
+
+/*
+ * The edge-to-processor hash of every stream edge for every group (Section III-A: h(u, v)
+ * picks the processor that stores the edge; Section III-B: one independent h_k per group).
+ *   edges: device uint32[num_edges][2]; slots: device uint32[G][num_edges].
+ * Asynchronous.  Errors: EINVAL, ENOTSUP (more than 8 groups), EDEVICE.
+ */
+rept_status rept_hash_slots(const rept_params* params, const uint32_t* edges, uint64_t num_edges,
+                            uint32_t* slots, void* stream);
+
+/* ------------------------------------------------------------------ batched counting ------ */
+
+/* rept_job.flags */
+#define REPT_JOB_ACCUMULATE 1u /* add to the outputs instead of overwriting them */
+
+/* One counting job of a batch: the updates of stream window [t0, t1) (t1 = UINT64_MAX: to
+ * the end) restricted to work units [unit0, unit1) (unit1 = UINT32_MAX: all).  Work units
+ * are the graph's apex nodes (rept_graph_info.num_apex of them); the counts of any partition
+ * of the units sum to the counts of the whole, which is what lets a job be split into chunks. */
+typedef struct rept_job {
+    const rept_graph* graph;
+    rept_params params;
+    int64_t* global; /* device int64[c] */
+    int64_t* local;  /* device int64[rows][n] */
+    uint64_t t0, t1;
+    uint32_t unit0, unit1;
+    uint32_t flags;
+    uint32_t reserved;
+} rept_job;
+
+/* Launch shape of the counting kernels; zero fields take the library defaults. */
+typedef struct rept_tuning {
+    uint32_t wave_cap;       /* apexes with out-degree <= wave_cap run one per wavefront (16..512) */
+    uint32_t block_cap;      /* adjacency chunk staged in LDS by the per-workgroup path (64..4096) */
+    uint32_t light_blocks;   /* workgroups of the wavefront-per-apex kernel (0: 8 per CU) */
+    uint32_t heavy_blocks;   /* workgroups of the workgroup-per-apex kernel (0: 2 per CU) */
+    uint32_t heavy_threads;  /* threads per workgroup of that kernel: 256, 512 or 1024 */
+    uint32_t reserved[3];
+} rept_tuning;
+
+/* Device workspace bytes for a batch of njobs jobs. */
+rept_status rept_batch_workspace_size(uint32_t njobs, size_t* bytes);
+
+/*
+ * Write the job table of a batch into `workspace` (device, >= rept_batch_workspace_size
+ * bytes, 256-byte aligned) with one host-to-device copy on `stream`.  After it, every
+ * launch of rept_batch_launch(workspace) runs this batch; the job table holds only device
+ * pointers and sizes, so a launch can be captured into a HIP graph and replayed.
+ * Errors: EINVAL, ENOTSUP, ENOMEM, EDEVICE.
+ */
+rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_tuning* tuning,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
+/* Run a prepared batch: one persistent launch per kernel kind drains a device work queue over
+ * all jobs.  Asynchronous; performs no host synchronisation and no allocation. */
+rept_status rept_batch_launch(void* workspace, void* stream);
+
+/* rept_batch_prepare followed by rept_batch_launch. */
+rept_status rept_batch_count(const rept_job* jobs, uint32_t njobs, const rept_tuning* tuning,
+                             void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------ misc ------------------ */
+
+/* Free the host handle only (the persistent device buffer stays the caller's). */
+void rept_destroy(rept_graph* graph);
+
+/* Static string for a status code. */
+const char* rept_status_str(int status);
+
+/* Compute units of the current device (host query; 0 on error). */
+uint32_t rept_device_cus(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* REPT_H */

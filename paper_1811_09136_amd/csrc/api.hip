@@ -1,0 +1,348 @@
+// C ABI of the REPT counting library (declarations and contracts in include/rept.h).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+#include <unordered_map>
+
+#include "common.h"
+
+namespace {
+
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): Weyl-sequence state, two multiply/xor-shift
+// mixing rounds.  Group k's hash coefficients a_0..a_3 are outputs 4k..4k+3 from state `seed`,
+// each shifted right by 3 and reduced modulo the Mersenne prime 2^61 - 1.
+struct SplitMix64 {
+    uint64_t s;
+    uint64_t next() {
+        s += 0x9e3779b97f4a7c15ULL;
+        uint64_t z = s;
+        z ^= z >> 30;
+        z *= 0xbf58476d1ce4e5b9ULL;
+        z ^= z >> 27;
+        z *= 0x94d049bb133111ebULL;
+        return z ^ (z >> 31);
+    }
+};
+
+void group_params(uint64_t seed, uint32_t G, uint64_t* hp) {
+    const uint64_t p61 = (1ull << 61) - 1;
+    SplitMix64 r{seed};
+    for (uint32_t q = 0; q < 4 * G; ++q) {
+        uint64_t v = r.next() >> 3;  // < 2^61 = p61 + 1
+        hp[q] = v == p61 ? 0 : v;
+    }
+}
+
+bool params_ok(const rept_params* p) {
+    if (!p || p->m == 0 || p->c == 0 || p->reserved != 0) return false;
+    if (p->flags & ~REPT_LOCAL_PER_PROC) return false;
+    return true;
+}
+
+uint32_t groups_of(const rept_params* p) { return (p->c + p->m - 1) / p->m; }
+
+struct Shape {
+    BatchHeader hdr;
+};
+std::mutex g_mu;
+std::unordered_map<void*, Shape> g_shapes;  // prepared batch workspaces -> launch shape
+
+bool valid_graph(const rept_graph* g) { return g && g->magic == REPT_MAGIC; }
+
+// Fill the launch shape for jobs of at most G_max groups and at most c_max processors.
+rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint64_t zero_words, bool any_zero,
+                        const rept_tuning* tu, BatchHeader* h) {
+    memset(h, 0, sizeof(*h));
+    const uint32_t cus = rept_num_cus() ? rept_num_cus() : 256;
+    uint32_t wave_cap = (tu && tu->wave_cap) ? tu->wave_cap : 128;
+    uint32_t block_cap = (tu && tu->block_cap) ? tu->block_cap : 1024;
+    uint32_t heavy_threads = (tu && tu->heavy_threads) ? tu->heavy_threads : 512;
+    if (wave_cap < 16 || wave_cap > 512) return REPT_EINVAL;
+    if (block_cap < 64 || block_cap > 4096) return REPT_EINVAL;
+    if (heavy_threads != 256 && heavy_threads != 512 && heavy_threads != 1024) return REPT_EINVAL;
+    const uint32_t hist_c = c_max <= REPT_HIST_CAP ? c_max : 0;
+    const uint32_t lds_cap = 160 * 1024;
+    uint32_t light_lds = rept_light_lds(wave_cap, G_max, hist_c);
+    uint32_t heavy_lds = rept_heavy_lds(block_cap, G_max, hist_c);
+    if (light_lds > lds_cap || heavy_lds > lds_cap) return REPT_EINVAL;
+    h->njobs = njobs;
+    h->wave_cap = wave_cap;
+    h->block_cap = block_cap;
+    h->light_blocks = (tu && tu->light_blocks) ? tu->light_blocks : 8 * cus;
+    h->heavy_blocks = (tu && tu->heavy_blocks) ? tu->heavy_blocks : 2 * cus;
+    h->heavy_threads = heavy_threads;
+    h->light_tile = 8;
+    h->hist_c = hist_c;
+    h->G_max = G_max;
+    h->light_lds = light_lds;
+    h->heavy_lds = heavy_lds;
+    h->any_zero = any_zero ? 1u : 0u;
+    h->zero_words = zero_words;
+    return REPT_OK;
+}
+
+rept_status make_job(const rept_job& jb, JobDev* d, uint64_t* zero_words) {
+    const rept_graph* g = jb.graph;
+    if (!valid_graph(g) || !params_ok(&jb.params) || !jb.global || !jb.local) return REPT_EINVAL;
+    const uint32_t G = groups_of(&jb.params);
+    if (G > REPT_GMAX || jb.params.m > 65536) return REPT_ENOTSUP;  // slots are staged as 16-bit
+    memset(d, 0, sizeof(*d));
+    d->off = g->off;
+    d->nbr = g->nbr;
+    d->tim = g->tim;
+    d->apex = g->apex;
+    d->global = jb.global;
+    d->local = jb.local;
+    group_params(jb.params.seed, G, d->hp);
+    d->n = g->n;
+    d->m = jb.params.m;
+    d->c = jb.params.c;
+    d->G = G;
+    d->per_proc = (jb.params.flags & REPT_LOCAL_PER_PROC) ? 1u : 0u;
+    d->rows = d->per_proc ? jb.params.c : G;
+    d->accumulate = (jb.flags & REPT_JOB_ACCUMULATE) ? 1u : 0u;
+    const uint64_t t1 = jb.t1 > g->E ? g->E : jb.t1;
+    if (jb.t0 > t1) return REPT_EINVAL;
+    d->t0 = (uint32_t)jb.t0;
+    d->t1 = (uint32_t)t1;
+    const uint32_t u1 = jb.unit1 > g->num_apex ? g->num_apex : jb.unit1;
+    if (jb.unit0 > u1) return REPT_EINVAL;
+    d->unit0 = jb.unit0;
+    d->unit1 = u1;
+    *zero_words = (uint64_t)d->c + (uint64_t)d->rows * d->n;
+    return REPT_OK;
+}
+
+rept_status count_one(const rept_graph* graph, const rept_params* params, uint64_t t0, uint64_t t1,
+                      bool accumulate, int64_t* global, int64_t* local, void* stream) {
+    if (!valid_graph(graph) || !params_ok(params) || !global || !local) return REPT_EINVAL;
+    if (t0 > t1 || t1 > graph->E) return REPT_EINVAL;
+    if (groups_of(params) > REPT_GMAX || params->m > 65536) return REPT_ENOTSUP;
+    rept_job jb;
+    memset(&jb, 0, sizeof(jb));
+    jb.graph = graph;
+    jb.params = *params;
+    jb.global = global;
+    jb.local = local;
+    jb.t0 = t0;
+    jb.t1 = t1;
+    jb.unit0 = 0;
+    jb.unit1 = UINT32_MAX;
+    jb.flags = accumulate ? REPT_JOB_ACCUMULATE : 0u;
+    JobDev d;
+    uint64_t zw = 0;
+    rept_status st = make_job(jb, &d, &zw);
+    if (st != REPT_OK) return st;
+    BatchHeader h;
+    st = make_header(1, d.G, d.c, zw, !accumulate, nullptr, &h);
+    if (st != REPT_OK) return st;
+    if (rept_launch_single(graph->ctrl, h, d, (hipStream_t)stream) != hipSuccess) return REPT_EDEVICE;
+    return REPT_OK;
+}
+
+}  // namespace
+
+uint32_t rept_num_cus() {
+    static int cached_dev = -1;
+    static uint32_t cached = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (dev != cached_dev) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        cached = (uint32_t)v;
+        cached_dev = dev;
+    }
+    return cached;
+}
+
+extern "C" {
+
+uint32_t rept_local_rows(const rept_params* p) {
+    if (!params_ok(p)) return 0;
+    return (p->flags & REPT_LOCAL_PER_PROC) ? p->c : groups_of(p);
+}
+
+rept_status rept_query_sizes(uint32_t n, uint64_t num_edges, size_t* persistent_bytes, size_t* scratch_bytes) {
+    if (n == 0 || n > (1u << 29) || num_edges >= (1ull << 31) || !persistent_bytes || !scratch_bytes)
+        return REPT_EINVAL;
+    rept_sizes_impl(n, num_edges, persistent_bytes, scratch_bytes);
+    return REPT_OK;
+}
+
+rept_status rept_build(uint32_t n, const uint32_t* edges, uint64_t num_edges, void* persistent,
+                       size_t persistent_bytes, void* scratch, size_t scratch_bytes, void* stream,
+                       rept_graph** out) {
+    if (!out || n == 0 || n > (1u << 29) || num_edges >= (1ull << 31) || !persistent || !scratch)
+        return REPT_EINVAL;
+    if (num_edges > 0 && !edges) return REPT_EINVAL;
+    if (((uintptr_t)edges & 7u) || ((uintptr_t)persistent & 255u) || ((uintptr_t)scratch & 255u))
+        return REPT_EINVAL;
+    return rept_build_impl(n, edges, num_edges, persistent, persistent_bytes, scratch, scratch_bytes,
+                           (hipStream_t)stream, out);
+}
+
+rept_status rept_graph_get_info(const rept_graph* g, rept_graph_info* info) {
+    if (!valid_graph(g) || !info) return REPT_EINVAL;
+    info->n = g->n;
+    info->num_edges = g->E;
+    info->num_apex = g->num_apex;
+    info->max_out_degree = g->max_out;
+    info->oriented_work = g->work;
+    info->sum_out_sq = g->sum_out_sq;
+    return REPT_OK;
+}
+
+rept_status rept_count(const rept_graph* graph, const rept_params* params, int64_t* global, int64_t* local,
+                       void* stream) {
+    if (!valid_graph(graph)) return REPT_EINVAL;
+    return count_one(graph, params, 0, graph->E, false, global, local, stream);
+}
+
+rept_status rept_count_range(const rept_graph* graph, const rept_params* params, uint64_t t0, uint64_t t1,
+                             int64_t* global, int64_t* local, void* stream) {
+    return count_one(graph, params, t0, t1, true, global, local, stream);
+}
+
+rept_status rept_estimate(uint32_t n, const rept_params* params, const int64_t* global, const int64_t* local,
+                          double* tau_hat, double* tau_v_hat) {
+    if (!params_ok(params) || n == 0 || !global || !tau_hat) return REPT_EINVAL;
+    const uint32_t m = params->m, c = params->c;
+    if (c > m && c % m != 0) return REPT_ENOTSUP;
+    const int64_t limit = (int64_t)1 << 53;
+    const double num = (double)((uint64_t)m * (uint64_t)m);
+    const double den = (double)c;
+    int64_t S = 0;
+    for (uint32_t i = 0; i < c; ++i) {
+        const int64_t x = global[i];
+        if (x < 0 || x >= limit - S) return REPT_ERANGE;
+        S += x;
+    }
+    double* tv = tau_v_hat;
+    if (tv && local) {
+        const uint32_t rows = rept_local_rows(params);
+        for (uint32_t v = 0; v < n; ++v) {
+            int64_t Sv = 0;
+            for (uint32_t r = 0; r < rows; ++r) {
+                const int64_t x = local[(uint64_t)r * n + v];
+                if (x < 0 || x >= limit - Sv) return REPT_ERANGE;
+                Sv += x;
+            }
+            const double prod = (double)Sv * num;
+            tv[v] = prod / den;
+        }
+    }
+    const double prod = (double)S * num;
+    *tau_hat = prod / den;
+    return REPT_OK;
+}
+
+rept_status rept_hash_slots(const rept_params* params, const uint32_t* edges, uint64_t num_edges, uint32_t* slots,
+                            void* stream) {
+    if (!params_ok(params) || (num_edges && (!edges || !slots))) return REPT_EINVAL;
+    if ((uintptr_t)edges & 7u) return REPT_EINVAL;
+    const uint32_t G = groups_of(params);
+    if (G > REPT_GMAX) return REPT_ENOTSUP;
+    if (num_edges == 0) return REPT_OK;
+    uint64_t hp[4 * REPT_GMAX] = {0};
+    group_params(params->seed, G, hp);
+    if (rept_launch_slots(hp, G, params->m, edges, num_edges, slots, (hipStream_t)stream) != hipSuccess)
+        return REPT_EDEVICE;
+    return REPT_OK;
+}
+
+rept_status rept_batch_workspace_size(uint32_t njobs, size_t* bytes) {
+    if (!bytes || njobs == 0 || njobs > 65535) return REPT_EINVAL;
+    *bytes = (sizeof(BatchHeader) + (size_t)njobs * sizeof(JobDev) + 255) & ~(size_t)255;
+    return REPT_OK;
+}
+
+rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_tuning* tuning, void* workspace,
+                               size_t workspace_bytes, void* stream) {
+    size_t need = 0;
+    if (!jobs || !workspace || rept_batch_workspace_size(njobs, &need) != REPT_OK) return REPT_EINVAL;
+    if ((uintptr_t)workspace & 255u) return REPT_EINVAL;
+    if (workspace_bytes < need) return REPT_ENOMEM;
+    const size_t bytes = sizeof(BatchHeader) + (size_t)njobs * sizeof(JobDev);
+    uint8_t* host = (uint8_t*)calloc(1, bytes);
+    if (!host) return REPT_ENOMEM;
+    JobDev* hj = (JobDev*)(host + sizeof(BatchHeader));
+    uint32_t G_max = 1, c_max = 1;
+    uint64_t zero_words = 0;
+    bool any_zero = false;
+    for (uint32_t j = 0; j < njobs; ++j) {
+        uint64_t zw = 0;
+        rept_status st = make_job(jobs[j], &hj[j], &zw);
+        if (st != REPT_OK) {
+            free(host);
+            return st;
+        }
+        G_max = hj[j].G > G_max ? hj[j].G : G_max;
+        c_max = hj[j].c > c_max ? hj[j].c : c_max;
+        if (!hj[j].accumulate) {
+            any_zero = true;
+            zero_words = zw > zero_words ? zw : zero_words;
+        }
+    }
+    BatchHeader h;
+    rept_status st = make_header(njobs, G_max, c_max, zero_words, any_zero, tuning, &h);
+    if (st != REPT_OK) {
+        free(host);
+        return st;
+    }
+    memcpy(host, &h, sizeof(h));
+    hipError_t e = hipMemcpyAsync(workspace, host, bytes, hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);  // `host` is freed below
+    free(host);
+    if (e != hipSuccess) return REPT_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_shapes[workspace] = Shape{h};
+    return REPT_OK;
+}
+
+rept_status rept_batch_launch(void* workspace, void* stream) {
+    BatchHeader h;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_shapes.find(workspace);
+        if (it == g_shapes.end()) return REPT_EINVAL;
+        h = it->second.hdr;
+    }
+    if (rept_launch_batch(workspace, h, (hipStream_t)stream) != hipSuccess) return REPT_EDEVICE;
+    return REPT_OK;
+}
+
+rept_status rept_batch_count(const rept_job* jobs, uint32_t njobs, const rept_tuning* tuning, void* workspace,
+                             size_t workspace_bytes, void* stream) {
+    rept_status st = rept_batch_prepare(jobs, njobs, tuning, workspace, workspace_bytes, stream);
+    if (st != REPT_OK) return st;
+    return rept_batch_launch(workspace, stream);
+}
+
+void rept_destroy(rept_graph* graph) {
+    if (valid_graph(graph)) {
+        graph->magic = 0;
+        free(graph);
+    }
+}
+
+const char* rept_status_str(int status) {
+    switch (status) {
+        case REPT_OK: return "ok";
+        case REPT_EINVAL: return "invalid argument";
+        case REPT_ERANGE: return "value out of range";
+        case REPT_ESELFLOOP: return "self-loop in stream";
+        case REPT_EDUP: return "duplicate edge in stream";
+        case REPT_ENOMEM: return "buffer too small";
+        case REPT_EDEVICE: return "device error";
+        case REPT_ENOTSUP: return "not supported";
+        default: return "unknown status";
+    }
+}
+
+uint32_t rept_device_cus(void) { return rept_num_cus(); }
+
+}  // extern "C"

@@ -1,0 +1,542 @@
+// Graph build for the counting pass: validation, degree orientation, and the oriented
+// adjacency (neighbour id + arrival time) grouped by lower-ranked endpoint and sorted by
+// neighbour id.
+//
+// The stream positions are the arrival times of Section II; the validation enforces the
+// simple undirected graph the paper assumes.  Orientation is this library's device layout
+// (not part of the paper): each undirected edge is stored once, at its endpoint of lower
+// rank (degree, id), so that every triangle is reachable from exactly one apex and every
+// adjacency segment is short (at most sqrt(2E) entries).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "common.h"
+
+namespace {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+constexpr int MEDIUM_MAX = 4096;  // segments sorted in LDS by one workgroup
+constexpr int SMALL_MAX = 64;     // segments sorted in registers by one wavefront
+
+__device__ __forceinline__ bool rank_less(uint32_t x, uint32_t dx, uint32_t y, uint32_t dy) {
+    return dx < dy || (dx == dy && x < y);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// exclusive scan of one value per thread over a 256-thread block; returns the block total
+__device__ uint32_t block_excl_scan256(uint32_t v, uint32_t& total) {
+    __shared__ uint32_t wsum[SCAN_THREADS / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_THREADS / 64; ++w) {
+        if (w < wid) base += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    total = tot;
+    return base + inc - v;
+}
+
+template <typename T>
+__device__ T block_reduce_sum256(T v) {
+    __shared__ T red[SCAN_THREADS / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    T s = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < SCAN_THREADS / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;  // valid in thread 0
+}
+
+// ---------------------------------------------------------------- exclusive scan (u32) ----
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(const uint32_t* __restrict__ in, uint64_t N,
+                                                               uint32_t* __restrict__ part) {
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    uint32_t s = 0;
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        uint64_t i = base + (uint64_t)r * SCAN_THREADS + threadIdx.x;
+        if (i < N) s += in[i];
+    }
+    uint32_t t = block_reduce_sum256<uint32_t>(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_top(uint32_t* part, uint32_t nparts) {
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t carry;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < nparts; base += 1024) {
+        uint32_t i = base + threadIdx.x;
+        uint32_t v = i < nparts ? part[i] : 0;
+        uint32_t inc = wave_incl_scan(v);
+        if (lane == 63) wsum[wid] = inc;
+        __syncthreads();
+        uint32_t pre = 0, tot = 0;
+        for (int w = 0; w < 16; ++w) {
+            if (w < wid) pre += wsum[w];
+            tot += wsum[w];
+        }
+        uint32_t c = carry;
+        if (i < nparts) part[i] = c + pre + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + tot;
+        __syncthreads();
+    }
+}
+
+// out[i] = sum of in[0..i), out[N] = total
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(const uint32_t* __restrict__ in, uint64_t N,
+                                                             const uint32_t* __restrict__ part,
+                                                             uint32_t* __restrict__ out) {
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        uint64_t i = base + r;
+        v[r] = i < N ? in[i] : 0;
+        s += v[r];
+    }
+    uint32_t total;
+    uint32_t pre = block_excl_scan256(s, total) + part[blockIdx.x];
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS; ++r) {
+        uint64_t i = base + r;
+        if (i < N) out[i] = pre;
+        pre += v[r];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_THREADS - 1) out[N] = pre;
+}
+
+// ---------------------------------------------------------------- build kernels ----------
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t count, uint32_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// degrees, range and self-loop checks
+__global__ void k_degree(const uint2* __restrict__ edges, uint64_t E, uint32_t n, uint32_t* deg,
+                         BuildStats* st) {
+    uint32_t bad = 0;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < E;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        uint2 e = edges[t];
+        if (e.x >= n || e.y >= n) {
+            bad |= RF_RANGE;
+            continue;
+        }
+        if (e.x == e.y) {
+            bad |= RF_SELFLOOP;
+            continue;
+        }
+        atomicAdd(&deg[e.x], 1u);
+        atomicAdd(&deg[e.y], 1u);
+    }
+    if (bad) atomicOr(&st->flags, bad);
+}
+
+// out-degree of each lower-ranked endpoint
+__global__ void k_orient_count(const uint2* __restrict__ edges, uint64_t E, uint32_t n,
+                               const uint32_t* __restrict__ deg, uint32_t* dout) {
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < E;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        uint2 e = edges[t];
+        if (e.x >= n || e.y >= n || e.x == e.y) continue;
+        uint32_t a = rank_less(e.x, deg[e.x], e.y, deg[e.y]) ? e.x : e.y;
+        atomicAdd(&dout[a], 1u);
+    }
+}
+
+// place every oriented entry (b, t) in its apex segment (unordered within the segment)
+__global__ void __launch_bounds__(SCAN_THREADS) k_scatter(const uint2* __restrict__ edges, uint64_t E, uint32_t n,
+                                                          const uint32_t* __restrict__ deg,
+                                                          const uint32_t* __restrict__ dout,
+                                                          const uint32_t* __restrict__ off, uint32_t* cursor,
+                                                          unsigned long long* __restrict__ packed,
+                                                          BuildStats* st) {
+    unsigned long long work = 0;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < E;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        uint2 e = edges[t];
+        if (e.x >= n || e.y >= n || e.x == e.y) continue;
+        bool xa = rank_less(e.x, deg[e.x], e.y, deg[e.y]);
+        uint32_t a = xa ? e.x : e.y, b = xa ? e.y : e.x;
+        uint32_t pos = off[a] + atomicAdd(&cursor[a], 1u);
+        packed[pos] = ((unsigned long long)b << 32) | (uint32_t)t;
+        work += dout[b];
+    }
+    unsigned long long s = block_reduce_sum256<unsigned long long>(work);
+    if (threadIdx.x == 0 && s) atomicAdd(&st->work, s);
+}
+
+// classify segments by size, histogram apexes by out-degree (descending order buckets)
+__global__ void __launch_bounds__(SCAN_THREADS) k_classify(const uint32_t* __restrict__ off, uint32_t n,
+                                                           uint32_t* ahist, uint32_t* medium,
+                                                           uint32_t* large, BuildStats* st) {
+    unsigned long long sq = 0;
+    uint32_t mx = 0, napex = 0;
+    for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
+        uint32_t d = off[a + 1] - off[a];
+        sq += (unsigned long long)d * d;
+        mx = d > mx ? d : mx;
+        if (d >= 2) {
+            atomicAdd(&ahist[n - 1 - d], 1u);
+            ++napex;
+        }
+        if (d > SMALL_MAX && d <= MEDIUM_MAX) medium[atomicAdd(&st->n_medium, 1u)] = a;
+        if (d > MEDIUM_MAX) large[atomicAdd(&st->n_large, 1u)] = a;
+    }
+    unsigned long long s = block_reduce_sum256<unsigned long long>(sq);
+    uint32_t na = block_reduce_sum256<uint32_t>(napex);
+    // max via shuffles
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        uint32_t o = __shfl_xor(mx, d, 64);
+        mx = o > mx ? o : mx;
+    }
+    if ((threadIdx.x & 63) == 0 && mx) atomicMax(&st->max_out, mx);
+    if (threadIdx.x == 0) {
+        if (s) atomicAdd(&st->sum_out_sq, s);
+        if (na) atomicAdd(&st->num_apex, na);
+    }
+}
+
+__global__ void k_apex_scatter(const uint32_t* __restrict__ off, uint32_t n, const uint32_t* __restrict__ aoff,
+                               uint32_t* acur, uint32_t* apex) {
+    for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
+        uint32_t d = off[a + 1] - off[a];
+        if (d < 2) continue;
+        uint32_t bkt = n - 1 - d;
+        apex[aoff[bkt] + atomicAdd(&acur[bkt], 1u)] = a;
+    }
+}
+
+__device__ __forceinline__ void emit_sorted(unsigned long long v, uint32_t idx, uint32_t seg, uint32_t d,
+                                            uint32_t* nbr, uint32_t* tim) {
+    if (idx < d) {
+        nbr[seg + idx] = (uint32_t)(v >> 32);
+        tim[seg + idx] = (uint32_t)v;
+    }
+}
+
+// segments of at most 64 entries: one wavefront, bitonic network across lanes
+__global__ void __launch_bounds__(256) k_sort_small(const uint32_t* __restrict__ off, uint32_t n,
+                                                    const unsigned long long* __restrict__ packed,
+                                                    uint32_t* __restrict__ nbr, uint32_t* __restrict__ tim,
+                                                    BuildStats* st) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    uint32_t dup = 0;
+    for (uint32_t a = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); a < n; a += waves) {
+        const uint32_t s = off[a], d = off[a + 1] - s;
+        if (d == 0 || d > SMALL_MAX) continue;
+        unsigned long long v = lane < (int)d ? packed[s + lane] : ~0ull;
+        for (int k = 2; k <= 64; k <<= 1) {
+            for (int j = k >> 1; j >= 1; j >>= 1) {
+                unsigned long long o = __shfl_xor(v, j, 64);
+                bool up = (lane & k) == 0;
+                bool lower = (lane & j) == 0;
+                bool take_min = (lower == up);
+                v = take_min ? (o < v ? o : v) : (o > v ? o : v);
+            }
+        }
+        unsigned long long prev = __shfl_up(v, 1, 64);
+        if (lane > 0 && lane < (int)d && (prev >> 32) == (v >> 32)) dup = 1;
+        emit_sorted(v, lane, s, d, nbr, tim);
+    }
+    if (dup) atomicOr(&st->flags, RF_DUP);
+}
+
+// segments of 65..4096 entries: one workgroup, bitonic sort in LDS
+__global__ void __launch_bounds__(512) k_sort_medium(const uint32_t* __restrict__ off, const uint32_t* __restrict__ list,
+                                                     const unsigned long long* __restrict__ packed,
+                                                     uint32_t* __restrict__ nbr, uint32_t* __restrict__ tim,
+                                                     BuildStats* st) {
+    __shared__ unsigned long long buf[MEDIUM_MAX];
+    const uint32_t cnt = st->n_medium;
+    for (uint32_t q = blockIdx.x; q < cnt; q += gridDim.x) {
+        const uint32_t a = list[q];
+        const uint32_t s = off[a], d = off[a + 1] - s;
+        uint32_t P = 128;
+        while (P < d) P <<= 1;
+        for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) buf[i] = i < d ? packed[s + i] : ~0ull;
+        __syncthreads();
+        for (uint32_t k = 2; k <= P; k <<= 1) {
+            for (uint32_t j = k >> 1; j >= 1; j >>= 1) {
+                for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
+                    uint32_t l = i ^ j;
+                    if (l > i) {
+                        unsigned long long x = buf[i], y = buf[l];
+                        bool up = (i & k) == 0;
+                        if ((x > y) == up) {
+                            buf[i] = y;
+                            buf[l] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        uint32_t dup = 0;
+        for (uint32_t i = threadIdx.x; i < d; i += blockDim.x) {
+            unsigned long long v = buf[i];
+            if (i > 0 && (buf[i - 1] >> 32) == (v >> 32)) dup = 1;
+            nbr[s + i] = (uint32_t)(v >> 32);
+            tim[s + i] = (uint32_t)v;
+        }
+        if (dup) atomicOr(&st->flags, RF_DUP);
+        __syncthreads();
+    }
+}
+
+// segments above 4096 entries: one wavefront, stable LSD radix sort (8-bit digits of the
+// neighbour id) ping-ponging between `packed` and `alt` over the segment's own range
+__global__ void __launch_bounds__(64) k_sort_large(const uint32_t* __restrict__ off, const uint32_t* __restrict__ list,
+                                                   unsigned long long* packed, unsigned long long* alt,
+                                                   uint32_t id_bits, uint32_t* __restrict__ nbr,
+                                                   uint32_t* __restrict__ tim, BuildStats* st) {
+    __shared__ uint32_t base[256];
+    const int lane = threadIdx.x;
+    const uint32_t cnt = st->n_large;
+    const uint32_t passes = (id_bits + 7) / 8;
+    for (uint32_t q = blockIdx.x; q < cnt; q += gridDim.x) {
+        const uint32_t a = list[q];
+        const uint32_t s = off[a], d = off[a + 1] - s;
+        unsigned long long* src = packed + s;
+        unsigned long long* dst = alt + s;
+        for (uint32_t pass = 0; pass < passes; ++pass) {
+            const uint32_t shift = 32 + 8 * pass;
+            for (int b = lane; b < 256; b += 64) base[b] = 0;
+            __syncthreads();
+            for (uint32_t i = lane; i < d; i += 64) atomicAdd(&base[(uint32_t)(src[i] >> shift) & 255u], 1u);
+            __syncthreads();
+            if (lane == 0) {
+                uint32_t run = 0;
+                for (int b = 0; b < 256; ++b) {
+                    uint32_t c = base[b];
+                    base[b] = run;
+                    run += c;
+                }
+            }
+            __syncthreads();
+            for (uint32_t c0 = 0; c0 < d; c0 += 64) {
+                const uint32_t i = c0 + lane;
+                const bool valid = i < d;
+                unsigned long long v = valid ? src[i] : 0ull;
+                uint32_t dig = (uint32_t)(v >> shift) & 255u;
+                unsigned long long peers = __ballot(valid);
+                for (int bit = 0; bit < 8; ++bit) {
+                    unsigned long long bb = __ballot(valid && ((dig >> bit) & 1u));
+                    peers &= ((dig >> bit) & 1u) ? bb : ~bb;
+                }
+                const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+                uint32_t rank = __popcll(peers & lt);
+                uint32_t pos = valid ? base[dig] + rank : 0;
+                __syncthreads();
+                if (valid) {
+                    dst[pos] = v;
+                    int last = 63 - __clzll(peers);
+                    if (lane == last) base[dig] += __popcll(peers);
+                }
+                __syncthreads();
+            }
+            unsigned long long* tmp = src;
+            src = dst;
+            dst = tmp;
+        }
+        uint32_t dup = 0;
+        for (uint32_t i = lane; i < d; i += 64) {
+            unsigned long long v = src[i];
+            if (i > 0 && (src[i - 1] >> 32) == (v >> 32)) dup = 1;
+            nbr[s + i] = (uint32_t)(v >> 32);
+            tim[s + i] = (uint32_t)v;
+        }
+        if (dup) atomicOr(&st->flags, RF_DUP);
+        __syncthreads();
+    }
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t ctrl, off, nbr, tim, apex, total;
+};
+struct ScratchLayout {
+    size_t stats, deg, dout, cursor, ahist, aoff, part, packed, alt, medium, large, total;
+};
+
+Layout persistent_layout(uint32_t n, uint64_t E) {
+    Layout L;
+    size_t p = 0;
+    L.ctrl = p;
+    p += align256(REPT_CTRL_BYTES);
+    L.off = p;
+    p += align256(((size_t)n + 1) * 4);
+    L.nbr = p;
+    p += align256((size_t)E * 4);
+    L.tim = p;
+    p += align256((size_t)E * 4);
+    L.apex = p;
+    p += align256((size_t)n * 4);
+    L.total = p;
+    return L;
+}
+
+ScratchLayout scratch_layout(uint32_t n, uint64_t E) {
+    ScratchLayout S;
+    size_t p = 0;
+    const size_t nparts = ((size_t)n + 1 + SCAN_TILE - 1) / SCAN_TILE + 1;
+    S.stats = p;
+    p += align256(sizeof(BuildStats));
+    S.deg = p;
+    p += align256((size_t)n * 4);
+    S.dout = p;
+    p += align256((size_t)n * 4);
+    S.cursor = p;
+    p += align256((size_t)n * 4);
+    S.ahist = p;
+    p += align256((size_t)n * 4);
+    S.aoff = p;
+    p += align256(((size_t)n + 1) * 4);
+    S.part = p;
+    p += align256(nparts * 4);
+    S.packed = p;
+    p += align256((size_t)E * 8);
+    S.alt = p;
+    p += align256((size_t)E * 8);
+    S.medium = p;
+    p += align256((size_t)n * 4);
+    S.large = p;
+    p += align256((size_t)n * 4);
+    S.total = p;
+    return S;
+}
+
+hipError_t scan_u32(const uint32_t* in, uint64_t N, uint32_t* part, uint32_t* out, hipStream_t s) {
+    const uint32_t nb = (uint32_t)((N + SCAN_TILE - 1) / SCAN_TILE);
+    const uint32_t nbl = nb ? nb : 1;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nbl), dim3(SCAN_THREADS), 0, s, in, N, part);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, part, nbl);
+    hipLaunchKernelGGL(k_scan_down, dim3(nbl), dim3(SCAN_THREADS), 0, s, in, N, part, out);
+    return hipGetLastError();
+}
+
+uint32_t grid_for(uint64_t items, uint32_t threads, uint32_t cap) {
+    uint64_t g = (items + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (uint32_t)g;
+}
+
+}  // namespace
+
+void rept_sizes_impl(uint32_t n, uint64_t E, size_t* persistent, size_t* scratch) {
+    *persistent = persistent_layout(n, E).total;
+    *scratch = scratch_layout(n, E).total;
+}
+
+rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void* persistent,
+                            size_t persistent_bytes, void* scratch, size_t scratch_bytes,
+                            hipStream_t s, rept_graph** out) {
+    const Layout L = persistent_layout(n, E);
+    const ScratchLayout S = scratch_layout(n, E);
+    if (persistent_bytes < L.total || scratch_bytes < S.total) return REPT_ENOMEM;
+    uint8_t* P = (uint8_t*)persistent;
+    uint8_t* X = (uint8_t*)scratch;
+    uint32_t* off = (uint32_t*)(P + L.off);
+    uint32_t* nbr = (uint32_t*)(P + L.nbr);
+    uint32_t* tim = (uint32_t*)(P + L.tim);
+    uint32_t* apex = (uint32_t*)(P + L.apex);
+    BuildStats* st = (BuildStats*)(X + S.stats);
+    uint32_t* deg = (uint32_t*)(X + S.deg);
+    uint32_t* dout = (uint32_t*)(X + S.dout);
+    uint32_t* cursor = (uint32_t*)(X + S.cursor);
+    uint32_t* ahist = (uint32_t*)(X + S.ahist);
+    uint32_t* aoff = (uint32_t*)(X + S.aoff);
+    uint32_t* part = (uint32_t*)(X + S.part);
+    unsigned long long* packed = (unsigned long long*)(X + S.packed);
+    unsigned long long* alt = (unsigned long long*)(X + S.alt);
+    uint32_t* medium = (uint32_t*)(X + S.medium);
+    uint32_t* large = (uint32_t*)(X + S.large);
+    const uint2* e2 = (const uint2*)edges;
+
+    const uint32_t cus = rept_num_cus();
+    const uint32_t cap = cus ? cus * 16 : 4096;
+    const uint32_t gE = grid_for(E, 256, cap), gN = grid_for(n, 256, cap);
+
+    // clear counters (fill kernels rather than memsets, so the sequence is capture-safe)
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)st,
+                       (uint64_t)(sizeof(BuildStats) / 4), 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, deg, (uint64_t)n, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, dout, (uint64_t)n, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, cursor, (uint64_t)n, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, ahist, (uint64_t)n, 0u);
+
+    hipLaunchKernelGGL(k_degree, dim3(gE), dim3(256), 0, s, e2, E, n, deg, st);
+    hipLaunchKernelGGL(k_orient_count, dim3(gE), dim3(256), 0, s, e2, E, n, deg, dout);
+    if (scan_u32(dout, n, part, off, s) != hipSuccess) return REPT_EDEVICE;
+    hipLaunchKernelGGL(k_scatter, dim3(gE), dim3(256), 0, s, e2, E, n, deg, dout, off, cursor, packed, st);
+    hipLaunchKernelGGL(k_classify, dim3(gN), dim3(256), 0, s, off, n, ahist, medium, large, st);
+    hipLaunchKernelGGL(k_sort_small, dim3(grid_for((uint64_t)n, 4, cap * 4)), dim3(256), 0, s, off, n, packed,
+                       nbr, tim, st);
+    hipLaunchKernelGGL(k_sort_medium, dim3(cus ? cus * 4 : 1024), dim3(512), 0, s, off, medium, packed, nbr,
+                       tim, st);
+    uint32_t id_bits = 1;
+    while (id_bits < 32 && ((uint64_t)1 << id_bits) < (uint64_t)n) ++id_bits;
+    hipLaunchKernelGGL(k_sort_large, dim3(cus ? cus : 256), dim3(64), 0, s, off, large, packed, alt, id_bits,
+                       nbr, tim, st);
+    if (scan_u32(ahist, n, part, aoff, s) != hipSuccess) return REPT_EDEVICE;
+    hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, cursor, (uint64_t)n, 0u);
+    hipLaunchKernelGGL(k_apex_scatter, dim3(gN), dim3(256), 0, s, off, n, aoff, cursor, apex);
+    if (hipGetLastError() != hipSuccess) return REPT_EDEVICE;
+
+    BuildStats hs;
+    if (hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s) != hipSuccess) return REPT_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return REPT_EDEVICE;
+    if (hs.flags & RF_RANGE) return REPT_ERANGE;
+    if (hs.flags & RF_SELFLOOP) return REPT_ESELFLOOP;
+    if (hs.flags & RF_DUP) return REPT_EDUP;
+
+    rept_graph* g = (rept_graph*)calloc(1, sizeof(rept_graph));
+    if (!g) return REPT_ENOMEM;
+    g->magic = REPT_MAGIC;
+    g->n = n;
+    g->E = E;
+    g->ctrl = P + L.ctrl;
+    g->off = off;
+    g->nbr = nbr;
+    g->tim = tim;
+    g->apex = apex;
+    g->num_apex = hs.num_apex;
+    g->max_out = hs.max_out;
+    g->work = hs.work;
+    g->sum_out_sq = hs.sum_out_sq;
+    *out = g;
+    return REPT_OK;
+}

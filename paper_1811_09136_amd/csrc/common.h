@@ -1,0 +1,111 @@
+// Internal declarations shared by the build, count and C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rept.h"
+
+#define REPT_GMAX 8           // hash groups handled by one launch (c <= 8*m)
+#define REPT_HIST_CAP 1024    // processors aggregated in LDS; larger c uses direct atomics
+#define REPT_CTRL_BYTES 4096  // control block at the head of a graph's persistent buffer
+#define REPT_MAGIC 0x52455054u
+
+// validation flags written by the build kernels
+#define RF_RANGE 1u
+#define RF_SELFLOOP 2u
+#define RF_DUP 4u
+
+// Build statistics, written by the build kernels into scratch and read once by the host.
+struct BuildStats {
+    uint32_t flags;
+    uint32_t num_apex;
+    uint32_t max_out;
+    uint32_t n_medium;  // segments sorted by a workgroup in LDS
+    uint32_t n_large;   // segments sorted by a workgroup in global memory
+    uint32_t pad[3];
+    unsigned long long work;        // sum over oriented edges a->b of outdeg(b)
+    unsigned long long sum_out_sq;  // sum over nodes of outdeg^2
+};
+
+// Host handle (opaque to callers).
+struct rept_graph {
+    uint32_t magic;
+    uint32_t n;
+    uint64_t E;
+    uint8_t* ctrl;       // device control block (REPT_CTRL_BYTES) for single-job launches
+    const uint32_t* off; // [n+1] oriented adjacency offsets
+    const uint32_t* nbr; // [E] higher-ranked neighbour ids, sorted within each segment
+    const uint32_t* tim; // [E] arrival time of that edge
+    const uint32_t* apex;// [num_apex] nodes with outdeg >= 2, by outdeg descending
+    uint32_t num_apex;
+    uint32_t max_out;
+    uint64_t work;
+    uint64_t sum_out_sq;
+};
+
+// Device-side job descriptor.
+struct JobDev {
+    const uint32_t* off;
+    const uint32_t* nbr;
+    const uint32_t* tim;
+    const uint32_t* apex;
+    int64_t* global;
+    int64_t* local;
+    uint64_t hp[4 * REPT_GMAX];  // polynomial hash coefficients (a0, a1, a2, a3) per group
+    uint32_t n, m, c, G;
+    uint32_t rows;       // local rows: G or c
+    uint32_t per_proc;   // 1: local rows are processors
+    uint32_t accumulate; // 1: do not zero the outputs first
+    uint32_t t0, t1;     // window [t0, t1)
+    uint32_t unit0, unit1;       // apex range [unit0, unit1)
+    uint32_t n_heavy;            // apexes of the range with outdeg > wave_cap (set by setup)
+    uint32_t light_tiles;        // set by setup
+    uint32_t heavy_prefix;       // exclusive prefix of heavy units over jobs (set by setup)
+    uint32_t light_prefix;       // exclusive prefix of light tiles over jobs (set by setup)
+    uint32_t pad[1];
+};
+
+// Batch header, followed in memory by JobDev[njobs].
+struct BatchHeader {
+    uint32_t njobs;
+    uint32_t wave_cap;
+    uint32_t block_cap;
+    uint32_t light_blocks;
+    uint32_t heavy_blocks;
+    uint32_t heavy_threads;
+    uint32_t light_tile;   // apexes per light queue tile
+    uint32_t hist_c;       // processors aggregated in LDS (0: direct atomics)
+    uint32_t G_max;        // max groups over jobs (LDS counter rows)
+    uint32_t light_lds;    // dynamic LDS bytes per light workgroup
+    uint32_t heavy_lds;    // dynamic LDS bytes per heavy workgroup
+    uint32_t heavy_total;  // set by setup
+    uint32_t light_total;  // set by setup
+    uint32_t q_heavy;      // queue counters, reset by setup
+    uint32_t q_light;
+    uint32_t any_zero;     // some job overwrites its outputs
+    uint64_t zero_words;   // max words to clear over jobs
+    uint32_t pad[14];
+};
+
+static_assert(sizeof(BatchHeader) % 16 == 0, "header alignment");
+static_assert(sizeof(JobDev) % 16 == 0, "job alignment");
+static_assert(sizeof(BatchHeader) + sizeof(JobDev) <= REPT_CTRL_BYTES, "control block size");
+
+// ---- build (build.hip) ----
+rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void* persistent,
+                            size_t persistent_bytes, void* scratch, size_t scratch_bytes,
+                            hipStream_t stream, rept_graph** out);
+void rept_sizes_impl(uint32_t n, uint64_t E, size_t* persistent, size_t* scratch);
+
+// ---- count (count.hip) ----
+// Launch setup + zero + heavy + light kernels for a batch already in device memory.
+hipError_t rept_launch_batch(void* ws, const BatchHeader& host_hdr, hipStream_t stream);
+hipError_t rept_launch_single(uint8_t* ctrl, const BatchHeader& hdr, const JobDev& job,
+                              hipStream_t stream);
+hipError_t rept_launch_slots(const uint64_t* hp, uint32_t G, uint32_t m, const uint32_t* edges,
+                             uint64_t E, uint32_t* slots, hipStream_t stream);
+// LDS bytes for the two counting kernels
+uint32_t rept_light_lds(uint32_t wave_cap, uint32_t G, uint32_t hist_c);
+uint32_t rept_heavy_lds(uint32_t block_cap, uint32_t G, uint32_t hist_c);
+uint32_t rept_num_cus();

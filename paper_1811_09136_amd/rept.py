@@ -1,0 +1,309 @@
+"""ctypes binding of ``librept.so`` (declared in ``include/rept.h``).
+
+Argument marshalling only: every step of the counting path runs in the HIP library.  PyTorch
+provides device memory (``torch.empty(..., device="cuda")``) and streams; nothing here
+computes counts.  If the library is missing, :func:`lib` raises -- there is no fallback.
+
+The functions named ``rept_*`` mirror the C calls one to one; :class:`Graph` and the helpers
+below them are conveniences built only from those calls.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librept.so")
+
+REPT_OK, REPT_EINVAL, REPT_ERANGE, REPT_ESELFLOOP, REPT_EDUP, REPT_ENOMEM, REPT_EDEVICE, REPT_ENOTSUP = \
+    0, -1, -2, -3, -4, -5, -6, -7
+REPT_LOCAL_PER_PROC = 1
+REPT_JOB_ACCUMULATE = 1
+UINT64_MAX = 2**64 - 1
+UINT32_MAX = 2**32 - 1
+
+
+class ReptError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {code} ({rept_status_str(code)})")
+
+
+class rept_params(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_uint32), ("c", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class rept_graph_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("num_edges", ctypes.c_uint64), ("num_apex", ctypes.c_uint32),
+                ("max_out_degree", ctypes.c_uint32), ("oriented_work", ctypes.c_uint64),
+                ("sum_out_sq", ctypes.c_uint64)]
+
+
+class rept_job(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_void_p), ("params", rept_params), ("global_", ctypes.c_void_p),
+                ("local", ctypes.c_void_p), ("t0", ctypes.c_uint64), ("t1", ctypes.c_uint64),
+                ("unit0", ctypes.c_uint32), ("unit1", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class rept_tuning(ctypes.Structure):
+    _fields_ = [("wave_cap", ctypes.c_uint32), ("block_cap", ctypes.c_uint32), ("light_blocks", ctypes.c_uint32),
+                ("heavy_blocks", ctypes.c_uint32), ("heavy_threads", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 3)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``librept.so``; raise if it has not been built (no CPU fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1811_09136_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        sz = ctypes.c_size_t
+        P = ctypes.POINTER
+        sig = {
+            "rept_local_rows": ([P(rept_params)], u32),
+            "rept_query_sizes": ([u32, u64, P(sz), P(sz)], i32),
+            "rept_build": ([u32, vp, u64, vp, sz, vp, sz, vp, P(vp)], i32),
+            "rept_graph_get_info": ([vp, P(rept_graph_info)], i32),
+            "rept_count": ([vp, P(rept_params), vp, vp, vp], i32),
+            "rept_count_range": ([vp, P(rept_params), u64, u64, vp, vp, vp], i32),
+            "rept_estimate": ([u32, P(rept_params), vp, vp, vp, vp], i32),
+            "rept_hash_slots": ([P(rept_params), vp, u64, vp, vp], i32),
+            "rept_batch_workspace_size": ([u32, P(sz)], i32),
+            "rept_batch_prepare": ([P(rept_job), u32, P(rept_tuning), vp, sz, vp], i32),
+            "rept_batch_launch": ([vp, vp], i32),
+            "rept_batch_count": ([P(rept_job), u32, P(rept_tuning), vp, sz, vp], i32),
+            "rept_destroy": ([vp], None),
+            "rept_status_str": ([i32], ctypes.c_char_p),
+            "rept_device_cus": ([], u32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["rept_local_rows", "rept_query_sizes", "rept_build", "rept_graph_get_info", "rept_count",
+            "rept_count_range", "rept_estimate", "rept_hash_slots", "rept_batch_workspace_size",
+            "rept_batch_prepare", "rept_batch_launch", "rept_batch_count", "rept_destroy", "rept_status_str",
+            "rept_device_cus"]
+
+
+def _check(code: int, where: str):
+    if code != REPT_OK:
+        raise ReptError(code, where)
+
+
+def _stream_ptr(stream) -> int | None:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream or None
+
+
+@dataclass(frozen=True)
+class Params:
+    """REPT sampling parameters: p = 1/m, c processors, hash seed (Table I)."""
+    m: int
+    c: int
+    seed: int
+    per_proc: bool = False
+
+    def c_struct(self) -> rept_params:
+        return rept_params(self.m, self.c, self.seed & UINT64_MAX, REPT_LOCAL_PER_PROC if self.per_proc else 0, 0)
+
+    @property
+    def groups(self) -> int:
+        return -(-self.c // self.m)
+
+    @property
+    def rows(self) -> int:
+        return self.c if self.per_proc else self.groups
+
+
+# ------------------------------------------------------------------ same-name wrappers -----
+
+def rept_status_str(code: int) -> str:
+    return lib().rept_status_str(int(code)).decode()
+
+
+def rept_local_rows(params: Params) -> int:
+    p = params.c_struct()
+    return int(lib().rept_local_rows(ctypes.byref(p)))
+
+
+def rept_query_sizes(n: int, num_edges: int) -> tuple[int, int]:
+    a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    _check(lib().rept_query_sizes(n, num_edges, ctypes.byref(a), ctypes.byref(b)), "rept_query_sizes")
+    return a.value, b.value
+
+
+def rept_build(n: int, edges_ptr: int, num_edges: int, persistent_ptr: int, persistent_bytes: int,
+               scratch_ptr: int, scratch_bytes: int, stream_ptr: int | None) -> int:
+    h = ctypes.c_void_p(0)
+    _check(lib().rept_build(n, edges_ptr, num_edges, persistent_ptr, persistent_bytes, scratch_ptr, scratch_bytes,
+                            stream_ptr, ctypes.byref(h)), "rept_build")
+    return h.value
+
+
+def rept_graph_get_info(handle: int) -> rept_graph_info:
+    info = rept_graph_info()
+    _check(lib().rept_graph_get_info(handle, ctypes.byref(info)), "rept_graph_get_info")
+    return info
+
+
+def rept_count(handle: int, params: Params, global_ptr: int, local_ptr: int, stream_ptr: int | None):
+    p = params.c_struct()
+    _check(lib().rept_count(handle, ctypes.byref(p), global_ptr, local_ptr, stream_ptr), "rept_count")
+
+
+def rept_count_range(handle: int, params: Params, t0: int, t1: int, global_ptr: int, local_ptr: int,
+                     stream_ptr: int | None):
+    p = params.c_struct()
+    _check(lib().rept_count_range(handle, ctypes.byref(p), t0, t1, global_ptr, local_ptr, stream_ptr),
+           "rept_count_range")
+
+
+def rept_estimate(n: int, params: Params, glob: np.ndarray, loc: np.ndarray | None):
+    """Host FP64 estimators; returns (tau_hat, tau_v_hat or None)."""
+    p = params.c_struct()
+    g = np.ascontiguousarray(glob, dtype=np.int64)
+    th = ctypes.c_double(0.0)
+    tv = None
+    lp = None
+    if loc is not None:
+        lo = np.ascontiguousarray(loc, dtype=np.int64)
+        tv = np.zeros(n, dtype=np.float64)
+        lp = lo.ctypes.data
+    _check(lib().rept_estimate(n, ctypes.byref(p), g.ctypes.data, lp, ctypes.addressof(th),
+                               None if tv is None else tv.ctypes.data), "rept_estimate")
+    return th.value, tv
+
+
+def rept_hash_slots(params: Params, edges_ptr: int, num_edges: int, slots_ptr: int, stream_ptr: int | None):
+    p = params.c_struct()
+    _check(lib().rept_hash_slots(ctypes.byref(p), edges_ptr, num_edges, slots_ptr, stream_ptr), "rept_hash_slots")
+
+
+def rept_batch_workspace_size(njobs: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().rept_batch_workspace_size(njobs, ctypes.byref(b)), "rept_batch_workspace_size")
+    return b.value
+
+
+def rept_batch_prepare(jobs, tuning: rept_tuning | None, ws_ptr: int, ws_bytes: int, stream_ptr: int | None):
+    arr = (rept_job * len(jobs))(*jobs)
+    _check(lib().rept_batch_prepare(arr, len(jobs), None if tuning is None else ctypes.byref(tuning), ws_ptr,
+                                    ws_bytes, stream_ptr), "rept_batch_prepare")
+
+
+def rept_batch_launch(ws_ptr: int, stream_ptr: int | None):
+    _check(lib().rept_batch_launch(ws_ptr, stream_ptr), "rept_batch_launch")
+
+
+def rept_batch_count(jobs, tuning: rept_tuning | None, ws_ptr: int, ws_bytes: int, stream_ptr: int | None):
+    arr = (rept_job * len(jobs))(*jobs)
+    _check(lib().rept_batch_count(arr, len(jobs), None if tuning is None else ctypes.byref(tuning), ws_ptr,
+                                  ws_bytes, stream_ptr), "rept_batch_count")
+
+
+def rept_destroy(handle: int):
+    lib().rept_destroy(handle)
+
+
+def rept_device_cus() -> int:
+    return int(lib().rept_device_cus())
+
+
+# ------------------------------------------------------------------ conveniences ----------
+
+def _alloc(nbytes: int, device):
+    import torch
+    # 256-byte alignment: the caching allocator returns 512-byte aligned blocks
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def to_device_edges(edges: np.ndarray, device="cuda"):
+    """Upload a host [E, 2] uint32 stream (stored as int32 bits; the library reads uint32)."""
+    import torch
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.uint32).reshape(-1, 2))
+    return torch.from_numpy(e.view(np.int32)).to(device)
+
+
+class Graph:
+    """A built graph on the device (owns its persistent buffer)."""
+
+    def __init__(self, edges_dev, n: int, stream=None):
+        import torch
+        self.device = edges_dev.device
+        self.n = int(n)
+        self.num_edges = int(edges_dev.shape[0])
+        pbytes, sbytes = rept_query_sizes(self.n, self.num_edges)
+        self.persistent_bytes = pbytes
+        self.scratch_bytes = sbytes
+        self.persistent = _alloc(pbytes, self.device)
+        scratch = _alloc(sbytes, self.device)
+        sp = _stream_ptr(stream)
+        self.handle = rept_build(self.n, edges_dev.data_ptr(), self.num_edges, self.persistent.data_ptr(), pbytes,
+                                 scratch.data_ptr(), sbytes, sp)
+        # scratch may be reused once rept_build returned (it synchronised its stream)
+        del scratch
+        self.info = rept_graph_get_info(self.handle)
+        self._torch = torch
+
+    def outputs(self, params: Params):
+        torch = self._torch
+        g = torch.empty(params.c, dtype=torch.int64, device=self.device)
+        l = torch.empty((params.rows, self.n), dtype=torch.int64, device=self.device)
+        return g, l
+
+    def count(self, params: Params, out=None, stream=None):
+        g, l = self.outputs(params) if out is None else out
+        rept_count(self.handle, params, g.data_ptr(), l.data_ptr(), _stream_ptr(stream))
+        return g, l
+
+    def count_range(self, params: Params, t0: int, t1: int, out, stream=None):
+        g, l = out
+        rept_count_range(self.handle, params, t0, t1, g.data_ptr(), l.data_ptr(), _stream_ptr(stream))
+        return g, l
+
+    def close(self):
+        if getattr(self, "handle", None):
+            rept_destroy(self.handle)
+            self.handle = None
+            self.persistent = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hash_slots(params: Params, edges_dev, stream=None):
+    import torch
+    E = int(edges_dev.shape[0])
+    out = torch.empty((params.groups, E), dtype=torch.int32, device=edges_dev.device)
+    rept_hash_slots(params, edges_dev.data_ptr(), E, out.data_ptr(), _stream_ptr(stream))
+    return out
+
+
+def make_job(graph: Graph, params: Params, out, t0: int = 0, t1: int = UINT64_MAX, unit0: int = 0,
+             unit1: int = UINT32_MAX, accumulate: bool = False) -> rept_job:
+    g, l = out
+    return rept_job(graph.handle, params.c_struct(), g.data_ptr(), l.data_ptr(), t0, t1, unit0, unit1,
+                    REPT_JOB_ACCUMULATE if accumulate else 0, 0)
+
+
+def tuning(wave_cap=0, block_cap=0, light_blocks=0, heavy_blocks=0, heavy_threads=0) -> rept_tuning:
+    return rept_tuning(wave_cap, block_cap, light_blocks, heavy_blocks, heavy_threads, (ctypes.c_uint32 * 3)())

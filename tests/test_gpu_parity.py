@@ -1,0 +1,177 @@
+"""Device path vs the CPU oracle, bit-exact on every integer counter.
+
+Inputs are seeded synthetic streams (module ``synth``).  Each case prints its name and shape
+before touching the GPU so that a failing run names its case.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _run(cuda, edges, n, m, c, seed, per_proc=False, tune=None, window=None):
+    import torch
+    from paper_1811_09136_amd import rept
+    p = rept.Params(m, c, seed, per_proc)
+    g = rept.Graph(rept.to_device_edges(edges, cuda), n)
+    if tune is None and window is None:
+        glob, loc = g.count(p)
+    else:
+        out = g.outputs(p)
+        out[0].zero_()
+        out[1].zero_()
+        t0, t1 = (0, len(edges)) if window is None else window
+        if tune is None:
+            glob, loc = g.count_range(p, t0, t1, out)
+        else:
+            job = rept.make_job(g, p, out, t0=t0, t1=t1, accumulate=True)
+            ws = torch.empty(rept.rept_batch_workspace_size(1), dtype=torch.uint8, device=cuda)
+            rept.rept_batch_count([job], tune, ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
+            glob, loc = out
+    torch.cuda.synchronize()
+    res = glob.cpu().numpy(), loc.cpu().numpy(), g.info
+    g.close()
+    return res
+
+
+def _check(edges, n, m, c, seed, got, per_proc=False, window=None):
+    kw = {}
+    if window is not None:
+        kw = dict(t0=window[0], t1=window[1])
+    og, ol = oracle.rept(edges, n, m, c, seed, per_proc=per_proc, **kw)
+    assert np.array_equal(got[0], og), (got[0], og)
+    assert np.array_equal(got[1], ol)
+    return og, ol
+
+
+def test_config1_parity(cuda):
+    e = synth.config1_stream()
+    _say("config1 ER n=2000 E=20000 m=10 c=10")
+    got = _run(cuda, e, 2000, 10, 10, 20181122)
+    og, ol = _check(e, 2000, 10, 10, 20181122, got)
+    assert og.sum() > 0
+    # invariant: each semi-triangle adds one to each of its three nodes
+    assert ol.sum() == 3 * og.sum()
+
+
+@pytest.mark.parametrize("m,c,per_proc", [(1, 1, False), (2, 2, False), (3, 7, False), (10, 40, False),
+                                          (4, 4, True), (5, 12, True), (2, 16, False)])
+def test_random_graphs(cuda, m, c, per_proc):
+    e = synth.er(300, 3000, 11 + m, 12 + c)
+    _say(f"ER n=300 E=3000 m={m} c={c} per_proc={per_proc}")
+    got = _run(cuda, e, 300, m, c, 1234 + m * c, per_proc=per_proc)
+    _check(e, 300, m, c, 1234 + m * c, got, per_proc=per_proc)
+
+
+@pytest.mark.parametrize("shape", ["complete", "wheel", "friendship", "bipartite", "cycle"])
+def test_closed_form_shapes(cuda, shape):
+    # m = 1: every triangle is counted once (its first two edges share the only slot)
+    mk = {"complete": lambda: (synth.complete(24), 24), "wheel": lambda: (synth.wheel(50), 51),
+          "friendship": lambda: (synth.friendship(30), 61), "bipartite": lambda: (synth.complete_bipartite(9, 13), 22),
+          "cycle": lambda: (synth.cycle(40), 40)}
+    e0, n = mk[shape]()
+    e = synth.shuffled(e0, 77, 78)
+    _say(f"shape={shape} n={n} E={len(e)} m=1 c=1")
+    got = _run(cuda, e, n, 1, 1, 5)
+    _check(e, n, 1, 1, 5, got)
+
+
+def test_windows_additive(cuda):
+    e = synth.er(500, 6000, 21, 22)
+    cuts = [0, 1, 1000, 2500, 2501, 6000]
+    _say("windows ER n=500 E=6000 m=3 c=6")
+    full = _run(cuda, e, 500, 3, 6, 9)
+    acc_g = np.zeros_like(full[0])
+    acc_l = np.zeros_like(full[1])
+    for t0, t1 in zip(cuts[:-1], cuts[1:]):
+        got = _run(cuda, e, 500, 3, 6, 9, window=(t0, t1))
+        _check(e, 500, 3, 6, 9, got, window=(t0, t1))
+        acc_g += got[0]
+        acc_l += got[1]
+    assert np.array_equal(acc_g, full[0]) and np.array_equal(acc_l, full[1])
+
+
+@pytest.mark.parametrize("tune", [dict(wave_cap=16, block_cap=64, heavy_threads=256),
+                                  dict(wave_cap=32, block_cap=128, heavy_threads=1024),
+                                  dict(wave_cap=512, block_cap=2048, heavy_threads=512, light_blocks=3, heavy_blocks=1)])
+def test_launch_shapes(cuda, tune):
+    from paper_1811_09136_amd import rept
+    e, n = synth.scaled_chung_lu(120_000, 31)
+    _say(f"Chung-Lu n={n} E={len(e)} m=3 c=5 tune={tune}")
+    got = _run(cuda, e, n, 3, 5, 17, tune=rept.tuning(**tune))
+    assert got[2].max_out_degree > 64  # the chunked workgroup path is exercised
+    _check(e, n, 3, 5, 17, got)
+
+
+def test_hash_slots(cuda):
+    import torch
+    from paper_1811_09136_amd import rept
+    e = synth.config1_stream()
+    for m, c in [(10, 40), (7, 7), (1, 3), (255, 1000)]:
+        _say(f"hash slots m={m} c={c}")
+        p = rept.Params(m, c, 99 + m)
+        s = rept.hash_slots(p, rept.to_device_edges(e, cuda))
+        torch.cuda.synchronize()
+        assert np.array_equal(s.cpu().numpy().view(np.uint32), oracle.slots(e, m, p.groups, p.seed))
+
+
+@pytest.mark.parametrize("case", ["selfloop", "dup_same", "dup_flipped", "range"])
+def test_invalid_streams(cuda, case):
+    from paper_1811_09136_amd import rept
+    e = synth.er(50, 200, 3, 4).copy()
+    if case == "selfloop":
+        e[100] = (7, 7)
+        code = rept.REPT_ESELFLOOP
+    elif case == "dup_same":
+        e[150] = e[20]
+        code = rept.REPT_EDUP
+    elif case == "dup_flipped":
+        e[150] = e[20][::-1]
+        code = rept.REPT_EDUP
+    else:
+        e[10] = (3, 50)
+        code = rept.REPT_ERANGE
+    assert oracle.validate(50, e) == code
+    _say(f"invalid stream {case}")
+    with pytest.raises(rept.ReptError) as ei:
+        rept.Graph(rept.to_device_edges(e, cuda), 50)
+    assert ei.value.code == code
+
+
+def test_degenerate_streams(cuda):
+    # empty stream, one edge, a path (no triangles), a single triangle in all 6 orders
+    cases = [(np.zeros((0, 2), np.uint32), 5), (np.array([[0, 1]], np.uint32), 2),
+             (np.array([[0, 1], [1, 2], [2, 3]], np.uint32), 4)]
+    import itertools
+    tri = [(0, 1), (1, 2), (0, 2)]
+    for perm in itertools.permutations(range(3)):
+        cases.append((np.array([tri[i] for i in perm], np.uint32), 3))
+    for e, n in cases:
+        for m, c in [(1, 1), (2, 2), (2, 4)]:
+            _say(f"degenerate E={len(e)} n={n} m={m} c={c}")
+            got = _run(cuda, e, n, m, c, 3)
+            _check(e, n, m, c, 3, got)
+
+
+def test_lds_budget_rejected(cuda):
+    # a staging chunk whose LDS footprint exceeds the 160 KB of a CU is refused, not launched
+    import torch
+    from paper_1811_09136_amd import rept
+    e = synth.er(100, 500, 1, 2)
+    g = rept.Graph(rept.to_device_edges(e, cuda), 100)
+    p = rept.Params(3, 6, 1)
+    out = g.outputs(p)
+    job = rept.make_job(g, p, out)
+    ws = torch.empty(rept.rept_batch_workspace_size(1), dtype=torch.uint8, device=cuda)
+    _say("LDS budget rejection")
+    with pytest.raises(rept.ReptError) as ei:
+        rept.rept_batch_count([job], rept.tuning(block_cap=4096), ws.data_ptr(), ws.numel(), None)
+    assert ei.value.code == rept.REPT_EINVAL
+    g.close()
