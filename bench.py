@@ -1,0 +1,230 @@
+"""Benchmark of the REPT counting path on one MI355X.
+
+One step = the whole hot path over one synthetic stream already resident in HBM:
+validate + orient + build (rept_build), the counting pass for all c processors (rept_count),
+the device-to-host copy of the integer counters and the FP64 estimators (rept_estimate).
+
+Default workload: Chung-Lu power-law stream, 1,000,000 nodes, 20,000,000 edges, exponent 2.1,
+random order, m = 10 (p = 0.1), c = 40 (four hash groups).  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+WORKLOADS = {
+    # name: (description, generator, n, m, c)
+    "config2": ("Chung-Lu 1M nodes / 20M edges, gamma 2.1, shuffled; m=10 c=40", "config2", 1_000_000, 10, 40),
+    "config1": ("Erdos-Renyi 2k nodes / 20k edges, shuffled; m=10 c=10", "config1", 2000, 10, 10),
+    "config3": ("R-MAT scale 24 edge factor 16 (0.57,0.19,0.19), dedup, generation order; m=100 c=100",
+                "config3", 1 << 24, 100, 100),
+}
+HASH_SEED = 20181122
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one device copy of 1 GiB (reference for FETCH_SIZE/WRITE_SIZE scaling)")
+    return ap.parse_args()
+
+
+def stream_for(name):
+    import synth
+    gen = WORKLOADS[name][1]
+    return {"config1": synth.config1_stream, "config2": synth.config2_stream, "config3": synth.config3_stream}[gen]()
+
+
+def count_kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("count.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_1811_09136_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload: str):
+    """HBM bytes per count launch from the committed PMC summary, if it was taken on the
+    current counting kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_count_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_digest") != count_kernel_source_digest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def algorithmic_bytes(info, tau: int, c: int, rows: int, n: int) -> float:
+    """Bytes the counting pass must move per launch (per-unit model of the recast):
+    16 B per oriented edge staged at its apex (neighbour id, arrival time, the neighbour's two
+    offsets), 12 B per apex (id and its two offsets), 4 B per list entry probed (neighbour id),
+    4 B per triangle found (arrival time of its third edge), 8 B per output counter."""
+    E = info.num_edges
+    return 16.0 * E + 12.0 * info.num_apex + 4.0 * info.oriented_work + 4.0 * tau + 8.0 * (c + rows * n)
+
+
+def streaming_model_bytes(deg_sq_half_sum: int, E: int, groups: int, semi: int, c: int, n: int) -> float:
+    """Bytes of the per-processor streaming formulation (each time-filtered per-processor set
+    read at every edge): 8 E + 8 W G + 24 sum tau^(i) + 8 (c + G n), W = sum_x C(d_x, 2)."""
+    return 8.0 * E + 8.0 * deg_sq_half_sum * groups + 24.0 * semi + 8.0 * (c + groups * n)
+
+
+def cpu_baseline(edges, n, m, c):
+    """The oracle (Algorithm 1 replay) timed on one host core for ONE processor of the job
+    (group 0, slot 0) over the full stream; every processor replays the whole stream with its
+    own sample of about E/m edges, so the job's single-core time is c times this."""
+    import oracle
+    t0 = time.perf_counter()
+    g, _ = oracle.rept(edges, n, m, 1, HASH_SEED)
+    dt = time.perf_counter() - t0
+    job_s = dt * c
+    return {"value": len(edges) / job_s, "unit": "stream edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"Algorithm 1 replay of 1 of {c} processors (group 0, slot 0) over all {len(edges)} "
+                      f"stream edges took {dt:.2f} s on one core; whole job = {c} x that"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
+                                   "run with --gpus 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1811_09136_amd import rept
+
+    desc, _, n, m, c = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    edges = stream_for(args.workload)
+    E = len(edges)
+    params = rept.Params(m, c, HASH_SEED)
+    rows = params.rows
+    d_edges = rept.to_device_edges(edges, dev)
+    pbytes, sbytes = rept.rept_query_sizes(n, E)
+    persistent = torch.empty(pbytes, dtype=torch.uint8, device=dev)
+    scratch = torch.empty(sbytes, dtype=torch.uint8, device=dev)
+    glob = torch.empty(c, dtype=torch.int64, device=dev)
+    loc = torch.empty((rows, n), dtype=torch.int64, device=dev)
+    h_glob = torch.empty(c, dtype=torch.int64, pin_memory=True)
+    h_loc = torch.empty((rows, n), dtype=torch.int64, pin_memory=True)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    torch.cuda.synchronize()
+
+    count_ms = []
+    build_ms = []
+
+    def step(record):
+        t0 = time.perf_counter()
+        h = rept.rept_build(n, d_edges.data_ptr(), E, persistent.data_ptr(), pbytes, scratch.data_ptr(), sbytes, sp)
+        t1 = time.perf_counter()  # rept_build synchronises its stream once (validation result)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        rept.rept_count(h, params, glob.data_ptr(), loc.data_ptr(), sp)
+        ev1.record(stream)
+        h_glob.copy_(glob, non_blocking=True)
+        h_loc.copy_(loc, non_blocking=True)
+        stream.synchronize()
+        tau_hat, tau_v = rept.rept_estimate(n, params, h_glob.numpy(), h_loc.numpy())
+        info = rept.rept_graph_get_info(h)
+        rept.rept_destroy(h)
+        if record:
+            count_ms.append(ev0.elapsed_time(ev1))
+            build_ms.append(1e3 * (t1 - t0))
+        return tau_hat, info
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tau_hat, info = step(True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1e3 * dt / args.steps
+    value = E * args.steps / dt
+
+    # exact triangle count (m = 1, untimed) for the per-launch byte model
+    h = rept.rept_build(n, d_edges.data_ptr(), E, persistent.data_ptr(), pbytes, scratch.data_ptr(), sbytes, sp)
+    p1 = rept.Params(1, 1, 0)
+    g1 = torch.empty(1, dtype=torch.int64, device=dev)
+    l1 = torch.empty((1, n), dtype=torch.int64, device=dev)
+    rept.rept_count(h, p1, g1.data_ptr(), l1.data_ptr(), sp)
+    torch.cuda.synchronize()
+    tau = int(g1.item())
+    rept.rept_destroy(h)
+
+    if args.copy_calibration:  # a plain device copy of 1 GiB, for counter scaling
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    avg_count_ms = float(np.mean(count_ms))
+    alg = algorithmic_bytes(info, tau, c, rows, n)
+    achieved = alg / (avg_count_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(args.workload)
+    deg = np.bincount(edges.ravel(), minlength=n).astype(np.int64)
+    W = int((deg * (deg - 1) // 2).sum())
+    semi = int(h_glob.numpy().sum())
+    sm_bytes = streaming_model_bytes(W, E, params.groups, semi, c, n)
+
+    out = {
+        "metric": "stream edges/sec on 1 GPU, % HBM roofline; batched/served vs plain",
+        "value": value,
+        "unit": "stream edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": n, "edges": E, "m": m, "c": c, "hash_seed": HASH_SEED},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": traffic},
+        "kernel": {"count_ms": avg_count_ms, "build_ms": float(np.mean(build_ms)),
+                   "count_edges_per_s": E / (avg_count_ms * 1e-3), "algorithmic_bytes": alg,
+                   "oriented_work": int(info.oriented_work), "triangles": tau, "semi_triangles": semi,
+                   "streaming_model_bytes": sm_bytes,
+                   "streaming_model_equiv_gbps": sm_bytes / (avg_count_ms * 1e-3) / 1e9,
+                   "source_digest": count_kernel_source_digest()},
+        "tau_hat": tau_hat,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(edges, n, m, c)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
