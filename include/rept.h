@@ -181,14 +181,19 @@ typedef struct rept_job {
     uint32_t reserved;
 } rept_job;
 
-/* Launch shape of the counting kernels; zero fields take the library defaults. */
+/* Launch shape of the counting kernel; zero fields take the library defaults.  The kernel is
+ * persistent: `blocks` workgroups of `threads` threads drain the work queue, first one apex per
+ * workgroup (apexes whose out-degree exceeds wave_cap), then one apex per wavefront.  The LDS
+ * footprint of a shape must fit the 160 KB of a compute unit (EINVAL otherwise). */
 typedef struct rept_tuning {
-    uint32_t wave_cap;       /* apexes with out-degree <= wave_cap run one per wavefront (16..512) */
-    uint32_t block_cap;      /* adjacency chunk staged in LDS by the per-workgroup path (64..4096) */
-    uint32_t light_blocks;   /* workgroups of the wavefront-per-apex kernel (0: 8 per CU) */
-    uint32_t heavy_blocks;   /* workgroups of the workgroup-per-apex kernel (0: 2 per CU) */
-    uint32_t heavy_threads;  /* threads per workgroup of that kernel: 256, 512 or 1024 */
-    uint32_t reserved[3];
+    uint32_t wave_cap;   /* 8..256: largest apex list counted by one wavefront (default 64) */
+    uint32_t block_cap;  /* 64..4096: apex entries hashed in LDS per chunk by a workgroup (default:
+                            smallest power of two >= the graphs' largest out-degree, at most 1024) */
+    uint32_t b_chunk;    /* 16..1024: neighbour lists staged per chunk by a workgroup (default 128) */
+    uint32_t blocks;     /* persistent workgroups (default: as many as fit, up to 4 per CU) */
+    uint32_t threads;    /* 64..1024, a multiple of 64 (default 256) */
+    uint32_t light_tile; /* 1..256: apexes taken per queue pop by a wavefront (default 8) */
+    uint32_t reserved[2];
 } rept_tuning;
 
 /* Device workspace bytes for a batch of njobs jobs. */

@@ -52,33 +52,44 @@ std::unordered_map<void*, Shape> g_shapes;  // prepared batch workspaces -> laun
 
 bool valid_graph(const rept_graph* g) { return g && g->magic == REPT_MAGIC; }
 
-// Fill the launch shape for jobs of at most G_max groups and at most c_max processors.
-rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint64_t zero_words, bool any_zero,
-                        const rept_tuning* tu, BatchHeader* h) {
+// Fill the launch shape for jobs of at most G_max groups, at most c_max processors and at most
+// max_out entries in an apex list.
+rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t max_out, uint64_t zero_words,
+                        bool any_zero, const rept_tuning* tu, BatchHeader* h) {
     memset(h, 0, sizeof(*h));
     const uint32_t cus = rept_num_cus() ? rept_num_cus() : 256;
-    uint32_t wave_cap = (tu && tu->wave_cap) ? tu->wave_cap : 128;
-    uint32_t block_cap = (tu && tu->block_cap) ? tu->block_cap : 1024;
-    uint32_t heavy_threads = (tu && tu->heavy_threads) ? tu->heavy_threads : 512;
-    if (wave_cap < 16 || wave_cap > 512) return REPT_EINVAL;
+    uint32_t fit = 64;
+    while (fit < max_out && fit < 1024) fit <<= 1;
+    const uint32_t wave_cap = (tu && tu->wave_cap) ? tu->wave_cap : 64;
+    const uint32_t block_cap = (tu && tu->block_cap) ? tu->block_cap : fit;
+    const uint32_t b_chunk = (tu && tu->b_chunk) ? tu->b_chunk : 128;
+    const uint32_t threads = (tu && tu->threads) ? tu->threads : 256;
+    const uint32_t light_tile = (tu && tu->light_tile) ? tu->light_tile : 8;
+    if (wave_cap < 8 || wave_cap > 256) return REPT_EINVAL;
     if (block_cap < 64 || block_cap > 4096) return REPT_EINVAL;
-    if (heavy_threads != 256 && heavy_threads != 512 && heavy_threads != 1024) return REPT_EINVAL;
+    if (b_chunk < 16 || b_chunk > 1024) return REPT_EINVAL;
+    if (threads < 64 || threads > 1024 || threads % 64) return REPT_EINVAL;
+    if (light_tile < 1 || light_tile > 256) return REPT_EINVAL;
     const uint32_t hist_c = c_max <= REPT_HIST_CAP ? c_max : 0;
-    const uint32_t lds_cap = 160 * 1024;
-    uint32_t light_lds = rept_light_lds(wave_cap, G_max, hist_c);
-    uint32_t heavy_lds = rept_heavy_lds(block_cap, G_max, hist_c);
-    if (light_lds > lds_cap || heavy_lds > lds_cap) return REPT_EINVAL;
+    const uint32_t lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c);
+    if (lds > 160 * 1024 - 256) return REPT_EINVAL;  // static LDS takes a few bytes more
+    uint32_t blocks = tu ? tu->blocks : 0;
+    if (!blocks) {
+        uint32_t per_cu = rept_count_blocks_per_cu(threads, lds);
+        if (per_cu == 0) per_cu = 1;
+        if (per_cu > 4) per_cu = 4;
+        blocks = per_cu * cus;
+    }
     h->njobs = njobs;
     h->wave_cap = wave_cap;
     h->block_cap = block_cap;
-    h->light_blocks = (tu && tu->light_blocks) ? tu->light_blocks : 8 * cus;
-    h->heavy_blocks = (tu && tu->heavy_blocks) ? tu->heavy_blocks : 2 * cus;
-    h->heavy_threads = heavy_threads;
-    h->light_tile = 8;
+    h->b_chunk = b_chunk;
+    h->blocks = blocks;
+    h->threads = threads;
+    h->light_tile = light_tile;
     h->hist_c = hist_c;
     h->G_max = G_max;
-    h->light_lds = light_lds;
-    h->heavy_lds = heavy_lds;
+    h->lds_bytes = lds;
     h->any_zero = any_zero ? 1u : 0u;
     h->zero_words = zero_words;
     return REPT_OK;
@@ -137,7 +148,7 @@ rept_status count_one(const rept_graph* graph, const rept_params* params, uint64
     rept_status st = make_job(jb, &d, &zw);
     if (st != REPT_OK) return st;
     BatchHeader h;
-    st = make_header(1, d.G, d.c, zw, !accumulate, nullptr, &h);
+    st = make_header(1, d.G, d.c, graph->max_out, zw, !accumulate, nullptr, &h);
     if (st != REPT_OK) return st;
     if (rept_launch_single(graph->ctrl, h, d, (hipStream_t)stream) != hipSuccess) return REPT_EDEVICE;
     return REPT_OK;
@@ -270,7 +281,7 @@ rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_
     uint8_t* host = (uint8_t*)calloc(1, bytes);
     if (!host) return REPT_ENOMEM;
     JobDev* hj = (JobDev*)(host + sizeof(BatchHeader));
-    uint32_t G_max = 1, c_max = 1;
+    uint32_t G_max = 1, c_max = 1, max_out = 0;
     uint64_t zero_words = 0;
     bool any_zero = false;
     for (uint32_t j = 0; j < njobs; ++j) {
@@ -282,13 +293,14 @@ rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_
         }
         G_max = hj[j].G > G_max ? hj[j].G : G_max;
         c_max = hj[j].c > c_max ? hj[j].c : c_max;
+        max_out = jobs[j].graph->max_out > max_out ? jobs[j].graph->max_out : max_out;
         if (!hj[j].accumulate) {
             any_zero = true;
             zero_words = zw > zero_words ? zw : zero_words;
         }
     }
     BatchHeader h;
-    rept_status st = make_header(njobs, G_max, c_max, zero_words, any_zero, tuning, &h);
+    rept_status st = make_header(njobs, G_max, c_max, max_out, zero_words, any_zero, tuning, &h);
     if (st != REPT_OK) {
         free(host);
         return st;

@@ -69,21 +69,21 @@ struct JobDev {
 // Batch header, followed in memory by JobDev[njobs].
 struct BatchHeader {
     uint32_t njobs;
-    uint32_t wave_cap;
-    uint32_t block_cap;
-    uint32_t light_blocks;
-    uint32_t heavy_blocks;
-    uint32_t heavy_threads;
+    uint32_t wave_cap;     // apexes with out-degree <= wave_cap are counted by one wavefront
+    uint32_t block_cap;    // adjacency entries staged per hash-table chunk by a workgroup
+    uint32_t b_chunk;      // neighbour lists staged per chunk by a workgroup
+    uint32_t blocks;       // persistent grid size
+    uint32_t threads;      // workgroup size (multiple of 64, <= 1024)
     uint32_t light_tile;   // apexes per light queue tile
     uint32_t hist_c;       // processors aggregated in LDS (0: direct atomics)
     uint32_t G_max;        // max groups over jobs (LDS counter rows)
-    uint32_t light_lds;    // dynamic LDS bytes per light workgroup
-    uint32_t heavy_lds;    // dynamic LDS bytes per heavy workgroup
+    uint32_t lds_bytes;    // dynamic LDS bytes per workgroup
     uint32_t heavy_total;  // set by setup
     uint32_t light_total;  // set by setup
     uint32_t q_heavy;      // queue counters, reset by setup
     uint32_t q_light;
     uint32_t any_zero;     // some job overwrites its outputs
+    uint32_t pad0;
     uint64_t zero_words;   // max words to clear over jobs
     uint32_t pad[14];
 };
@@ -105,7 +105,9 @@ hipError_t rept_launch_single(uint8_t* ctrl, const BatchHeader& hdr, const JobDe
                               hipStream_t stream);
 hipError_t rept_launch_slots(const uint64_t* hp, uint32_t G, uint32_t m, const uint32_t* edges,
                              uint64_t E, uint32_t* slots, hipStream_t stream);
-// LDS bytes for the two counting kernels
-uint32_t rept_light_lds(uint32_t wave_cap, uint32_t G, uint32_t hist_c);
-uint32_t rept_heavy_lds(uint32_t block_cap, uint32_t G, uint32_t hist_c);
+// LDS bytes of the counting kernel for a launch shape
+uint32_t rept_count_lds(uint32_t threads, uint32_t wave_cap, uint32_t block_cap, uint32_t b_chunk, uint32_t G,
+                        uint32_t hist_c);
+// resident workgroups per CU of the counting kernel for a launch shape (0 if unknown)
+uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes);
 uint32_t rept_num_cus();

@@ -16,12 +16,17 @@
 // One pass therefore serves all c processors, and a window [t0, t1) of stream updates is the
 // set of triangles whose last edge arrived in the window.
 //
-// Kernels.  k_heavy: one workgroup per apex with a long list (adjacency chunks staged in LDS);
-// k_light: one wavefront per apex with a short list.  Both are persistent and drain a device
-// work queue over all jobs of a batch.  Local counts are aggregated per list entry in LDS and
-// global counts per processor in an LDS histogram before the 64-bit global atomics.
+// Kernel.  k_count is persistent and drains a device work queue over all jobs of a batch, in
+// two phases: apexes with long lists one per workgroup (the list is hashed into LDS chunk by
+// chunk), then apexes with short lists one per wavefront.  A team (workgroup or wavefront)
+// stages a's list in an LDS hash table (W side) and the lists of a's out-neighbours b that
+// are not empty (B side), then walks the concatenated b lists in windows of 64 entries: each
+// entry is one global load and one LDS probe.  Hits (triangles) go to a per-wavefront LDS
+// queue and are attributed in full-wave batches.  Local counts are aggregated per staged
+// entry and global counts per processor in LDS before the 64-bit global atomics.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdio.h>
 
 #include "common.h"
 
@@ -29,6 +34,7 @@ namespace {
 
 constexpr uint32_t kHashMul = 0x9E3779B1u;  // table index: Fibonacci hashing of the node id
 constexpr uint64_t kP61 = (1ull << 61) - 1;  // Mersenne prime of the edge hash
+constexpr uint32_t kQueue = 128;             // per-wavefront hit queue capacity
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -36,13 +42,37 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+template <bool BLOCK>
+__device__ __forceinline__ void team_sync() {
+    if (BLOCK) __syncthreads();
+    else wave_sync();
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = threadIdx.x & 63;
+    const uint32_t lane = lane_id();
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
         uint32_t o = __shfl_up(v, d, 64);
-        if (lane >= d) v += o;
+        if (lane >= (uint32_t)d) v += o;
     }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= (uint32_t)d) v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     return v;
 }
 
@@ -58,57 +88,120 @@ __host__ __device__ inline uint32_t log2u(uint32_t p) {
 }
 __host__ __device__ inline uint32_t up16(uint32_t x) { return (x + 15u) & ~15u; }
 
-// ---- LDS layouts (shared by host sizing and device carving) ----
-struct LightLayout {
-    uint32_t coef, hkey, hidx, ew, et, boff, bscan, slot, cnt, acnt, hist, team;
+// ---- LDS layout (shared by host sizing and device carving) --------------------------------
+// [per-wave misc] x nwaves, then one union region: the workgroup's heavy team area or the
+// wavefronts' light team areas (the heavy phase finishes before the light phase starts).
+struct Area {  // one team's staging area: W side (hash table of a's list) + B side (b lists)
+    uint32_t hkey, hidx, ew, et, wslot, cntw;
+    uint32_t eb, etb, bslot, cntb, boff, bscan;
+    uint32_t red;  // 64 words of team scratch (scans, reductions, broadcast)
+    uint32_t bytes;
 };
-__host__ __device__ inline LightLayout light_layout(uint32_t D, uint32_t G, uint32_t HC) {
-    LightLayout L;
-    const uint32_t H = pow2_at_least(2 * D);
+__host__ __device__ inline Area area_layout(uint32_t DW, uint32_t DB, uint32_t G) {
+    Area A;
+    const uint32_t H = pow2_at_least(2 * DW);
     uint32_t p = 0;
-    L.coef = p; p = up16(p + 8 * 4 * REPT_GMAX);
-    L.hkey = p; p = up16(p + 4 * H);
-    L.hidx = p; p = up16(p + 2 * H);
-    L.ew = p; p = up16(p + 4 * D);
-    L.et = p; p = up16(p + 4 * D);
-    L.boff = p; p = up16(p + 4 * D);
-    L.bscan = p; p = up16(p + 4 * (D + 1));
-    L.slot = p; p = up16(p + 2 * G * D);
-    L.cnt = p; p = up16(p + 4 * G * D);
-    L.acnt = p; p = up16(p + 4 * REPT_GMAX);
-    L.hist = p; p = up16(p + 4 * HC);
-    L.team = p;
+    A.hkey = p; p = up16(p + 4 * H);
+    A.hidx = p; p = up16(p + 2 * H);
+    A.ew = p; p = up16(p + 4 * DW);
+    A.et = p; p = up16(p + 4 * DW);
+    A.wslot = p; p = up16(p + 2 * G * DW);
+    A.cntw = p; p = up16(p + 4 * G * DW);
+    A.eb = p; p = up16(p + 4 * DB);
+    A.etb = p; p = up16(p + 4 * DB);
+    A.bslot = p; p = up16(p + 2 * G * DB);
+    A.cntb = p; p = up16(p + 4 * G * DB);
+    A.boff = p; p = up16(p + 4 * DB);
+    A.bscan = p; p = up16(p + 4 * (DB + 1));
+    A.red = p; p = up16(p + 4 * 64);
+    A.bytes = p;
+    return A;
+}
+struct Misc {  // per wavefront
+    uint32_t coef, mark, qv, qp, hist, bytes;
+};
+__host__ __device__ inline Misc misc_layout(uint32_t HC) {
+    Misc M;
+    uint32_t p = 0;
+    M.coef = p; p = up16(p + 8 * 4 * REPT_GMAX);
+    M.mark = p; p = up16(p + 4 * 64);
+    M.qv = p; p = up16(p + 4 * kQueue);
+    M.qp = p; p = up16(p + 4 * kQueue);
+    M.hist = p; p = up16(p + 4 * HC);
+    M.bytes = p;
+    return M;
+}
+struct Layout {
+    Misc misc;
+    Area heavy, light;
+    uint32_t union_off, total;
+};
+__host__ __device__ inline Layout count_layout(uint32_t nwaves, uint32_t DL, uint32_t DW, uint32_t DB,
+                                               uint32_t G, uint32_t HC) {
+    Layout L;
+    L.misc = misc_layout(HC);
+    L.heavy = area_layout(DW, DB, G);
+    L.light = area_layout(DL, DL, G);
+    L.union_off = nwaves * L.misc.bytes;
+    const uint32_t u = L.heavy.bytes > nwaves * L.light.bytes ? L.heavy.bytes : nwaves * L.light.bytes;
+    L.total = L.union_off + u;
     return L;
 }
 
-struct HeavyLayout {
-    uint32_t coef, hkey, hidx, ew, et, wslot, cntw, eb, etb, boff, bscan, bslot, cntb, acnt, hist, misc, total;
+// ---- views ---------------------------------------------------------------------------------
+struct TeamView {
+    uint32_t* hkey;
+    uint16_t* hidx;
+    uint32_t* ew;
+    uint32_t* et;
+    uint16_t* wslot;
+    uint32_t* cntw;
+    uint32_t* eb;
+    uint32_t* etb;
+    uint16_t* bslot;
+    uint32_t* cntb;
+    uint32_t* boff;
+    uint32_t* bscan;
+    uint32_t* red;
+    uint32_t DW, DB;
 };
-__host__ __device__ inline HeavyLayout heavy_layout(uint32_t D, uint32_t G, uint32_t HC) {
-    HeavyLayout L;
-    const uint32_t H = pow2_at_least(2 * D);
-    uint32_t p = 0;
-    L.coef = p; p = up16(p + 8 * 4 * REPT_GMAX);
-    L.hkey = p; p = up16(p + 4 * H);
-    L.hidx = p; p = up16(p + 2 * H);
-    L.ew = p; p = up16(p + 4 * D);
-    L.et = p; p = up16(p + 4 * D);
-    L.wslot = p; p = up16(p + 2 * G * D);
-    L.cntw = p; p = up16(p + 4 * G * D);
-    L.eb = p; p = up16(p + 4 * D);
-    L.etb = p; p = up16(p + 4 * D);
-    L.boff = p; p = up16(p + 4 * D);
-    L.bscan = p; p = up16(p + 4 * (D + 1));
-    L.bslot = p; p = up16(p + 2 * G * D);
-    L.cntb = p; p = up16(p + 4 * G * D);
-    L.acnt = p; p = up16(p + 4 * REPT_GMAX);
-    L.hist = p; p = up16(p + 4 * HC);
-    L.misc = p; p = up16(p + 4 * 64);
-    L.total = p;
-    return L;
+__device__ inline TeamView team_view(uint8_t* base, const Area& A, uint32_t DW, uint32_t DB) {
+    TeamView T;
+    T.hkey = (uint32_t*)(base + A.hkey);
+    T.hidx = (uint16_t*)(base + A.hidx);
+    T.ew = (uint32_t*)(base + A.ew);
+    T.et = (uint32_t*)(base + A.et);
+    T.wslot = (uint16_t*)(base + A.wslot);
+    T.cntw = (uint32_t*)(base + A.cntw);
+    T.eb = (uint32_t*)(base + A.eb);
+    T.etb = (uint32_t*)(base + A.etb);
+    T.bslot = (uint16_t*)(base + A.bslot);
+    T.cntb = (uint32_t*)(base + A.cntb);
+    T.boff = (uint32_t*)(base + A.boff);
+    T.bscan = (uint32_t*)(base + A.bscan);
+    T.red = (uint32_t*)(base + A.red);
+    T.DW = DW;
+    T.DB = DB;
+    return T;
+}
+struct WaveView {
+    uint64_t* coef;
+    uint32_t* mark;
+    uint32_t* qv;
+    uint32_t* qp;
+    uint32_t* hist;
+};
+__device__ inline WaveView wave_view(uint8_t* base, const Misc& M) {
+    WaveView V;
+    V.coef = (uint64_t*)(base + M.coef);
+    V.mark = (uint32_t*)(base + M.mark);
+    V.qv = (uint32_t*)(base + M.qv);
+    V.qp = (uint32_t*)(base + M.qp);
+    V.hist = (uint32_t*)(base + M.hist);
+    return V;
 }
 
-// ---- per-job constants held while a team works on that job ----
+// ---- per-job constants held while a wavefront works on that job ----------------------------
 struct JobRegs {
     const uint32_t* off;
     const uint32_t* nbr;
@@ -116,10 +209,10 @@ struct JobRegs {
     const uint32_t* apex;
     int64_t* global;
     int64_t* local;
-    uint32_t n, m, c, G, per_proc, t0, t1, last_ck;
+    uint32_t n, m, c, G, per_proc, t0, t1, last_ck, use_hist;
 };
 
-__device__ inline void load_job(const JobDev* __restrict__ j, JobRegs& r) {
+__device__ inline void load_job(const JobDev* __restrict__ j, uint32_t HC, JobRegs& r) {
     r.off = j->off;
     r.nbr = j->nbr;
     r.tim = j->tim;
@@ -134,9 +227,10 @@ __device__ inline void load_job(const JobDev* __restrict__ j, JobRegs& r) {
     r.t0 = j->t0;
     r.t1 = j->t1;
     r.last_ck = j->c - (j->G - 1) * j->m;
+    r.use_hist = (HC != 0 && j->c <= HC) ? 1u : 0u;
 }
 
-// ---- edge hash: degree-3 polynomial over GF(2^61 - 1), Horner form ----
+// ---- edge hash: degree-3 polynomial over GF(2^61 - 1), Horner form ---------------------------
 __device__ __forceinline__ uint64_t fold61(uint64_t r) {  // r < 2^62 -> [0, p)
     r = (r & kP61) + (r >> 61);
     return r >= kP61 ? r - kP61 : r;
@@ -157,37 +251,11 @@ __device__ __forceinline__ uint32_t slot_of(const uint64_t* c4, uint32_t m, uint
     return (uint32_t)__umul64hi(h << 3, (uint64_t)m);
 }
 
-// Attribute the triangle (a, b, w) with edge times t_ab, t_aw, t_bw.  The first two edges by
-// time are looked up (apex edges: staged slots s_ab(g), s_aw(g)) or hashed ({b, w}); for
-// every group whose slots agree on an active processor, sink(g, processor) is called.
-template <typename SAB, typename SAW, typename Sink>
-__device__ __forceinline__ void attribute(const JobRegs& J, const uint64_t* coef, uint32_t b, uint32_t w,
-                                          uint32_t tab, uint32_t taw, uint32_t tbw, SAB&& s_ab, SAW&& s_aw,
-                                          Sink&& sink) {
-    // which edge arrived last: 0 = {a,b}, 1 = {a,w}, 2 = {b,w} (arrival times are distinct)
-    const uint32_t last = (tab > taw && tab > tbw) ? 0u : (taw > tbw ? 1u : 2u);
-    const uint32_t tl = last == 0 ? tab : (last == 1 ? taw : tbw);
-    if (tl < J.t0 || tl >= J.t1) return;
-    for (uint32_t g = 0; g < J.G; ++g) {
-        {
-            uint32_t s1, s2;
-            if (last == 2) {
-                s1 = s_ab(g);
-                s2 = s_aw(g);
-            } else {
-                s1 = last == 0 ? s_aw(g) : s_ab(g);
-                s2 = slot_of(coef + 4 * g, J.m, b, w);
-            }
-            const uint32_t ck = (g + 1 < J.G) ? J.m : J.last_ck;
-            if (s1 == s2 && s1 < ck) sink(g, g * J.m + s1);
-        }
-    }
-}
-
 __device__ __forceinline__ void add64(int64_t* p, uint64_t v) {
     atomicAdd((unsigned long long*)p, (unsigned long long)v);
 }
 
+// ---- LDS hash table of a's list (linear probing, keys w + 1, 0 = empty) ----------------------
 __device__ __forceinline__ void hash_insert(uint32_t* hkey, uint16_t* hidx, uint32_t bits, uint32_t w,
                                             uint32_t i) {
     const uint32_t mask = (1u << bits) - 1u;
@@ -206,7 +274,7 @@ __device__ __forceinline__ int hash_find(const uint32_t* hkey, const uint16_t* h
     const uint32_t mask = (1u << bits) - 1u;
     uint32_t h = (w * kHashMul) >> (32 - bits);
     for (;;) {
-        uint32_t k = hkey[h];
+        const uint32_t k = hkey[h];
         if (k == w + 1u) return hidx[h];
         if (k == 0u) return -1;
         h = (h + 1u) & mask;
@@ -217,7 +285,7 @@ __device__ __forceinline__ int hash_find(const uint32_t* hkey, const uint16_t* h
 __device__ __forceinline__ uint32_t find_seg(const uint32_t* scan, uint32_t cnt, uint32_t it) {
     uint32_t lo = 0, hi = cnt;
     while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
+        const uint32_t mid = (lo + hi) >> 1;
         if (scan[mid] <= it) lo = mid; else hi = mid;
     }
     return lo;
@@ -227,11 +295,259 @@ __device__ __forceinline__ uint32_t find_seg(const uint32_t* scan, uint32_t cnt,
 __device__ __forceinline__ uint32_t find_job(const JobDev* jobs, uint32_t njobs, uint32_t tile, bool heavy) {
     uint32_t lo = 0, hi = njobs;
     while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        uint32_t p = heavy ? jobs[mid].heavy_prefix : jobs[mid].light_prefix;
+        const uint32_t mid = (lo + hi) >> 1;
+        const uint32_t p = heavy ? jobs[mid].heavy_prefix : jobs[mid].light_prefix;
         if (p <= tile) lo = mid; else hi = mid;
     }
     return lo;
+}
+
+// exclusive scan over the team (wave: 64 lanes; block: all threads, via T.red)
+template <bool BLOCK>
+__device__ __forceinline__ uint32_t team_excl_scan(uint32_t v, uint32_t* red, uint32_t& total) {
+    const uint32_t inc = wave_incl_scan(v);
+    if (!BLOCK) {
+        total = __shfl(inc, 63, 64);
+        return inc - v;
+    }
+    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 63) red[wid] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+        const uint32_t x = red[w];
+        if (w < wid) pre += x;
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return pre + inc - v;
+}
+
+template <bool BLOCK>
+__device__ __forceinline__ uint32_t team_sum(uint32_t v, uint32_t* red) {
+    const uint32_t s = wave_sum(v);
+    if (!BLOCK) return s;
+    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) red[16 + wid] = s;
+    __syncthreads();
+    uint32_t t = 0;
+    for (uint32_t w = 0; w < nw; ++w) t += red[16 + w];
+    __syncthreads();
+    return t;
+}
+
+// Attribute queued hits [0, qn) of this wavefront.  A hit is (B index ib, W index k, list
+// position p): the triangle (a, b = eb[ib], w = ew[k]) with times t_ab = etb[ib],
+// t_aw = et[k], t_bw = tim[p].  Its first two edges by time decide the processor per group:
+// edges at a have their slots staged; {b, w} is hashed here.
+__device__ void drain_hits(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a, uint32_t qn) {
+    const uint32_t lane = lane_id();
+    for (uint32_t q0 = 0; q0 < qn; q0 += 64) {
+        const uint32_t q = q0 + lane;
+        if (q < qn) {
+            const uint32_t v = V.qv[q];
+            const uint32_t ib = v & 0xffffu, k = v >> 16;
+            const uint32_t p = V.qp[q];
+            const uint32_t b = T.eb[ib], w = T.ew[k];
+            const uint32_t tab = T.etb[ib], taw = T.et[k], tbw = J.tim[p];
+            // which edge arrived last: 0 = {a,b}, 1 = {a,w}, 2 = {b,w} (times are distinct)
+            const uint32_t last = (tab > taw && tab > tbw) ? 0u : (taw > tbw ? 1u : 2u);
+            const uint32_t tl = last == 0 ? tab : (last == 1 ? taw : tbw);
+            if (tl >= J.t0 && tl < J.t1) {
+                for (uint32_t g = 0; g < J.G; ++g) {
+                    const uint32_t sab = T.bslot[g * T.DB + ib], saw = T.wslot[g * T.DW + k];
+                    uint32_t s1, s2;
+                    if (last == 2) {
+                        s1 = sab;
+                        s2 = saw;
+                    } else {
+                        s1 = last == 0 ? saw : sab;
+                        s2 = slot_of(V.coef + 4 * g, J.m, b, w);
+                    }
+                    const uint32_t ck = (g + 1 < J.G) ? J.m : J.last_ck;
+                    if (s1 == s2 && s1 < ck) {
+                        const uint32_t proc = g * J.m + s1;
+                        if (J.use_hist) atomicAdd(&V.hist[proc], 1u);
+                        else add64(J.global + proc, 1);
+                        if (J.per_proc) {
+                            int64_t* row = J.local + (uint64_t)proc * J.n;
+                            add64(row + a, 1);
+                            add64(row + b, 1);
+                            add64(row + w, 1);
+                        } else {
+                            atomicAdd(&T.cntb[g * T.DB + ib], 1u);
+                            atomicAdd(&T.cntw[g * T.DW + k], 1u);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    wave_sync();
+}
+
+// Walk items [w_begin, w_end) (in windows of 64) of the staged B chunk: item `it` is entry
+// it - bscan[own] of the list of b = eb[own], where own is the largest index with
+// bscan[own] <= it.  Non-empty lists only, so segment starts are distinct.
+__device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a, uint32_t bits,
+                           uint32_t bn, uint32_t T_items, uint32_t it_begin, uint32_t it_end) {
+    const uint32_t lane = lane_id();
+    uint32_t qn = 0;
+    if (it_begin >= it_end) return;
+    uint32_t i0 = find_seg(T.bscan, bn, it_begin);  // owner of the first item (uniform)
+    for (uint32_t base = it_begin; base < it_end; base += 64) {
+        // owners of the 64 items of this window: mark segment starts, then a running max
+        V.mark[lane] = 0;
+        wave_sync();
+        const uint32_t idx = i0 + 1 + lane;
+        if (idx < bn) {
+            const uint32_t st = T.bscan[idx];
+            if (st < base + 64) V.mark[st - base] = lane + 1;
+        }
+        wave_sync();
+        const uint32_t rel = wave_incl_max(V.mark[lane]);
+        const uint32_t own = i0 + rel;
+        const uint32_t it = base + lane;
+        bool hit = false;
+        uint32_t p = 0, k = 0;
+        if (it < it_end) {
+            p = T.boff[own] + (it - T.bscan[own]);
+            const int kk = hash_find(T.hkey, T.hidx, bits, J.nbr[p]);
+            hit = kk >= 0;
+            k = (uint32_t)kk;
+        }
+        const uint64_t hm = __ballot(hit);
+        if (hit) {
+            const uint32_t pos = qn + __popcll(hm & ((1ull << lane) - 1ull));
+            V.qv[pos] = own | (k << 16);
+            V.qp[pos] = p;
+        }
+        qn += (uint32_t)__popcll(hm);
+        if (qn >= 64) {
+            wave_sync();
+            drain_hits(J, T, V, a, qn);
+            qn = 0;
+        }
+        // owner of the next window's first item
+        const uint32_t last_own = __shfl(own, 63, 64);
+        const uint32_t nx = last_own + 1;
+        i0 = (nx < bn && T.bscan[nx] <= base + 64) ? nx : last_own;
+        wave_sync();
+    }
+    if (qn) {
+        wave_sync();
+        drain_hits(J, T, V, a, qn);
+    }
+}
+
+// Count every triangle whose lowest-ranked node is a.  The team is the workgroup (BLOCK) or
+// this wavefront.  a's list is hashed into LDS in chunks of DW entries (W side); for each W
+// chunk the lists of all of a's out-neighbours are walked in chunks of DB entries (B side).
+template <bool BLOCK>
+__device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a) {
+    const uint32_t nt = BLOCK ? blockDim.x : 64;
+    const uint32_t tid = BLOCK ? threadIdx.x : lane_id();
+    const uint32_t nw = nt >> 6, wid = BLOCK ? (threadIdx.x >> 6) : 0;
+    const uint32_t s = J.off[a], d = J.off[a + 1] - s;
+    const uint32_t G = J.G;
+    for (uint32_t ws = 0; ws < d; ws += T.DW) {
+        const uint32_t wn = (d - ws) < T.DW ? (d - ws) : T.DW;
+        const uint32_t bits = log2u(pow2_at_least(2 * wn));
+        for (uint32_t i = tid; i < (1u << bits); i += nt) T.hkey[i] = 0;
+        team_sync<BLOCK>();
+        for (uint32_t i = tid; i < wn; i += nt) {
+            const uint32_t w = J.nbr[s + ws + i];
+            T.ew[i] = w;
+            T.et[i] = J.tim[s + ws + i];
+            for (uint32_t g = 0; g < G; ++g) {
+                T.wslot[g * T.DW + i] = (uint16_t)slot_of(V.coef + 4 * g, J.m, a, w);
+                T.cntw[g * T.DW + i] = 0;
+            }
+            hash_insert(T.hkey, T.hidx, bits, w, i);
+        }
+        team_sync<BLOCK>();
+        for (uint32_t bs = 0; bs < d; bs += T.DB) {
+            const uint32_t braw = (d - bs) < T.DB ? (d - bs) : T.DB;
+            // stage the non-empty lists of this chunk: compact by a scan of "non-empty", then
+            // scan their lengths
+            uint32_t nb = 0, items = 0;
+            for (uint32_t c0 = 0; c0 < braw; c0 += nt) {
+                const uint32_t i = c0 + tid;
+                uint32_t b = 0, bo = 0, bd = 0, tb = 0;
+                if (i < braw) {
+                    b = J.nbr[s + bs + i];
+                    tb = J.tim[s + bs + i];
+                    bo = J.off[b];
+                    bd = J.off[b + 1] - bo;
+                }
+                uint32_t tot_nb, tot_items;
+                const uint32_t pos = nb + team_excl_scan<BLOCK>(bd ? 1u : 0u, T.red, tot_nb);
+                const uint32_t sc = items + team_excl_scan<BLOCK>(bd, T.red, tot_items);
+                if (bd) {
+                    T.eb[pos] = b;
+                    T.etb[pos] = tb;
+                    T.boff[pos] = bo;
+                    T.bscan[pos] = sc;
+                    for (uint32_t g = 0; g < G; ++g) {
+                        T.bslot[g * T.DB + pos] = (uint16_t)slot_of(V.coef + 4 * g, J.m, a, b);
+                        T.cntb[g * T.DB + pos] = 0;
+                    }
+                }
+                nb += tot_nb;
+                items += tot_items;
+            }
+            if (tid == 0) T.bscan[nb] = items;
+            team_sync<BLOCK>();
+            if (nb) {
+                // each wavefront of the team walks one contiguous range of windows
+                const uint32_t nwin = (items + 63) / 64;
+                const uint32_t per = (nwin + nw - 1) / nw;
+                const uint32_t w0 = wid * per, w1 = (w0 + per) < nwin ? (w0 + per) : nwin;
+                const uint32_t ib = w0 * 64, ie = (w1 * 64) < items ? (w1 * 64) : items;
+                if (w0 < w1) walk_items(J, T, V, a, bits, nb, items, ib, ie);
+            }
+            team_sync<BLOCK>();
+            if (!J.per_proc) {
+                for (uint32_t x = tid; x < G * nb; x += nt) {
+                    const uint32_t g = x / nb, i = x - g * nb;
+                    const uint32_t v = T.cntb[g * T.DB + i];
+                    if (v) add64(J.local + (uint64_t)g * J.n + T.eb[i], v);
+                }
+            }
+            team_sync<BLOCK>();
+        }
+        if (!J.per_proc) {
+            // flush the w-side counts; their sum per group is a's own count for this chunk
+            for (uint32_t g = 0; g < G; ++g) {
+                uint32_t part = 0;
+                for (uint32_t i = tid; i < wn; i += nt) {
+                    const uint32_t v = T.cntw[g * T.DW + i];
+                    if (v) {
+                        add64(J.local + (uint64_t)g * J.n + T.ew[i], v);
+                        part += v;
+                    }
+                }
+                const uint32_t tot = team_sum<BLOCK>(part, T.red);
+                if (tid == 0 && tot) add64(J.local + (uint64_t)g * J.n + a, tot);
+            }
+        }
+        team_sync<BLOCK>();
+    }
+}
+
+__device__ void flush_hist(const JobRegs& J, const WaveView& V, int cur) {
+    if (cur < 0 || !J.use_hist) return;
+    const uint32_t lane = lane_id();
+    wave_sync();
+    for (uint32_t p = lane; p < J.c; p += 64) {
+        const uint32_t v = V.hist[p];
+        if (v) {
+            add64(J.global + p, v);
+            V.hist[p] = 0;
+        }
+    }
+    wave_sync();
 }
 
 // ======================================================================= setup / zero ====
@@ -252,8 +568,8 @@ __global__ void k_setup(BatchHeader* hdr, JobDev* jobs) {
         // apexes are sorted by out-degree, descending: the ones above `cap` form a prefix
         uint32_t lo = 0, hi = J.unit1;  // first index whose out-degree <= cap (unit1 <= num_apex)
         while (lo < hi) {
-            uint32_t mid = (lo + hi) >> 1;
-            uint32_t a = J.apex[mid];
+            const uint32_t mid = (lo + hi) >> 1;
+            const uint32_t a = J.apex[mid];
             if (J.off[a + 1] - J.off[a] > cap) lo = mid + 1; else hi = mid;
         }
         const uint32_t hb = lo;
@@ -285,335 +601,70 @@ __global__ void k_zero(const BatchHeader* hdr, const JobDev* jobs) {
     }
 }
 
-// ======================================================================= light kernel ====
+// ======================================================================= count kernel ====
 
-__global__ void __launch_bounds__(256) k_light(BatchHeader* hdr, const JobDev* __restrict__ jobs) {
+__global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* __restrict__ jobs) {
     extern __shared__ __align__(16) uint8_t lds[];
-    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const uint32_t D = hdr->wave_cap, GM = hdr->G_max, HC = hdr->hist_c;
-    const uint32_t njobs = hdr->njobs, total = hdr->light_total, tile_len = hdr->light_tile;
-    const LightLayout L = light_layout(D, GM, HC);
-    uint8_t* base = lds + wid * L.team;
-    uint64_t* coef = (uint64_t*)(base + L.coef);
-    uint32_t* hkey = (uint32_t*)(base + L.hkey);
-    uint16_t* hidx = (uint16_t*)(base + L.hidx);
-    uint32_t* ew = (uint32_t*)(base + L.ew);
-    uint32_t* et = (uint32_t*)(base + L.et);
-    uint32_t* boff = (uint32_t*)(base + L.boff);
-    uint32_t* bscan = (uint32_t*)(base + L.bscan);
-    uint16_t* eslot = (uint16_t*)(base + L.slot);
-    uint32_t* cnt = (uint32_t*)(base + L.cnt);
-    uint32_t* acnt = (uint32_t*)(base + L.acnt);
-    uint32_t* hist = (uint32_t*)(base + L.hist);
+    const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t DL = hdr->wave_cap, DW = hdr->block_cap, DB = hdr->b_chunk;
+    const uint32_t GM = hdr->G_max, HC = hdr->hist_c, njobs = hdr->njobs;
+    const Layout L = count_layout(nw, DL, DW, DB, GM, HC);
+    const WaveView V = wave_view(lds + wid * L.misc.bytes, L.misc);
+    uint8_t* uni = lds + L.union_off;
+    __shared__ uint32_t s_tile;
 
-    for (uint32_t i = lane; i < HC; i += 64) hist[i] = 0;
-    wave_sync();
-
+    for (uint32_t i = lane; i < HC; i += 64) V.hist[i] = 0;
     JobRegs J;
     int cur = -1;
-    uint64_t since_flush = 0;
 
-    auto flush_hist = [&]() {
-        if (cur >= 0 && HC && J.c <= HC) {  // jobs with c > HC bypass the histogram
-            wave_sync();
-            for (uint32_t p = lane; p < J.c; p += 64) {
-                uint32_t v = hist[p];
-                if (v) {
-                    add64(J.global + p, v);
-                    hist[p] = 0;
-                }
+    // phase 1: long lists, one apex per workgroup
+    {
+        const TeamView T = team_view(uni, L.heavy, DW, DB);
+        const uint32_t total = hdr->heavy_total;
+        for (;;) {
+            if (threadIdx.x == 0) s_tile = atomicAdd(&hdr->q_heavy, 1u);
+            __syncthreads();
+            const uint32_t tile = s_tile;
+            __syncthreads();
+            if (tile >= total) break;
+            const uint32_t j = find_job(jobs, njobs, tile, true);
+            if ((int)j != cur) {
+                flush_hist(J, V, cur);
+                load_job(jobs + j, HC, J);
+                if (lane < 4 * REPT_GMAX) V.coef[lane] = jobs[j].hp[lane];
+                cur = (int)j;
             }
-            wave_sync();
-        }
-        since_flush = 0;
-    };
-
-    for (;;) {
-        uint32_t tile = 0;
-        if (lane == 0) tile = atomicAdd(&hdr->q_light, 1u);
-        tile = __shfl(tile, 0, 64);
-        if (tile >= total) break;
-        const uint32_t j = find_job(jobs, njobs, tile, false);
-        if ((int)j != cur) {
-            flush_hist();
-            load_job(jobs + j, J);
-            if (lane < 4 * REPT_GMAX) coef[lane] = jobs[j].hp[lane];
-            cur = (int)j;
-            wave_sync();
-        }
-        const JobDev& JD = jobs[j];
-        const uint32_t ub = JD.unit0 + JD.n_heavy + (tile - JD.light_prefix) * tile_len;
-        uint32_t ue = ub + tile_len;
-        if (ue > JD.unit1) ue = JD.unit1;
-        const bool use_hist = HC != 0 && J.c <= HC;
-
-        for (uint32_t u = ub; u < ue; ++u) {
-            const uint32_t a = J.apex[u];
-            const uint32_t s = J.off[a], d = J.off[a + 1] - s;
-            const uint32_t bits = log2u(pow2_at_least(2 * d));
-            const uint32_t Ha = 1u << bits;
-            for (uint32_t i = lane; i < Ha; i += 64) hkey[i] = 0;
-            if (!J.per_proc) {
-                for (uint32_t g = 0; g < J.G; ++g)
-                    for (uint32_t i = lane; i < d; i += 64) cnt[g * D + i] = 0;
-                if (lane < REPT_GMAX) acnt[lane] = 0;
-            }
-            wave_sync();
-            // stage a's list: ids, times, slots of the edges {a, x}, hash table, list scan
-            uint32_t run = 0;
-            for (uint32_t c0 = 0; c0 < d; c0 += 64) {
-                const uint32_t i = c0 + lane;
-                uint32_t bd = 0;
-                if (i < d) {
-                    const uint32_t w = J.nbr[s + i];
-                    ew[i] = w;
-                    et[i] = J.tim[s + i];
-                    const uint32_t bo = J.off[w];
-                    bd = J.off[w + 1] - bo;
-                    boff[i] = bo;
-                    for (uint32_t g = 0; g < J.G; ++g) eslot[g * D + i] = (uint16_t)slot_of(coef + 4 * g, J.m, a, w);
-                    hash_insert(hkey, hidx, bits, w, i);
-                }
-                const uint32_t inc = wave_incl_scan(bd);
-                if (i < d) bscan[i] = run + inc - bd;
-                run += __shfl(inc, 63, 64);
-            }
-            if (lane == 0) bscan[d] = run;
-            wave_sync();
-            const uint32_t T = run;
-            for (uint32_t b0 = 0; b0 < T; b0 += 64) {
-                const uint32_t it = b0 + lane;
-                if (it < T) {
-                    const uint32_t i = find_seg(bscan, d, it);
-                    const uint32_t p = boff[i] + (it - bscan[i]);
-                    const uint32_t w = J.nbr[p];
-                    const int k = hash_find(hkey, hidx, bits, w);
-                    if (k >= 0) {
-                        const uint32_t b = ew[i];
-                        attribute(
-                            J, coef, b, w, et[i], et[k], J.tim[p], [&](uint32_t g) { return (uint32_t)eslot[g * D + i]; },
-                            [&](uint32_t g) { return (uint32_t)eslot[g * D + k]; },
-                            [&](uint32_t g, uint32_t proc) {
-                                if (use_hist) atomicAdd(&hist[proc], 1u);
-                                else add64(J.global + proc, 1);
-                                if (J.per_proc) {
-                                    int64_t* row = J.local + (uint64_t)proc * J.n;
-                                    add64(row + a, 1);
-                                    add64(row + b, 1);
-                                    add64(row + w, 1);
-                                } else {
-                                    atomicAdd(&acnt[g], 1u);
-                                    atomicAdd(&cnt[g * D + i], 1u);
-                                    atomicAdd(&cnt[g * D + k], 1u);
-                                }
-                            });
-                    }
-                }
-            }
-            wave_sync();
-            if (!J.per_proc) {
-                for (uint32_t g = 0; g < J.G; ++g) {
-                    int64_t* row = J.local + (uint64_t)g * J.n;
-                    for (uint32_t i = lane; i < d; i += 64) {
-                        const uint32_t v = cnt[g * D + i];
-                        if (v) add64(row + ew[i], v);
-                    }
-                }
-                if (lane < J.G) {
-                    const uint32_t v = acnt[lane];
-                    if (v) add64(J.local + (uint64_t)lane * J.n + a, v);
-                }
-            }
-            wave_sync();
-            since_flush += T;
-            if (since_flush > (1ull << 30)) flush_hist();
+            __syncthreads();
+            const uint32_t a = J.apex[jobs[j].unit0 + (tile - jobs[j].heavy_prefix)];
+            count_apex<true>(J, T, V, a);
         }
     }
-    flush_hist();
-}
+    __syncthreads();  // the union area changes owners
 
-// ======================================================================= heavy kernel ====
-
-__device__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
-    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const uint32_t inc = wave_incl_scan(v);
-    if (lane == 63) wsum[wid] = inc;
-    __syncthreads();
-    uint32_t pre = 0, tot = 0;
-    for (uint32_t w = 0; w < nw; ++w) {
-        const uint32_t x = wsum[w];
-        if (w < wid) pre += x;
-        tot += x;
+    // phase 2: short lists, one apex per wavefront
+    {
+        const TeamView T = team_view(uni + wid * L.light.bytes, L.light, DL, DL);
+        const uint32_t total = hdr->light_total, tile_len = hdr->light_tile;
+        for (;;) {
+            uint32_t tile = 0;
+            if (lane == 0) tile = atomicAdd(&hdr->q_light, 1u);
+            tile = __shfl(tile, 0, 64);
+            if (tile >= total) break;
+            const uint32_t j = find_job(jobs, njobs, tile, false);
+            if ((int)j != cur) {
+                flush_hist(J, V, cur);
+                load_job(jobs + j, HC, J);
+                if (lane < 4 * REPT_GMAX) V.coef[lane] = jobs[j].hp[lane];
+                cur = (int)j;
+                wave_sync();
+            }
+            const JobDev& JD = jobs[j];
+            const uint32_t ub = JD.unit0 + JD.n_heavy + (tile - JD.light_prefix) * tile_len;
+            const uint32_t ue = (ub + tile_len) < JD.unit1 ? (ub + tile_len) : JD.unit1;
+            for (uint32_t u = ub; u < ue; ++u) count_apex<false>(J, T, V, J.apex[u]);
+        }
     }
-    __syncthreads();
-    total = tot;
-    return pre + inc - v;
-}
-
-__global__ void __launch_bounds__(1024) k_heavy(BatchHeader* hdr, const JobDev* __restrict__ jobs) {
-    extern __shared__ __align__(16) uint8_t lds[];
-    const uint32_t tid = threadIdx.x, nt = blockDim.x;
-    const uint32_t D = hdr->block_cap, GM = hdr->G_max, HC = hdr->hist_c;
-    const uint32_t njobs = hdr->njobs, total = hdr->heavy_total;
-    const HeavyLayout L = heavy_layout(D, GM, HC);
-    uint64_t* coef = (uint64_t*)(lds + L.coef);
-    uint32_t* hkey = (uint32_t*)(lds + L.hkey);
-    uint16_t* hidx = (uint16_t*)(lds + L.hidx);
-    uint32_t* ew = (uint32_t*)(lds + L.ew);
-    uint32_t* et = (uint32_t*)(lds + L.et);
-    uint16_t* wslot = (uint16_t*)(lds + L.wslot);
-    uint32_t* cntw = (uint32_t*)(lds + L.cntw);
-    uint32_t* eb = (uint32_t*)(lds + L.eb);
-    uint32_t* etb = (uint32_t*)(lds + L.etb);
-    uint32_t* boff = (uint32_t*)(lds + L.boff);
-    uint32_t* bscan = (uint32_t*)(lds + L.bscan);
-    uint16_t* bslot = (uint16_t*)(lds + L.bslot);
-    uint32_t* cntb = (uint32_t*)(lds + L.cntb);
-    uint32_t* acnt = (uint32_t*)(lds + L.acnt);
-    uint32_t* hist = (uint32_t*)(lds + L.hist);
-    uint32_t* misc = (uint32_t*)(lds + L.misc);  // [0]: tile, [16..31]: wave sums
-
-    for (uint32_t i = tid; i < HC; i += nt) hist[i] = 0;
-    __syncthreads();
-
-    JobRegs J;
-    int cur = -1;
-    uint64_t since_flush = 0;
-    auto flush_hist = [&]() {
-        if (cur >= 0 && HC && J.c <= HC) {  // jobs with c > HC bypass the histogram
-            __syncthreads();
-            for (uint32_t p = tid; p < J.c; p += nt) {
-                const uint32_t v = hist[p];
-                if (v) {
-                    add64(J.global + p, v);
-                    hist[p] = 0;
-                }
-            }
-            __syncthreads();
-        }
-        since_flush = 0;
-    };
-
-    for (;;) {
-        if (tid == 0) misc[0] = atomicAdd(&hdr->q_heavy, 1u);
-        __syncthreads();
-        const uint32_t tile = misc[0];
-        __syncthreads();
-        if (tile >= total) break;
-        const uint32_t j = find_job(jobs, njobs, tile, true);
-        if ((int)j != cur) {
-            flush_hist();
-            load_job(jobs + j, J);
-            if (tid < 4 * REPT_GMAX) coef[tid] = jobs[j].hp[tid];
-            cur = (int)j;
-            __syncthreads();
-        }
-        const bool use_hist = HC != 0 && J.c <= HC;
-        const uint32_t a = J.apex[jobs[j].unit0 + (tile - jobs[j].heavy_prefix)];
-        const uint32_t s = J.off[a], d = J.off[a + 1] - s;
-        if (tid < REPT_GMAX) acnt[tid] = 0;
-
-        for (uint32_t ws = 0; ws < d; ws += D) {
-            const uint32_t wn = (d - ws) < D ? (d - ws) : D;
-            const uint32_t bits = log2u(pow2_at_least(2 * wn));
-            const uint32_t Ha = 1u << bits;
-            for (uint32_t i = tid; i < Ha; i += nt) hkey[i] = 0;
-            if (!J.per_proc)
-                for (uint32_t x = tid; x < J.G * wn; x += nt) cntw[(x / wn) * D + (x % wn)] = 0;
-            __syncthreads();
-            for (uint32_t i = tid; i < wn; i += nt) {
-                const uint32_t w = J.nbr[s + ws + i];
-                ew[i] = w;
-                et[i] = J.tim[s + ws + i];
-                for (uint32_t g = 0; g < J.G; ++g) wslot[g * D + i] = (uint16_t)slot_of(coef + 4 * g, J.m, a, w);
-                hash_insert(hkey, hidx, bits, w, i);
-            }
-            __syncthreads();
-            for (uint32_t bs = 0; bs < d; bs += D) {
-                const uint32_t bn = (d - bs) < D ? (d - bs) : D;
-                uint32_t run = 0;
-                for (uint32_t c0 = 0; c0 < bn; c0 += nt) {
-                    const uint32_t i = c0 + tid;
-                    uint32_t bd = 0;
-                    if (i < bn) {
-                        const uint32_t b = J.nbr[s + bs + i];
-                        eb[i] = b;
-                        etb[i] = J.tim[s + bs + i];
-                        const uint32_t bo = J.off[b];
-                        bd = J.off[b + 1] - bo;
-                        boff[i] = bo;
-                        for (uint32_t g = 0; g < J.G; ++g) {
-                            bslot[g * D + i] = (uint16_t)slot_of(coef + 4 * g, J.m, a, b);
-                            if (!J.per_proc) cntb[g * D + i] = 0;
-                        }
-                    }
-                    uint32_t tot;
-                    const uint32_t ex = block_excl_scan(bd, misc + 16, tot);
-                    if (i < bn) bscan[i] = run + ex;
-                    run += tot;
-                }
-                if (tid == 0) bscan[bn] = run;
-                __syncthreads();
-                const uint32_t T = run;
-                for (uint32_t b0 = 0; b0 < T; b0 += nt) {
-                    const uint32_t it = b0 + tid;
-                    if (it < T) {
-                        const uint32_t i = find_seg(bscan, bn, it);
-                        const uint32_t p = boff[i] + (it - bscan[i]);
-                        const uint32_t w = J.nbr[p];
-                        const int k = hash_find(hkey, hidx, bits, w);
-                        if (k >= 0) {
-                            const uint32_t b = eb[i];
-                            attribute(
-                                J, coef, b, w, etb[i], et[k], J.tim[p],
-                                [&](uint32_t g) { return (uint32_t)bslot[g * D + i]; },
-                                [&](uint32_t g) { return (uint32_t)wslot[g * D + k]; },
-                                [&](uint32_t g, uint32_t proc) {
-                                    if (use_hist) atomicAdd(&hist[proc], 1u);
-                                    else add64(J.global + proc, 1);
-                                    if (J.per_proc) {
-                                        int64_t* row = J.local + (uint64_t)proc * J.n;
-                                        add64(row + a, 1);
-                                        add64(row + b, 1);
-                                        add64(row + w, 1);
-                                    } else {
-                                        atomicAdd(&acnt[g], 1u);
-                                        atomicAdd(&cntb[g * D + i], 1u);
-                                        atomicAdd(&cntw[g * D + k], 1u);
-                                    }
-                                });
-                        }
-                    }
-                }
-                __syncthreads();
-                if (!J.per_proc) {
-                    for (uint32_t x = tid; x < J.G * bn; x += nt) {
-                        const uint32_t g = x / bn, i = x % bn;
-                        const uint32_t v = cntb[g * D + i];
-                        if (v) add64(J.local + (uint64_t)g * J.n + eb[i], v);
-                    }
-                }
-                __syncthreads();
-                since_flush += T;
-                if (since_flush > (1ull << 30)) flush_hist();
-            }
-            if (!J.per_proc) {
-                for (uint32_t x = tid; x < J.G * wn; x += nt) {
-                    const uint32_t g = x / wn, i = x % wn;
-                    const uint32_t v = cntw[g * D + i];
-                    if (v) add64(J.local + (uint64_t)g * J.n + ew[i], v);
-                }
-                if (tid < J.G) {  // a's own count, flushed per chunk to stay within 32 bits
-                    const uint32_t v = acnt[tid];
-                    if (v) add64(J.local + (uint64_t)tid * J.n + a, v);
-                }
-            }
-            __syncthreads();
-            if (tid < REPT_GMAX) acnt[tid] = 0;
-        }
-        __syncthreads();
-    }
-    flush_hist();
+    flush_hist(J, V, cur);
 }
 
 // ======================================================================= hash slots ======
@@ -633,17 +684,23 @@ __global__ void k_slots(HashParams P, uint32_t G, uint32_t m, const uint2* __res
 
 bool g_attr_set = false;
 
+hipError_t report(hipError_t e, const char* what) {
+    if (e != hipSuccess) fprintf(stderr, "rept: %s failed: %s\n", what, hipGetErrorString(e));
+    return e;
+}
+
 hipError_t set_attrs() {
     if (g_attr_set) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute((const void*)k_light, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)k_heavy, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
+    // the kernel's static LDS (a few bytes) and the dynamic part share the CU's 160 KB
+    hipError_t e = hipFuncSetAttribute((const void*)k_count, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024 - 256);
+    if (e != hipSuccess) return report(e, "hipFuncSetAttribute(k_count)");
     g_attr_set = true;
     return hipSuccess;
 }
 
 hipError_t launch_common(uint8_t* ws, const BatchHeader& h, hipStream_t s) {
+    (void)hipGetLastError();  // launch errors below are this call's own
     hipError_t e = set_attrs();
     if (e != hipSuccess) return e;
     BatchHeader* hdr = (BatchHeader*)ws;
@@ -655,19 +712,28 @@ hipError_t launch_common(uint8_t* ws, const BatchHeader& h, hipStream_t s) {
         if (blocks < 1) blocks = 1;
         hipLaunchKernelGGL(k_zero, dim3((uint32_t)blocks, h.njobs), dim3(256), 0, s, hdr, jobs);
     }
-    hipLaunchKernelGGL(k_heavy, dim3(h.heavy_blocks), dim3(h.heavy_threads), h.heavy_lds, s, hdr, jobs);
-    hipLaunchKernelGGL(k_light, dim3(h.light_blocks), dim3(256), h.light_lds, s, hdr, jobs);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_count, dim3(h.blocks), dim3(h.threads), h.lds_bytes, s, hdr, jobs);
+    return report(hipGetLastError(), "counting kernel launch");
 }
 
 }  // namespace
 
-uint32_t rept_light_lds(uint32_t wave_cap, uint32_t G, uint32_t hist_c) {
-    return 4 * light_layout(wave_cap, G, hist_c).team;
+uint32_t rept_count_lds(uint32_t threads, uint32_t wave_cap, uint32_t block_cap, uint32_t b_chunk, uint32_t G,
+                        uint32_t hist_c) {
+    return count_layout(threads / 64, wave_cap, block_cap, b_chunk, G, hist_c).total;
 }
 
-uint32_t rept_heavy_lds(uint32_t block_cap, uint32_t G, uint32_t hist_c) {
-    return heavy_layout(block_cap, G, hist_c).total;
+uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes) {
+    if (set_attrs() != hipSuccess) return 0;
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_count, (int)threads,
+                                                                (size_t)lds_bytes);
+    if (e != hipSuccess) {
+        report(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor(k_count)");
+        (void)hipGetLastError();
+        return 0;
+    }
+    return nb > 0 ? (uint32_t)nb : 0u;
 }
 
 hipError_t rept_launch_batch(void* ws, const BatchHeader& h, hipStream_t s) {

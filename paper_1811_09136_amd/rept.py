@@ -51,9 +51,9 @@ class rept_job(ctypes.Structure):
 
 
 class rept_tuning(ctypes.Structure):
-    _fields_ = [("wave_cap", ctypes.c_uint32), ("block_cap", ctypes.c_uint32), ("light_blocks", ctypes.c_uint32),
-                ("heavy_blocks", ctypes.c_uint32), ("heavy_threads", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 3)]
+    _fields_ = [("wave_cap", ctypes.c_uint32), ("block_cap", ctypes.c_uint32), ("b_chunk", ctypes.c_uint32),
+                ("blocks", ctypes.c_uint32), ("threads", ctypes.c_uint32), ("light_tile", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 _lib = None
@@ -305,5 +305,6 @@ def make_job(graph: Graph, params: Params, out, t0: int = 0, t1: int = UINT64_MA
                     REPT_JOB_ACCUMULATE if accumulate else 0, 0)
 
 
-def tuning(wave_cap=0, block_cap=0, light_blocks=0, heavy_blocks=0, heavy_threads=0) -> rept_tuning:
-    return rept_tuning(wave_cap, block_cap, light_blocks, heavy_blocks, heavy_threads, (ctypes.c_uint32 * 3)())
+def tuning(wave_cap=0, block_cap=0, b_chunk=0, blocks=0, threads=0, light_tile=0) -> rept_tuning:
+    """Launch shape of the counting kernel (zero = library default); see ``rept_tuning`` in rept.h."""
+    return rept_tuning(wave_cap, block_cap, b_chunk, blocks, threads, light_tile, (ctypes.c_uint32 * 2)())

@@ -98,9 +98,11 @@ def test_windows_additive(cuda):
     assert np.array_equal(acc_g, full[0]) and np.array_equal(acc_l, full[1])
 
 
-@pytest.mark.parametrize("tune", [dict(wave_cap=16, block_cap=64, heavy_threads=256),
-                                  dict(wave_cap=32, block_cap=128, heavy_threads=1024),
-                                  dict(wave_cap=512, block_cap=2048, heavy_threads=512, light_blocks=3, heavy_blocks=1)])
+@pytest.mark.parametrize("tune", [dict(wave_cap=16, block_cap=64, b_chunk=16, threads=256),
+                                  dict(wave_cap=32, block_cap=128, b_chunk=64, threads=1024, light_tile=1),
+                                  dict(wave_cap=8, block_cap=64, b_chunk=1024, threads=64, blocks=3),
+                                  dict(wave_cap=256, block_cap=2048, b_chunk=256, threads=512, blocks=1,
+                                       light_tile=256)])
 def test_launch_shapes(cuda, tune):
     from paper_1811_09136_amd import rept
     e, n = synth.scaled_chung_lu(120_000, 31)
@@ -172,6 +174,7 @@ def test_lds_budget_rejected(cuda):
     ws = torch.empty(rept.rept_batch_workspace_size(1), dtype=torch.uint8, device=cuda)
     _say("LDS budget rejection")
     with pytest.raises(rept.ReptError) as ei:
-        rept.rept_batch_count([job], rept.tuning(block_cap=4096), ws.data_ptr(), ws.numel(), None)
+        rept.rept_batch_count([job], rept.tuning(block_cap=4096, b_chunk=1024, threads=1024), ws.data_ptr(),
+                              ws.numel(), None)
     assert ei.value.code == rept.REPT_EINVAL
     g.close()
