@@ -140,13 +140,25 @@ __global__ void k_fill_u32(uint32_t* p, uint64_t count, uint32_t v) {
         p[i] = v;
 }
 
-// degrees, range and self-loop checks
-__global__ void k_degree(const uint2* __restrict__ edges, uint64_t E, uint32_t n, uint32_t* deg,
-                         BuildStats* st) {
+// ---- degrees without global atomics: endpoints are partitioned into buckets of 2^shift
+// consecutive ids (at most DEG_BUCKETS buckets, one LDS histogram per workgroup), then each
+// bucket is counted by one workgroup in LDS.  Hub ids therefore never contend in memory.
+constexpr uint32_t DEG_BUCKETS = 4096;
+constexpr uint32_t DEG_SUB = 8192;  // ids counted per LDS pass
+
+// per-workgroup bucket histogram of the endpoints of its edge range, with the range and
+// self-loop checks of the stream (invalid edges contribute nothing)
+__global__ void __launch_bounds__(1024) k_deg_hist(const uint2* __restrict__ edges, uint64_t E, uint32_t n,
+                                                   uint32_t shift, uint32_t NB, uint64_t per_block,
+                                                   uint32_t* __restrict__ bhist, BuildStats* st) {
+    __shared__ uint32_t h[DEG_BUCKETS];
+    for (uint32_t i = threadIdx.x; i < NB; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const uint64_t e0 = (uint64_t)blockIdx.x * per_block;
+    const uint64_t e1 = (e0 + per_block) < E ? (e0 + per_block) : E;
     uint32_t bad = 0;
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < E;
-         t += (uint64_t)gridDim.x * blockDim.x) {
-        uint2 e = edges[t];
+    for (uint64_t t = e0 + threadIdx.x; t < e1; t += blockDim.x) {
+        const uint2 e = edges[t];
         if (e.x >= n || e.y >= n) {
             bad |= RF_RANGE;
             continue;
@@ -155,10 +167,66 @@ __global__ void k_degree(const uint2* __restrict__ edges, uint64_t E, uint32_t n
             bad |= RF_SELFLOOP;
             continue;
         }
-        atomicAdd(&deg[e.x], 1u);
-        atomicAdd(&deg[e.y], 1u);
+        atomicAdd(&h[e.x >> shift], 1u);
+        atomicAdd(&h[e.y >> shift], 1u);
     }
     if (bad) atomicOr(&st->flags, bad);
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < NB; b += blockDim.x) bhist[(uint64_t)b * gridDim.x + blockIdx.x] = h[b];
+}
+
+// write every valid endpoint id into its bucket's range (order within a bucket is free)
+__global__ void __launch_bounds__(1024) k_deg_scatter(const uint2* __restrict__ edges, uint64_t E, uint32_t n,
+                                                      uint32_t shift, uint32_t NB, uint64_t per_block,
+                                                      const uint32_t* __restrict__ boff, uint32_t* __restrict__ part) {
+    __shared__ uint32_t base[DEG_BUCKETS];
+    for (uint32_t b = threadIdx.x; b < NB; b += blockDim.x) base[b] = boff[(uint64_t)b * gridDim.x + blockIdx.x];
+    __syncthreads();
+    const uint64_t e0 = (uint64_t)blockIdx.x * per_block;
+    const uint64_t e1 = (e0 + per_block) < E ? (e0 + per_block) : E;
+    for (uint64_t t = e0 + threadIdx.x; t < e1; t += blockDim.x) {
+        const uint2 e = edges[t];
+        if (e.x >= n || e.y >= n || e.x == e.y) continue;
+        part[atomicAdd(&base[e.x >> shift], 1u)] = e.x;
+        part[atomicAdd(&base[e.y >> shift], 1u)] = e.y;
+    }
+}
+
+// Workgroups take fixed slices of the partitioned endpoints (so a bucket full of hubs is
+// shared by many workgroups); within a slice each bucket's part is counted in LDS and added
+// to the degrees with one atomic per distinct id.  `deg` must be zero on entry.
+constexpr uint32_t DEG_SLICE = 65536;
+__global__ void __launch_bounds__(1024) k_deg_count(const uint32_t* __restrict__ part,
+                                                    const uint32_t* __restrict__ boff, uint32_t nblk, uint32_t NB,
+                                                    uint32_t shift, uint32_t n, uint32_t* __restrict__ deg) {
+    __shared__ uint32_t cnt[DEG_SUB];
+    const uint32_t total = boff[(uint64_t)NB * nblk];
+    const uint64_t span = (uint64_t)1 << shift;
+    for (uint64_t s0 = (uint64_t)blockIdx.x * DEG_SLICE; s0 < total; s0 += (uint64_t)gridDim.x * DEG_SLICE) {
+        const uint64_t s1 = (s0 + DEG_SLICE) < total ? (s0 + DEG_SLICE) : total;
+        const uint32_t b_first = part[s0] >> shift, b_last = part[s1 - 1] >> shift;
+        for (uint32_t b = b_first; b <= b_last; ++b) {
+            const uint64_t start = boff[(uint64_t)b * nblk];
+            const uint64_t end = (b + 1 < NB) ? boff[(uint64_t)(b + 1) * nblk] : total;
+            const uint64_t lo = start > s0 ? start : s0, hi = end < s1 ? end : s1;
+            if (lo >= hi) continue;
+            const uint64_t v0 = (uint64_t)b << shift;
+            for (uint64_t r0 = 0; r0 < span && v0 + r0 < n; r0 += DEG_SUB) {
+                for (uint32_t i = threadIdx.x; i < DEG_SUB; i += blockDim.x) cnt[i] = 0;
+                __syncthreads();
+                for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+                    const uint64_t x = (uint64_t)part[i] - v0 - r0;
+                    if (x < DEG_SUB) atomicAdd(&cnt[x], 1u);
+                }
+                __syncthreads();
+                for (uint32_t i = threadIdx.x; i < DEG_SUB; i += blockDim.x) {
+                    const uint64_t v = v0 + r0 + i;
+                    if (cnt[i] && v < n) atomicAdd(&deg[v], cnt[i]);
+                }
+                __syncthreads();
+            }
+        }
+    }
 }
 
 // out-degree of each lower-ranked endpoint
@@ -195,26 +263,59 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scatter(const uint2* __restric
     if (threadIdx.x == 0 && s) atomicAdd(&st->work, s);
 }
 
-// classify segments by size, histogram apexes by out-degree (descending order buckets)
+// Out-degrees below APEX_LDS_BINS are histogrammed per workgroup in LDS (the common small
+// out-degrees would otherwise hammer a few global counters); each workgroup covers one
+// contiguous node range.
+constexpr uint32_t APEX_LDS_BINS = 4096;
+
+__device__ __forceinline__ void node_range(uint32_t n, uint32_t& a0, uint32_t& a1) {
+    const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
+    a0 = blockIdx.x * per;
+    a1 = a0 + per < n ? a0 + per : n;
+    if (a0 > n) a0 = n;
+}
+
+// classify segments by size (sort path), histogram apexes by out-degree for the descending
+// apex order (bucket n-1-d), and the statistics of the oriented graph
 __global__ void __launch_bounds__(SCAN_THREADS) k_classify(const uint32_t* __restrict__ off, uint32_t n,
                                                            uint32_t* ahist, uint32_t* medium,
                                                            uint32_t* large, BuildStats* st) {
+    __shared__ uint32_t h[APEX_LDS_BINS];
+    __shared__ uint32_t cnt[2], base[2];
+    for (uint32_t i = threadIdx.x; i < APEX_LDS_BINS; i += blockDim.x) h[i] = 0;
+    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t a0, a1;
+    node_range(n, a0, a1);
     unsigned long long sq = 0;
     uint32_t mx = 0, napex = 0;
-    for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
-        uint32_t d = off[a + 1] - off[a];
+    for (uint32_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
+        const uint32_t d = off[a + 1] - off[a];
         sq += (unsigned long long)d * d;
         mx = d > mx ? d : mx;
         if (d >= 2) {
-            atomicAdd(&ahist[n - 1 - d], 1u);
+            if (d < APEX_LDS_BINS) atomicAdd(&h[d], 1u);
+            else atomicAdd(&ahist[n - 1 - d], 1u);
             ++napex;
         }
-        if (d > SMALL_MAX && d <= MEDIUM_MAX) medium[atomicAdd(&st->n_medium, 1u)] = a;
-        if (d > MEDIUM_MAX) large[atomicAdd(&st->n_large, 1u)] = a;
+        if (d > SMALL_MAX && d <= MEDIUM_MAX) atomicAdd(&cnt[0], 1u);
+        if (d > MEDIUM_MAX) atomicAdd(&cnt[1], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        base[0] = cnt[0] ? atomicAdd(&st->n_medium, cnt[0]) : 0;
+        base[1] = cnt[1] ? atomicAdd(&st->n_large, cnt[1]) : 0;
+    }
+    for (uint32_t d = threadIdx.x; d < APEX_LDS_BINS; d += blockDim.x)
+        if (h[d]) atomicAdd(&ahist[n - 1 - d], h[d]);
+    __syncthreads();
+    for (uint32_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
+        const uint32_t d = off[a + 1] - off[a];
+        if (d > SMALL_MAX && d <= MEDIUM_MAX) medium[atomicAdd(&base[0], 1u)] = a;
+        if (d > MEDIUM_MAX) large[atomicAdd(&base[1], 1u)] = a;
     }
     unsigned long long s = block_reduce_sum256<unsigned long long>(sq);
     uint32_t na = block_reduce_sum256<uint32_t>(napex);
-    // max via shuffles
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         uint32_t o = __shfl_xor(mx, d, 64);
@@ -227,13 +328,29 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_classify(const uint32_t* __res
     }
 }
 
-__global__ void k_apex_scatter(const uint32_t* __restrict__ off, uint32_t n, const uint32_t* __restrict__ aoff,
-                               uint32_t* acur, uint32_t* apex) {
-    for (uint32_t a = blockIdx.x * blockDim.x + threadIdx.x; a < n; a += gridDim.x * blockDim.x) {
-        uint32_t d = off[a + 1] - off[a];
+// place apexes in out-degree-descending order: reserve each bin's range once per workgroup
+__global__ void __launch_bounds__(SCAN_THREADS) k_apex_scatter(const uint32_t* __restrict__ off, uint32_t n,
+                                                               const uint32_t* __restrict__ aoff, uint32_t* acur,
+                                                               uint32_t* apex) {
+    __shared__ uint32_t h[APEX_LDS_BINS];
+    for (uint32_t i = threadIdx.x; i < APEX_LDS_BINS; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    uint32_t a0, a1;
+    node_range(n, a0, a1);
+    for (uint32_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
+        const uint32_t d = off[a + 1] - off[a];
+        if (d >= 2 && d < APEX_LDS_BINS) atomicAdd(&h[d], 1u);
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < APEX_LDS_BINS; d += blockDim.x)
+        if (h[d]) h[d] = aoff[n - 1 - d] + atomicAdd(&acur[n - 1 - d], h[d]);
+    __syncthreads();
+    for (uint32_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
+        const uint32_t d = off[a + 1] - off[a];
         if (d < 2) continue;
-        uint32_t bkt = n - 1 - d;
-        apex[aoff[bkt] + atomicAdd(&acur[bkt], 1u)] = a;
+        const uint32_t pos = d < APEX_LDS_BINS ? atomicAdd(&h[d], 1u)
+                                               : aoff[n - 1 - d] + atomicAdd(&acur[n - 1 - d], 1u);
+        apex[pos] = a;
     }
 }
 
@@ -388,8 +505,27 @@ struct Layout {
     size_t ctrl, off, nbr, tim, apex, total;
 };
 struct ScratchLayout {
-    size_t stats, deg, dout, cursor, ahist, aoff, part, packed, alt, medium, large, total;
+    size_t stats, deg, dout, cursor, ahist, aoff, part, packed, alt, medium, large, bhist, bscan, total;
 };
+
+// partition of endpoints for the degree count: buckets of 2^shift ids, NB <= DEG_BUCKETS of
+// them, nblk workgroups each covering per_block edges
+struct DegPlan {
+    uint32_t shift, NB, nblk;
+    uint64_t per_block;
+};
+DegPlan deg_plan(uint32_t n, uint64_t E) {
+    DegPlan D;
+    uint32_t bits = 1;
+    while (bits < 32 && ((uint64_t)1 << bits) < (uint64_t)n) ++bits;
+    D.shift = bits > 24 ? bits - 12 : 12;
+    D.NB = (uint32_t)(((uint64_t)n + ((uint64_t)1 << D.shift) - 1) >> D.shift);
+    uint64_t nb = (E + 8191) / 8192;
+    D.nblk = (uint32_t)(nb < 1 ? 1 : (nb > 2048 ? 2048 : nb));
+    D.per_block = (E + D.nblk - 1) / D.nblk;
+    if (D.per_block == 0) D.per_block = 1;
+    return D;
+}
 
 Layout persistent_layout(uint32_t n, uint64_t E) {
     Layout L;
@@ -411,7 +547,10 @@ Layout persistent_layout(uint32_t n, uint64_t E) {
 ScratchLayout scratch_layout(uint32_t n, uint64_t E) {
     ScratchLayout S;
     size_t p = 0;
-    const size_t nparts = ((size_t)n + 1 + SCAN_TILE - 1) / SCAN_TILE + 1;
+    const DegPlan D = deg_plan(n, E);
+    const size_t nhist = (size_t)D.NB * D.nblk;
+    const size_t scan_max = (nhist > (size_t)n ? nhist : (size_t)n) + 1;
+    const size_t nparts = (scan_max + SCAN_TILE - 1) / SCAN_TILE + 1;
     S.stats = p;
     p += align256(sizeof(BuildStats));
     S.deg = p;
@@ -434,6 +573,10 @@ ScratchLayout scratch_layout(uint32_t n, uint64_t E) {
     p += align256((size_t)n * 4);
     S.large = p;
     p += align256((size_t)n * 4);
+    S.bhist = p;
+    p += align256(nhist * 4);
+    S.bscan = p;
+    p += align256((nhist + 1) * 4);
     S.total = p;
     return S;
 }
@@ -484,25 +627,37 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     unsigned long long* alt = (unsigned long long*)(X + S.alt);
     uint32_t* medium = (uint32_t*)(X + S.medium);
     uint32_t* large = (uint32_t*)(X + S.large);
+    uint32_t* bhist = (uint32_t*)(X + S.bhist);
+    uint32_t* bscan = (uint32_t*)(X + S.bscan);
     const uint2* e2 = (const uint2*)edges;
 
     const uint32_t cus = rept_num_cus();
     const uint32_t cap = cus ? cus * 16 : 4096;
     const uint32_t gE = grid_for(E, 256, cap), gN = grid_for(n, 256, cap);
+    const uint32_t gA = grid_for(n, 2048, 512);  // node-range kernels with LDS histograms
+    const DegPlan D = deg_plan(n, E);
 
     // clear counters (fill kernels rather than memsets, so the sequence is capture-safe)
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)st,
                        (uint64_t)(sizeof(BuildStats) / 4), 0u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, deg, (uint64_t)n, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, dout, (uint64_t)n, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, cursor, (uint64_t)n, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, ahist, (uint64_t)n, 0u);
 
-    hipLaunchKernelGGL(k_degree, dim3(gE), dim3(256), 0, s, e2, E, n, deg, st);
+    // degrees: partition endpoints by id bucket (reusing `packed` as the partition), count in LDS
+    uint32_t* ends = (uint32_t*)packed;
+    hipLaunchKernelGGL(k_deg_hist, dim3(D.nblk), dim3(1024), 0, s, e2, E, n, D.shift, D.NB, D.per_block, bhist, st);
+    if (scan_u32(bhist, (uint64_t)D.NB * D.nblk, part, bscan, s) != hipSuccess) return REPT_EDEVICE;
+    hipLaunchKernelGGL(k_deg_scatter, dim3(D.nblk), dim3(1024), 0, s, e2, E, n, D.shift, D.NB, D.per_block, bscan,
+                       ends);
+    hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, deg, (uint64_t)n, 0u);
+    hipLaunchKernelGGL(k_deg_count, dim3(grid_for(2 * E, DEG_SLICE, 4096)), dim3(1024), 0, s, ends, bscan, D.nblk,
+                       D.NB, D.shift, n, deg);
+
     hipLaunchKernelGGL(k_orient_count, dim3(gE), dim3(256), 0, s, e2, E, n, deg, dout);
     if (scan_u32(dout, n, part, off, s) != hipSuccess) return REPT_EDEVICE;
     hipLaunchKernelGGL(k_scatter, dim3(gE), dim3(256), 0, s, e2, E, n, deg, dout, off, cursor, packed, st);
-    hipLaunchKernelGGL(k_classify, dim3(gN), dim3(256), 0, s, off, n, ahist, medium, large, st);
+    hipLaunchKernelGGL(k_classify, dim3(gA), dim3(256), 0, s, off, n, ahist, medium, large, st);
     hipLaunchKernelGGL(k_sort_small, dim3(grid_for((uint64_t)n, 4, cap * 4)), dim3(256), 0, s, off, n, packed,
                        nbr, tim, st);
     hipLaunchKernelGGL(k_sort_medium, dim3(cus ? cus * 4 : 1024), dim3(512), 0, s, off, medium, packed, nbr,
@@ -513,7 +668,7 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
                        nbr, tim, st);
     if (scan_u32(ahist, n, part, aoff, s) != hipSuccess) return REPT_EDEVICE;
     hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, cursor, (uint64_t)n, 0u);
-    hipLaunchKernelGGL(k_apex_scatter, dim3(gN), dim3(256), 0, s, off, n, aoff, cursor, apex);
+    hipLaunchKernelGGL(k_apex_scatter, dim3(gA), dim3(256), 0, s, off, n, aoff, cursor, apex);
     if (hipGetLastError() != hipSuccess) return REPT_EDEVICE;
 
     BuildStats hs;

@@ -729,7 +729,7 @@ uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes) {
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_count, (int)threads,
                                                                 (size_t)lds_bytes);
     if (e != hipSuccess) {
-        report(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor(k_count)");
+        (void)report(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor(k_count)");
         (void)hipGetLastError();
         return 0;
     }
