@@ -93,7 +93,7 @@ __host__ __device__ inline uint32_t up16(uint32_t x) { return (x + 15u) & ~15u; 
 // wavefronts' light team areas (the heavy phase finishes before the light phase starts).
 struct Area {  // one team's staging area: W side (hash table of a's list) + B side (b lists)
     uint32_t hkey, hidx, ew, et, wslot, cntw;
-    uint32_t eb, etb, bslot, cntb, boff, bscan;
+    uint32_t eb, etb, bslot, cntb, bpos;
     uint32_t red;  // 64 words of team scratch (scans, reductions, broadcast)
     uint32_t bytes;
 };
@@ -111,8 +111,7 @@ __host__ __device__ inline Area area_layout(uint32_t DW, uint32_t DB, uint32_t G
     A.etb = p; p = up16(p + 4 * DB);
     A.bslot = p; p = up16(p + 2 * G * DB);
     A.cntb = p; p = up16(p + 4 * G * DB);
-    A.boff = p; p = up16(p + 4 * DB);
-    A.bscan = p; p = up16(p + 4 * (DB + 1));
+    A.bpos = p; p = up16(p + 8 * (DB + 1));  // (list offset, first item) per staged list
     A.red = p; p = up16(p + 4 * 64);
     A.bytes = p;
     return A;
@@ -160,8 +159,7 @@ struct TeamView {
     uint32_t* etb;
     uint16_t* bslot;
     uint32_t* cntb;
-    uint32_t* boff;
-    uint32_t* bscan;
+    uint2* bpos;  // .x: offset of b's list, .y: index of its first item in the chunk's walk
     uint32_t* red;
     uint32_t DW, DB;
 };
@@ -177,8 +175,7 @@ __device__ inline TeamView team_view(uint8_t* base, const Area& A, uint32_t DW, 
     T.etb = (uint32_t*)(base + A.etb);
     T.bslot = (uint16_t*)(base + A.bslot);
     T.cntb = (uint32_t*)(base + A.cntb);
-    T.boff = (uint32_t*)(base + A.boff);
-    T.bscan = (uint32_t*)(base + A.bscan);
+    T.bpos = (uint2*)(base + A.bpos);
     T.red = (uint32_t*)(base + A.red);
     T.DW = DW;
     T.DB = DB;
@@ -255,38 +252,49 @@ __device__ __forceinline__ void add64(int64_t* p, uint64_t v) {
     atomicAdd((unsigned long long*)p, (unsigned long long)v);
 }
 
-// ---- LDS hash table of a's list (linear probing, keys w + 1, 0 = empty) ----------------------
-__device__ __forceinline__ void hash_insert(uint32_t* hkey, uint16_t* hidx, uint32_t bits, uint32_t w,
+// loads from the graph arrays (global memory: lets the compiler emit global, not flat, loads)
+__device__ __forceinline__ uint32_t ldg(const uint32_t* p) {
+    return *(const __attribute__((address_space(1))) uint32_t*)p;
+}
+
+// ---- LDS hash table of a's list: 2-slot buckets probed linearly; keys w + 1, 0 = empty.
+// Slot 0 of a bucket fills before slot 1, so an empty slot ends a probe sequence.  kbits is
+// log2 of the bucket count (at least the number of keys: load factor <= 1/2).
+__device__ __forceinline__ void hash_insert(uint32_t* hkey, uint16_t* hidx, uint32_t kbits, uint32_t w,
                                             uint32_t i) {
-    const uint32_t mask = (1u << bits) - 1u;
-    uint32_t h = (w * kHashMul) >> (32 - bits);
+    const uint32_t mask = (1u << kbits) - 1u;
+    uint32_t b = (w * kHashMul) >> (32 - kbits);
     for (;;) {
-        uint32_t old = atomicCAS(&hkey[h], 0u, w + 1u);
-        if (old == 0u) {
-            hidx[h] = (uint16_t)i;
+        if (atomicCAS(&hkey[2 * b], 0u, w + 1u) == 0u) {
+            hidx[2 * b] = (uint16_t)i;
             return;
         }
-        h = (h + 1u) & mask;
+        if (atomicCAS(&hkey[2 * b + 1], 0u, w + 1u) == 0u) {
+            hidx[2 * b + 1] = (uint16_t)i;
+            return;
+        }
+        b = (b + 1u) & mask;
     }
 }
 
-__device__ __forceinline__ int hash_find(const uint32_t* hkey, const uint16_t* hidx, uint32_t bits, uint32_t w) {
-    const uint32_t mask = (1u << bits) - 1u;
-    uint32_t h = (w * kHashMul) >> (32 - bits);
+__device__ __forceinline__ int hash_find(const uint32_t* hkey, const uint16_t* hidx, uint32_t kbits, uint32_t w) {
+    const uint32_t mask = (1u << kbits) - 1u, key = w + 1u;
+    uint32_t b = (w * kHashMul) >> (32 - kbits);
     for (;;) {
-        const uint32_t k = hkey[h];
-        if (k == w + 1u) return hidx[h];
-        if (k == 0u) return -1;
-        h = (h + 1u) & mask;
+        const uint2 kk = *(const uint2*)(hkey + 2 * b);
+        if (kk.x == key) return hidx[2 * b];
+        if (kk.y == key) return hidx[2 * b + 1];
+        if (kk.y == 0u) return -1;
+        b = (b + 1u) & mask;
     }
 }
 
-// largest i in [0, cnt) with scan[i] <= it, given scan[0] <= it < scan[cnt]
-__device__ __forceinline__ uint32_t find_seg(const uint32_t* scan, uint32_t cnt, uint32_t it) {
+// largest i in [0, cnt) with bpos[i].y <= it, given bpos[0].y <= it < bpos[cnt].y
+__device__ __forceinline__ uint32_t find_seg(const uint2* bpos, uint32_t cnt, uint32_t it) {
     uint32_t lo = 0, hi = cnt;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (scan[mid] <= it) lo = mid; else hi = mid;
+        if (bpos[mid].y <= it) lo = mid; else hi = mid;
     }
     return lo;
 }
@@ -350,7 +358,7 @@ __device__ void drain_hits(const JobRegs& J, const TeamView& T, const WaveView& 
             const uint32_t ib = v & 0xffffu, k = v >> 16;
             const uint32_t p = V.qp[q];
             const uint32_t b = T.eb[ib], w = T.ew[k];
-            const uint32_t tab = T.etb[ib], taw = T.et[k], tbw = J.tim[p];
+            const uint32_t tab = T.etb[ib], taw = T.et[k], tbw = ldg(J.tim + p);
             // which edge arrived last: 0 = {a,b}, 1 = {a,w}, 2 = {b,w} (times are distinct)
             const uint32_t last = (tab > taw && tab > tbw) ? 0u : (taw > tbw ? 1u : 2u);
             const uint32_t tl = last == 0 ? tab : (last == 1 ? taw : tbw);
@@ -387,39 +395,45 @@ __device__ void drain_hits(const JobRegs& J, const TeamView& T, const WaveView& 
     wave_sync();
 }
 
-// Walk items [w_begin, w_end) (in windows of 64) of the staged B chunk: item `it` is entry
-// it - bscan[own] of the list of b = eb[own], where own is the largest index with
-// bscan[own] <= it.  Non-empty lists only, so segment starts are distinct.
-__device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a, uint32_t bits,
-                           uint32_t bn, uint32_t T_items, uint32_t it_begin, uint32_t it_end) {
+// popcount of the bits of `m` below this lane
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Walk items [it_begin, it_end) (in windows of 64) of the staged B chunk: item `it` is entry
+// it - bpos[own].y of the list of b = eb[own], where own is the largest index with
+// bpos[own].y <= it.  Only non-empty lists are staged, so list starts are distinct: a lane's
+// owner is i0 plus the number of list starts at or before its position in the window.
+__device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a, uint32_t kbits,
+                           uint32_t bn, uint32_t it_begin, uint32_t it_end) {
     const uint32_t lane = lane_id();
     uint32_t qn = 0;
     if (it_begin >= it_end) return;
-    uint32_t i0 = find_seg(T.bscan, bn, it_begin);  // owner of the first item (uniform)
+    uint32_t i0 = find_seg(T.bpos, bn, it_begin);  // owner of the first item (uniform)
     for (uint32_t base = it_begin; base < it_end; base += 64) {
-        // owners of the 64 items of this window: mark segment starts, then a running max
         V.mark[lane] = 0;
         wave_sync();
         const uint32_t idx = i0 + 1 + lane;
         if (idx < bn) {
-            const uint32_t st = T.bscan[idx];
-            if (st < base + 64) V.mark[st - base] = lane + 1;
+            const uint32_t st = T.bpos[idx].y;
+            if (st < base + 64) V.mark[st - base] = 1;
         }
         wave_sync();
-        const uint32_t rel = wave_incl_max(V.mark[lane]);
-        const uint32_t own = i0 + rel;
+        const uint32_t flag = V.mark[lane];
+        const uint32_t own = i0 + lanes_below(__ballot(flag != 0)) + flag;
         const uint32_t it = base + lane;
         bool hit = false;
         uint32_t p = 0, k = 0;
         if (it < it_end) {
-            p = T.boff[own] + (it - T.bscan[own]);
-            const int kk = hash_find(T.hkey, T.hidx, bits, J.nbr[p]);
+            const uint2 bp = T.bpos[own];
+            p = bp.x + (it - bp.y);
+            const int kk = hash_find(T.hkey, T.hidx, kbits, ldg(J.nbr + p));
             hit = kk >= 0;
             k = (uint32_t)kk;
         }
         const uint64_t hm = __ballot(hit);
         if (hit) {
-            const uint32_t pos = qn + __popcll(hm & ((1ull << lane) - 1ull));
+            const uint32_t pos = qn + lanes_below(hm);
             V.qv[pos] = own | (k << 16);
             V.qp[pos] = p;
         }
@@ -430,9 +444,9 @@ __device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& 
             qn = 0;
         }
         // owner of the next window's first item
-        const uint32_t last_own = __shfl(own, 63, 64);
+        const uint32_t last_own = __builtin_amdgcn_readlane(own, 63);
         const uint32_t nx = last_own + 1;
-        i0 = (nx < bn && T.bscan[nx] <= base + 64) ? nx : last_own;
+        i0 = (nx < bn && T.bpos[nx].y <= base + 64) ? nx : last_own;
         wave_sync();
     }
     if (qn) {
@@ -453,18 +467,18 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
     const uint32_t G = J.G;
     for (uint32_t ws = 0; ws < d; ws += T.DW) {
         const uint32_t wn = (d - ws) < T.DW ? (d - ws) : T.DW;
-        const uint32_t bits = log2u(pow2_at_least(2 * wn));
-        for (uint32_t i = tid; i < (1u << bits); i += nt) T.hkey[i] = 0;
+        const uint32_t slots = pow2_at_least(2 * wn), kbits = log2u(slots) - 1;
+        for (uint32_t i = tid; i < slots; i += nt) T.hkey[i] = 0;
         team_sync<BLOCK>();
         for (uint32_t i = tid; i < wn; i += nt) {
-            const uint32_t w = J.nbr[s + ws + i];
+            const uint32_t w = ldg(J.nbr + s + ws + i);
             T.ew[i] = w;
-            T.et[i] = J.tim[s + ws + i];
+            T.et[i] = ldg(J.tim + s + ws + i);
             for (uint32_t g = 0; g < G; ++g) {
                 T.wslot[g * T.DW + i] = (uint16_t)slot_of(V.coef + 4 * g, J.m, a, w);
                 T.cntw[g * T.DW + i] = 0;
             }
-            hash_insert(T.hkey, T.hidx, bits, w, i);
+            hash_insert(T.hkey, T.hidx, kbits, w, i);
         }
         team_sync<BLOCK>();
         for (uint32_t bs = 0; bs < d; bs += T.DB) {
@@ -476,10 +490,10 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                 const uint32_t i = c0 + tid;
                 uint32_t b = 0, bo = 0, bd = 0, tb = 0;
                 if (i < braw) {
-                    b = J.nbr[s + bs + i];
-                    tb = J.tim[s + bs + i];
-                    bo = J.off[b];
-                    bd = J.off[b + 1] - bo;
+                    b = ldg(J.nbr + s + bs + i);
+                    tb = ldg(J.tim + s + bs + i);
+                    bo = ldg(J.off + b);
+                    bd = ldg(J.off + b + 1) - bo;
                 }
                 uint32_t tot_nb, tot_items;
                 const uint32_t pos = nb + team_excl_scan<BLOCK>(bd ? 1u : 0u, T.red, tot_nb);
@@ -487,8 +501,7 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                 if (bd) {
                     T.eb[pos] = b;
                     T.etb[pos] = tb;
-                    T.boff[pos] = bo;
-                    T.bscan[pos] = sc;
+                    T.bpos[pos] = make_uint2(bo, sc);
                     for (uint32_t g = 0; g < G; ++g) {
                         T.bslot[g * T.DB + pos] = (uint16_t)slot_of(V.coef + 4 * g, J.m, a, b);
                         T.cntb[g * T.DB + pos] = 0;
@@ -497,7 +510,7 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                 nb += tot_nb;
                 items += tot_items;
             }
-            if (tid == 0) T.bscan[nb] = items;
+            if (tid == 0) T.bpos[nb] = make_uint2(0u, items);
             team_sync<BLOCK>();
             if (nb) {
                 // each wavefront of the team walks one contiguous range of windows
@@ -505,7 +518,7 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                 const uint32_t per = (nwin + nw - 1) / nw;
                 const uint32_t w0 = wid * per, w1 = (w0 + per) < nwin ? (w0 + per) : nwin;
                 const uint32_t ib = w0 * 64, ie = (w1 * 64) < items ? (w1 * 64) : items;
-                if (w0 < w1) walk_items(J, T, V, a, bits, nb, items, ib, ie);
+                if (w0 < w1) walk_items(J, T, V, a, kbits, nb, ib, ie);
             }
             team_sync<BLOCK>();
             if (!J.per_proc) {
