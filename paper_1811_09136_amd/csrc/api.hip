@@ -234,17 +234,33 @@ rept_status rept_estimate(uint32_t n, const rept_params* params, const int64_t* 
     }
     double* tv = tau_v_hat;
     if (tv && local) {
+        // S_v summed row by row (sequential reads) into an exact int64 buffer, then scaled
         const uint32_t rows = rept_local_rows(params);
-        for (uint32_t v = 0; v < n; ++v) {
-            int64_t Sv = 0;
-            for (uint32_t r = 0; r < rows; ++r) {
-                const int64_t x = local[(uint64_t)r * n + v];
-                if (x < 0 || x >= limit - Sv) return REPT_ERANGE;
-                Sv += x;
+        int64_t* acc = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+        if (!acc) return REPT_ENOMEM;
+        memcpy(acc, local, sizeof(int64_t) * (size_t)n);
+        bool bad = false;
+        for (uint32_t v = 0; v < n; ++v) bad |= (acc[v] < 0 || acc[v] >= limit);
+        for (uint32_t r = 1; r < rows && !bad; ++r) {
+            const int64_t* row = local + (uint64_t)r * n;
+            for (uint32_t v = 0; v < n; ++v) {
+                const int64_t x = row[v];
+                if (x < 0 || x >= limit - acc[v]) {
+                    bad = true;
+                    break;
+                }
+                acc[v] += x;
             }
-            const double prod = (double)Sv * num;
+        }
+        if (bad) {
+            free(acc);
+            return REPT_ERANGE;
+        }
+        for (uint32_t v = 0; v < n; ++v) {
+            const double prod = (double)acc[v] * num;
             tv[v] = prod / den;
         }
+        free(acc);
     }
     const double prod = (double)S * num;
     *tau_hat = prod / den;

@@ -50,30 +50,21 @@ __device__ __forceinline__ void team_sync() {
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
 
+// Inclusive prefix sum over the 64 lanes with DPP: shifts by 1, 2, 4, 8 within rows of 16
+// lanes, then row 0's and row 2's last lanes broadcast into rows 1 and 3 (row_bcast:15), then
+// lane 31 into rows 2 and 3 (row_bcast:31).  Lanes without a source add zero.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t o = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v += o;
-    }
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t o = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v = o > v ? o : v;
-    }
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
     return v;
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
+    return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), 63);
 }
 
 __host__ __device__ inline uint32_t pow2_at_least(uint32_t x) {
@@ -502,8 +493,12 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                     T.eb[pos] = b;
                     T.etb[pos] = tb;
                     T.bpos[pos] = make_uint2(bo, sc);
+                    // the edge {a, b} is also a W entry when it falls in the current W chunk
+                    const uint32_t e = bs + i;
+                    const bool staged = e >= ws && e < ws + wn;
                     for (uint32_t g = 0; g < G; ++g) {
-                        T.bslot[g * T.DB + pos] = (uint16_t)slot_of(V.coef + 4 * g, J.m, a, b);
+                        T.bslot[g * T.DB + pos] =
+                            staged ? T.wslot[g * T.DW + (e - ws)] : (uint16_t)slot_of(V.coef + 4 * g, J.m, a, b);
                         T.cntb[g * T.DB + pos] = 0;
                     }
                 }

@@ -1,0 +1,77 @@
+"""C ABI of librept.so on the host (CPU only): exported symbols, host-only calls, and the
+FP64 estimator against the oracle's (0 ulp)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "rept.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rept_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1811_09136_amd import rept
+    lib = rept.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(rept.EXPORTED) <= set(names)
+
+
+def test_host_only_calls():
+    from paper_1811_09136_amd import rept
+    assert rept.rept_local_rows(rept.Params(10, 40, 1)) == 4
+    assert rept.rept_local_rows(rept.Params(10, 40, 1, per_proc=True)) == 40
+    assert rept.rept_local_rows(rept.Params(7, 3, 1)) == 1
+    pb, sb = rept.rept_query_sizes(1_000_000, 20_000_000)
+    assert pb >= 8 * 20_000_000 and sb > 0
+    for bad in [(0, 10), (1 << 30, 10), (10, 1 << 31)]:
+        with pytest.raises(rept.ReptError) as ei:
+            rept.rept_query_sizes(*bad)
+        assert ei.value.code == rept.REPT_EINVAL
+    assert rept.rept_status_str(rept.REPT_EDUP) == "duplicate edge in stream"
+    lib = rept.lib()
+    p = rept.rept_params(0, 1, 0, 0, 0)
+    assert lib.rept_local_rows(ctypes.byref(p)) == 0
+
+
+@pytest.mark.parametrize("m,c", [(1, 1), (10, 10), (10, 40), (7, 3), (100, 400), (3, 1)])
+def test_estimate_zero_ulp_against_oracle(m, c):
+    from paper_1811_09136_amd import rept
+    rng = np.random.default_rng(m * 1000 + c)
+    n = 500
+    G = -(-c // m)
+    glob = rng.integers(0, 2**40, size=c)
+    loc = rng.integers(0, 2**40, size=(G, n))
+    th, tv = rept.rept_estimate(n, rept.Params(m, c, 0), glob, loc)
+    oth, otv = oracle.estimate(n, m, c, glob, loc)
+    assert th == oth
+    assert np.array_equal(tv.view(np.uint64), otv.view(np.uint64))
+    glob2 = rng.integers(0, 2**40, size=c)
+    locp = rng.integers(0, 2**40, size=(c, n))
+    th, tv = rept.rept_estimate(n, rept.Params(m, c, 0, per_proc=True), glob2, locp)
+    oth, otv = oracle.estimate(n, m, c, glob2, locp)
+    assert th == oth and np.array_equal(tv.view(np.uint64), otv.view(np.uint64))
+
+
+def test_estimate_errors_match_oracle():
+    from paper_1811_09136_amd import rept
+    with pytest.raises(rept.ReptError) as ei:
+        rept.rept_estimate(3, rept.Params(10, 15, 0), np.zeros(15, np.int64), None)
+    assert ei.value.code == rept.REPT_ENOTSUP
+    with pytest.raises(rept.ReptError) as ei:
+        rept.rept_estimate(3, rept.Params(2, 2, 0), np.array([2**52, 2**52]), None)
+    assert ei.value.code == rept.REPT_ERANGE
+    with pytest.raises(rept.ReptError) as ei:
+        rept.rept_estimate(2, rept.Params(2, 2, 0), np.array([1, 1]), np.array([[2**52, 1]], np.int64) * 0 + np.array([[-1, 0]]))
+    assert ei.value.code == rept.REPT_ERANGE
