@@ -68,6 +68,8 @@ def _load():
         L.oracle_validate.restype = i32
         L.oracle_rept.argtypes = [u32, u32, u32, u64, i32, vp, u64, u64, u64, vp, vp, vp]
         L.oracle_rept.restype = i32
+        L.oracle_rept_procs.argtypes = [u32, u32, u32, u64, i32, vp, u64, u64, u64, vp, u32, u32, vp, vp]
+        L.oracle_rept_procs.restype = i32
         L.oracle_edge_updates.argtypes = [u32, u32, u32, u64, i32, vp, u64, vp, u64, vp, vp]
         L.oracle_edge_updates.restype = i32
         L.oracle_estimate.argtypes = [u32, u32, u32, u32, vp, vp, vp, vp]
@@ -127,6 +129,38 @@ def rept(edges, n: int, m: int, c: int, seed: int, per_proc: bool = False, t0: i
                              None if ov is None else ov.ctypes.data, glob.ctypes.data, loc.ctypes.data)
     if rc != OK:
         raise OracleError(rc, "oracle_rept")
+    return glob, loc
+
+
+def rept_threads(edges, n: int, m: int, c: int, seed: int, per_proc: bool = False, t0: int = 0,
+                 t1: int | None = None, workers: int = 8):
+    """Algorithm 1 with the c processors split over host threads (the C replay releases the
+    GIL).  Processors are independent, so the per-thread partial counts sum to ``rept``."""
+    import concurrent.futures as cf
+    e = _edges(edges)
+    E = len(e)
+    t1 = E if t1 is None else t1
+    G = groups(m, c)
+    rows = c if per_proc else G
+    workers = max(1, min(workers, c))
+    bounds = [(c * w // workers, c * (w + 1) // workers) for w in range(workers)]
+
+    def run(lo_hi):
+        lo, hi = lo_hi
+        g = np.zeros(c, dtype=np.int64)
+        lo_arr = np.zeros((rows, n), dtype=np.int64)
+        rc = _load().oracle_rept_procs(n, m, c, seed & (2**64 - 1), int(per_proc), e.ctypes.data, E, t0, t1,
+                                       None, lo, hi, g.ctypes.data, lo_arr.ctypes.data)
+        if rc != OK:
+            raise OracleError(rc, "oracle_rept_procs")
+        return g, lo_arr
+
+    glob = np.zeros(c, dtype=np.int64)
+    loc = np.zeros((rows, n), dtype=np.int64)
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        for g, lo_arr in ex.map(run, bounds):
+            glob += g
+            loc += lo_arr
     return glob, loc
 
 

@@ -153,13 +153,20 @@ int oracle_validate(uint32_t n, const uint32_t *edges, uint64_t E) {
     for (uint64_t t = 0; t < E; ++t) {
         if (edges[2 * t] == edges[2 * t + 1]) return OR_ESELFLOOP;
     }
-    edgeset s;
-    if (es_init(&s, E)) return OR_ENOMEM;
+    /* set of unordered pairs seen so far (keys only; open addressing, load <= 1/2) */
+    uint64_t cap = 16;
+    while (cap < 2 * E + 2) cap <<= 1;
+    uint64_t *key = (uint64_t *)calloc(cap, sizeof(uint64_t));
+    if (!key) return OR_ENOMEM;
     int rc = OR_OK;
     for (uint64_t t = 0; t < E && rc == OR_OK; ++t) {
-        if (!es_put(&s, pairkey(edges[2 * t], edges[2 * t + 1]), t)) rc = OR_EDUP;
+        const uint64_t k1 = pairkey(edges[2 * t], edges[2 * t + 1]) + 1;
+        uint64_t h = mix(k1 - 1) & (cap - 1);
+        while (key[h] && key[h] != k1) h = (h + 1) & (cap - 1);
+        if (key[h] == k1) rc = OR_EDUP;
+        key[h] = k1;
     }
-    es_free(&s);
+    free(key);
     return rc;
 }
 
@@ -199,12 +206,15 @@ static int adj_push(adjlist *a, uint32_t w) {
  *   local[k*n + v]               = sum over processors i of group k of tau_v^(i)   (per_proc = 0)
  *   local[i*n + v]               = tau_v^(i)                                       (per_proc = 1)
  * slot_override (optional, [G][E] uint16): replaces h_k(edge t) by slot_override[k*E + t].
+ * Only processors i in [p_lo, p_hi) are replayed (processors are independent trials, Section
+ * I); the others contribute nothing, so disjoint ranges sum to the full result.
  */
-int oracle_rept(uint32_t n, uint32_t m, uint32_t c, uint64_t seed, int per_proc,
-                const uint32_t *edges, uint64_t E, uint64_t t0, uint64_t t1,
-                const uint16_t *slot_override, int64_t *global, int64_t *local) {
+int oracle_rept_procs(uint32_t n, uint32_t m, uint32_t c, uint64_t seed, int per_proc,
+                      const uint32_t *edges, uint64_t E, uint64_t t0, uint64_t t1,
+                      const uint16_t *slot_override, uint32_t p_lo, uint32_t p_hi, int64_t *global,
+                      int64_t *local) {
     if (n == 0 || m == 0 || c == 0 || !edges || !global || !local) return OR_EINVAL;
-    if (t0 > t1 || t1 > E) return OR_EINVAL;
+    if (t0 > t1 || t1 > E || p_lo > p_hi || p_hi > c) return OR_EINVAL;
     int rc = oracle_validate(n, edges, E);
     if (rc) return rc;
     const uint32_t G = (c + m - 1) / m;
@@ -221,12 +231,14 @@ int oracle_rept(uint32_t n, uint32_t m, uint32_t c, uint64_t seed, int per_proc,
 
     for (uint32_t k = 0; k < G && rc == OR_OK; ++k) {
         const uint32_t ck = (k + 1 < G) ? m : c - (G - 1) * m; /* processors in group k */
+        if (k * m + ck <= p_lo || k * m >= p_hi) continue;  /* no processor of this group asked */
         for (uint64_t t = 0; t < E; ++t) {
             slot[t] = slot_override ? slot_override[(uint64_t)k * E + t]
                                     : oracle_slot(params + 4 * k, m, edges[2 * t], edges[2 * t + 1]);
         }
         for (uint32_t j = 0; j < ck && rc == OR_OK; ++j) {
             const uint32_t i = k * m + j;
+            if (i < p_lo || i >= p_hi) continue;
             int64_t *loc = local + (uint64_t)(per_proc ? i : k) * n;
             uint64_t mine = 0; /* |E^(i)| at the end of the stream */
             for (uint64_t t = 0; t < E; ++t) mine += (slot[t] == j);
@@ -272,6 +284,13 @@ int oracle_rept(uint32_t n, uint32_t m, uint32_t c, uint64_t seed, int per_proc,
     return rc;
 }
 
+/* all c processors */
+int oracle_rept(uint32_t n, uint32_t m, uint32_t c, uint64_t seed, int per_proc,
+                const uint32_t *edges, uint64_t E, uint64_t t0, uint64_t t1,
+                const uint16_t *slot_override, int64_t *global, int64_t *local) {
+    return oracle_rept_procs(n, m, c, seed, per_proc, edges, E, t0, t1, slot_override, 0, c, global, local);
+}
+
 /* ------------------------------------------------------------------ per-edge form -------- */
 
 /*
@@ -310,27 +329,43 @@ int oracle_edge_updates(uint32_t n, uint32_t m, uint32_t c, uint64_t seed, int p
     const uint32_t G = (c + m - 1) / m;
     uint64_t *params = (uint64_t *)malloc(sizeof(uint64_t) * 4 * G);
     uint64_t *off = (uint64_t *)calloc((uint64_t)n + 1, sizeof(uint64_t));
-    nbr_t *nb = (nbr_t *)malloc(sizeof(nbr_t) * 2 * (E ? E : 1));
     uint64_t *fill = (uint64_t *)calloc((uint64_t)n, sizeof(uint64_t));
-    if (!params || !off || !nb || !fill) {
+    uint8_t *need = (uint8_t *)calloc((uint64_t)n, 1);
+    if (!params || !off || !fill || !need) {
         free(params);
         free(off);
-        free(nb);
         free(fill);
+        free(need);
         return OR_ENOMEM;
     }
     oracle_hash_params(seed, G, params);
-    for (uint64_t t = 0; t < E; ++t) {
-        off[edges[2 * t] + 1]++;
-        off[edges[2 * t + 1] + 1]++;
+    /* adjacency lists only of the endpoints of the edges asked for */
+    for (uint64_t q = 0; q < nts; ++q) {
+        need[edges[2 * ts[q]]] = 1;
+        need[edges[2 * ts[q] + 1]] = 1;
     }
-    for (uint32_t x = 0; x < n; ++x) off[x + 1] += off[x];
     for (uint64_t t = 0; t < E; ++t) {
         const uint32_t u = edges[2 * t], v = edges[2 * t + 1];
-        nb[off[u] + fill[u]++] = (nbr_t){v, (uint32_t)t};
-        nb[off[v] + fill[v]++] = (nbr_t){u, (uint32_t)t};
+        if (need[u]) off[u + 1]++;
+        if (need[v]) off[v + 1]++;
     }
-    for (uint32_t x = 0; x < n; ++x) qsort(nb + off[x], off[x + 1] - off[x], sizeof(nbr_t), cmp_nbr);
+    for (uint32_t x = 0; x < n; ++x) off[x + 1] += off[x];
+    nbr_t *nb = (nbr_t *)malloc(sizeof(nbr_t) * (off[n] ? off[n] : 1));
+    if (!nb) {
+        free(params);
+        free(off);
+        free(fill);
+        free(need);
+        return OR_ENOMEM;
+    }
+    for (uint64_t t = 0; t < E; ++t) {
+        const uint32_t u = edges[2 * t], v = edges[2 * t + 1];
+        if (need[u]) nb[off[u] + fill[u]++] = (nbr_t){v, (uint32_t)t};
+        if (need[v]) nb[off[v] + fill[v]++] = (nbr_t){u, (uint32_t)t};
+    }
+    for (uint32_t x = 0; x < n; ++x)
+        if (need[x]) qsort(nb + off[x], off[x + 1] - off[x], sizeof(nbr_t), cmp_nbr);
+    free(need);
 
     for (uint64_t q = 0; q < nts; ++q) {
         const uint64_t t = ts[q];
