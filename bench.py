@@ -7,7 +7,11 @@ the device-to-host copy of the integer counters and the FP64 estimators (rept_es
 Default workload: Chung-Lu power-law stream, 1,000,000 nodes, 20,000,000 edges, exponent 2.1,
 random order, m = 10 (p = 0.1), c = 40 (four hash groups).  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--workload NAME]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-batched] [--no-served]
+                  [--workload NAME]
+
+The line also carries "batched" (512 jobs: plain one-by-one vs one graph-captured batched launch)
+and "served" (Poisson requests: continuous batching vs a FIFO plain loop) comparisons.
 """
 from __future__ import annotations
 
@@ -41,6 +45,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--no-served", action="store_true", help="skip the served-vs-plain comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 1 GiB (reference for FETCH_SIZE/WRITE_SIZE scaling)")
     return ap.parse_args()
@@ -106,6 +112,90 @@ def cpu_baseline(edges, n, m, c):
     return {"value": len(edges) / job_s, "unit": "stream edges/s", "cores": 1, "kind": "oracle",
             "sample": f"Algorithm 1 replay of 1 of {c} processors (group 0, slot 0) over all {len(edges)} "
                       f"stream edges took {dt:.2f} s on one core; whole job = {c} x that"}
+
+
+def bench_batched(dev, reps: int = 3):
+    """512 jobs (256 independent Chung-Lu streams, 10k-2M edges log-uniform, plus 256 hash-seed
+    replicas of one 5M-edge stream), m = c = 20: one rept_count per job (plain) against one
+    autotuned, graph-captured launch of all jobs (batched).  Outputs must be identical."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1811_09136_amd import rept
+    from paper_1811_09136_amd.batch import Autotuner, Batch, Job, run_plain, time_call
+
+    t_gen = time.perf_counter()
+    streams, (rep, rep_n), rep_seeds = synth.batch_jobs(seed=4)
+    t_gen = time.perf_counter() - t_gen
+    graphs = [rept.Graph(rept.to_device_edges(e, dev), n) for e, n in streams]
+    rg = rept.Graph(rept.to_device_edges(rep, dev), rep_n)
+    P = lambda s: rept.Params(20, 20, int(s))
+    jobs = [Job(g, P(i + 1)) for i, g in enumerate(graphs)] + [Job(rg, P(s)) for s in rep_seeds]
+    for j in jobs:
+        j.ensure_outputs()
+    total = sum(len(e) for e, _ in streams) + len(rep) * len(rep_seeds)
+    run_plain(jobs)
+    plain_s = min(time_call(run_plain, jobs) for _ in range(reps))
+    ref = [(j.out[0].clone(), j.out[1].clone()) for j in jobs]
+    tuner = Autotuner(reps=2)
+    shape = tuner.best(jobs)
+    b = Batch(jobs, rept.tuning(**shape) if shape else None)
+    b.capture()
+    batched_s = min(time_call(b.replay) for _ in range(reps))
+    same = all(torch.equal(j.out[0], g) and torch.equal(j.out[1], l) for j, (g, l) in zip(jobs, ref))
+    # replica statistics (Theorem 3 with c = m: Var = tau (m - 1))
+    tau = int(rg.count(rept.Params(1, 1, 0))[0].item())
+    ests = np.array([rept.rept_estimate(rep_n, j.params, j.out[0].cpu().numpy(), None)[0]
+                     for j in jobs[len(streams):]])
+    nrmse = float(np.sqrt(np.mean((ests - tau) ** 2)) / tau)
+    for g in graphs:
+        g.close()
+    rg.close()
+    return {"workload": "256 Chung-Lu streams (1e4-2e6 edges, log-uniform) + 256 hash-seed replicas of a 5e6-edge "
+                        "stream, m=c=20",
+            "jobs": len(jobs), "stream_edges": int(total),
+            "plain_edges_per_s": total / plain_s, "batched_edges_per_s": total / batched_s,
+            "speedup": plain_s / batched_s, "plain_ms": 1e3 * plain_s, "batched_ms": 1e3 * batched_s,
+            "identical_outputs": bool(same), "tuned_shape": shape, "generation_s": t_gen,
+            "replicas": {"R": len(ests), "tau": tau, "mean_tau_hat": float(ests.mean()),
+                         "nrmse": nrmse, "nrmse_theory": float(np.sqrt(19.0 / tau))}}
+
+
+def bench_served(dev, n_requests: int = 64, mults=(0.25, 0.5, 1.0, 1.5, 2.0)):
+    """Poisson arrivals of count requests (lognormal sizes, median 2e5 edges, max 2e7; m in
+    {10, 50, 100}, c in {m, 4m}); continuous batching against a FIFO plain loop at arrival
+    rates swept around the plain loop's saturation rate."""
+    import numpy as np
+    import synth
+    from paper_1811_09136_amd.serve import DeviceExecutor, Request, Server, run_fifo_plain, summarize
+
+    tr = synth.serving_trace(seed=5, n_requests=n_requests, rate_per_s=1.0)
+    gaps = np.diff([0.0] + [r["arrival_s"] for r in tr])
+    graphs = [synth.scaled_chung_lu(r["E"], r["graph_seed"] % (2**31)) for r in tr]
+    ex = DeviceExecutor(dev)
+
+    def requests(rate):
+        arr = np.cumsum(gaps) / rate
+        return [Request(i, float(arr[i]), e, n, r["m"], r["c"], r["hash_seed"])
+                for i, ((e, n), r) in enumerate(zip(graphs, tr))]
+
+    import torch
+    free = torch.cuda.mem_get_info(dev)[0]
+    budget = int(0.5 * free)
+    run_fifo_plain(ex, requests(1e9)[:4])  # warm-up
+    sat = run_fifo_plain(ex, requests(1e9))  # everything at t = 0: service rate of the plain loop
+    mu = n_requests / (max(r.done_s for r in sat) - min(r.arrival_s for r in sat))
+    sweep = []
+    for mult in mults:
+        reqs = requests(mult * mu)
+        fifo = summarize(run_fifo_plain(ex, reqs), reqs)
+        srv = Server(ex, budget_bytes=budget, max_active=64, chunk_units=1 << 16, build_workers=2)
+        served = summarize(srv.run(reqs), reqs)
+        sweep.append({"rate_per_s": mult * mu, "rate_x_plain_saturation": mult, "fifo_plain": fifo,
+                      "served": served})
+    return {"workload": f"{n_requests} Poisson requests, lognormal edges (median 2e5, max 2e7), m in {{10,50,100}}, "
+                        "c in {m,4m}", "plain_saturation_req_per_s": mu, "hbm_budget_bytes": budget,
+            "total_edges": int(sum(len(e) for e, _ in graphs)), "sweep": sweep}
 
 
 def main():
@@ -221,6 +311,10 @@ def main():
                    "source_digest": count_kernel_source_digest()},
         "tau_hat": tau_hat,
     }
+    if not args.no_batched:
+        out["batched"] = bench_batched(dev)
+    if not args.no_served:
+        out["served"] = bench_served(dev)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(edges, n, m, c)
     print(json.dumps(out), flush=True)
