@@ -71,7 +71,13 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     if (threads < 64 || threads > 1024 || threads % 64) return REPT_EINVAL;
     if (light_tile < 1 || light_tile > 256) return REPT_EINVAL;
     const uint32_t hist_c = c_max <= REPT_HIST_CAP ? c_max : 0;
-    const uint32_t lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c);
+    // the light phase's hash tables are sparser (fewer probes) where the LDS budget allows
+    uint32_t light_table = 4;
+    uint32_t lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table);
+    if (lds > 160 * 1024 - 256) {
+        light_table = 2;
+        lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table);
+    }
     if (lds > 160 * 1024 - 256) return REPT_EINVAL;  // static LDS takes a few bytes more
     uint32_t blocks = tu ? tu->blocks : 0;
     if (!blocks) {
@@ -90,6 +96,7 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     h->hist_c = hist_c;
     h->G_max = G_max;
     h->lds_bytes = lds;
+    h->light_table = light_table;
     h->any_zero = any_zero ? 1u : 0u;
     h->zero_words = zero_words;
     return REPT_OK;

@@ -83,7 +83,7 @@ struct BatchHeader {
     uint32_t q_heavy;      // queue counters, reset by setup
     uint32_t q_light;
     uint32_t any_zero;     // some job overwrites its outputs
-    uint32_t pad0;
+    uint32_t light_table;  // hash slots per key, at least, in the light phase (2 or 4)
     uint64_t zero_words;   // max words to clear over jobs
     uint32_t pad[14];
 };
@@ -107,7 +107,7 @@ hipError_t rept_launch_slots(const uint64_t* hp, uint32_t G, uint32_t m, const u
                              uint64_t E, uint32_t* slots, hipStream_t stream);
 // LDS bytes of the counting kernel for a launch shape
 uint32_t rept_count_lds(uint32_t threads, uint32_t wave_cap, uint32_t block_cap, uint32_t b_chunk, uint32_t G,
-                        uint32_t hist_c);
+                        uint32_t hist_c, uint32_t light_table);
 // resident workgroups per CU of the counting kernel for a launch shape (0 if unknown)
 uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes);
 uint32_t rept_num_cus();

@@ -34,7 +34,9 @@ namespace {
 
 constexpr uint32_t kHashMul = 0x9E3779B1u;  // table index: Fibonacci hashing of the node id
 constexpr uint64_t kP61 = (1ull << 61) - 1;  // Mersenne prime of the edge hash
-constexpr uint32_t kQueue = 128;             // per-wavefront hit queue capacity
+constexpr uint32_t kWalk = 4;                // windows of 64 entries walked per round
+constexpr uint32_t kQueue = 64 * (kWalk + 1);  // per-wavefront hit queue: < 64 left + one round
+constexpr uint32_t kHeavyTable = 2;          // hash slots per key, at least (heavy phase)
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -88,9 +90,9 @@ struct Area {  // one team's staging area: W side (hash table of a's list) + B s
     uint32_t red;  // 64 words of team scratch (scans, reductions, broadcast)
     uint32_t bytes;
 };
-__host__ __device__ inline Area area_layout(uint32_t DW, uint32_t DB, uint32_t G) {
+__host__ __device__ inline Area area_layout(uint32_t DW, uint32_t DB, uint32_t G, uint32_t tf) {
     Area A;
-    const uint32_t H = pow2_at_least(2 * DW);
+    const uint32_t H = pow2_at_least(tf * DW);
     uint32_t p = 0;
     A.hkey = p; p = up16(p + 4 * H);
     A.hidx = p; p = up16(p + 2 * H);
@@ -114,7 +116,7 @@ __host__ __device__ inline Misc misc_layout(uint32_t HC) {
     Misc M;
     uint32_t p = 0;
     M.coef = p; p = up16(p + 8 * 4 * REPT_GMAX);
-    M.mark = p; p = up16(p + 4 * 64);
+    M.mark = p; p = up16(p + 64 * kWalk);  // one byte per entry of a round
     M.qv = p; p = up16(p + 4 * kQueue);
     M.qp = p; p = up16(p + 4 * kQueue);
     M.hist = p; p = up16(p + 4 * HC);
@@ -127,11 +129,11 @@ struct Layout {
     uint32_t union_off, total;
 };
 __host__ __device__ inline Layout count_layout(uint32_t nwaves, uint32_t DL, uint32_t DW, uint32_t DB,
-                                               uint32_t G, uint32_t HC) {
+                                               uint32_t G, uint32_t HC, uint32_t LT) {
     Layout L;
     L.misc = misc_layout(HC);
-    L.heavy = area_layout(DW, DB, G);
-    L.light = area_layout(DL, DL, G);
+    L.heavy = area_layout(DW, DB, G, kHeavyTable);
+    L.light = area_layout(DL, DL, G, LT);
     L.union_off = nwaves * L.misc.bytes;
     const uint32_t u = L.heavy.bytes > nwaves * L.light.bytes ? L.heavy.bytes : nwaves * L.light.bytes;
     L.total = L.union_off + u;
@@ -153,9 +155,11 @@ struct TeamView {
     uint2* bpos;  // .x: offset of b's list, .y: index of its first item in the chunk's walk
     uint32_t* red;
     uint32_t DW, DB;
+    uint32_t tf;  // hash slots per key, at least
 };
-__device__ inline TeamView team_view(uint8_t* base, const Area& A, uint32_t DW, uint32_t DB) {
+__device__ inline TeamView team_view(uint8_t* base, const Area& A, uint32_t DW, uint32_t DB, uint32_t tf) {
     TeamView T;
+    T.tf = tf;
     T.hkey = (uint32_t*)(base + A.hkey);
     T.hidx = (uint16_t*)(base + A.hidx);
     T.ew = (uint32_t*)(base + A.ew);
@@ -174,7 +178,7 @@ __device__ inline TeamView team_view(uint8_t* base, const Area& A, uint32_t DW, 
 }
 struct WaveView {
     uint64_t* coef;
-    uint32_t* mark;
+    uint8_t* mark;
     uint32_t* qv;
     uint32_t* qp;
     uint32_t* hist;
@@ -182,7 +186,7 @@ struct WaveView {
 __device__ inline WaveView wave_view(uint8_t* base, const Misc& M) {
     WaveView V;
     V.coef = (uint64_t*)(base + M.coef);
-    V.mark = (uint32_t*)(base + M.mark);
+    V.mark = base + M.mark;
     V.qv = (uint32_t*)(base + M.qv);
     V.qp = (uint32_t*)(base + M.qp);
     V.hist = (uint32_t*)(base + M.hist);
@@ -268,18 +272,6 @@ __device__ __forceinline__ void hash_insert(uint32_t* hkey, uint16_t* hidx, uint
     }
 }
 
-__device__ __forceinline__ int hash_find(const uint32_t* hkey, const uint16_t* hidx, uint32_t kbits, uint32_t w) {
-    const uint32_t mask = (1u << kbits) - 1u, key = w + 1u;
-    uint32_t b = (w * kHashMul) >> (32 - kbits);
-    for (;;) {
-        const uint2 kk = *(const uint2*)(hkey + 2 * b);
-        if (kk.x == key) return hidx[2 * b];
-        if (kk.y == key) return hidx[2 * b + 1];
-        if (kk.y == 0u) return -1;
-        b = (b + 1u) & mask;
-    }
-}
-
 // largest i in [0, cnt) with bpos[i].y <= it, given bpos[0].y <= it < bpos[cnt].y
 __device__ __forceinline__ uint32_t find_seg(const uint2* bpos, uint32_t cnt, uint32_t it) {
     uint32_t lo = 0, hi = cnt;
@@ -336,8 +328,8 @@ __device__ __forceinline__ uint32_t team_sum(uint32_t v, uint32_t* red) {
     return t;
 }
 
-// Attribute queued hits [0, qn) of this wavefront.  A hit is (B index ib, W index k, list
-// position p): the triangle (a, b = eb[ib], w = ew[k]) with times t_ab = etb[ib],
+// Attribute queued hits [0, qn) of this wavefront.  A hit is (B index ib, hash slot of the W
+// entry k, list position p): the triangle (a, b = eb[ib], w = ew[k]) with times t_ab = etb[ib],
 // t_aw = et[k], t_bw = tim[p].  Its first two edges by time decide the processor per group:
 // edges at a have their slots staged; {b, w} is hashed here.
 __device__ void drain_hits(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a, uint32_t qn) {
@@ -346,7 +338,7 @@ __device__ void drain_hits(const JobRegs& J, const TeamView& T, const WaveView& 
         const uint32_t q = q0 + lane;
         if (q < qn) {
             const uint32_t v = V.qv[q];
-            const uint32_t ib = v & 0xffffu, k = v >> 16;
+            const uint32_t ib = v & 0xffffu, k = T.hidx[v >> 16];
             const uint32_t p = V.qp[q];
             const uint32_t b = T.eb[ib], w = T.ew[k];
             const uint32_t tab = T.etb[ib], taw = T.et[k], tbw = ldg(J.tim + p);
@@ -391,53 +383,105 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Walk items [it_begin, it_end) (in windows of 64) of the staged B chunk: item `it` is entry
-// it - bpos[own].y of the list of b = eb[own], where own is the largest index with
-// bpos[own].y <= it.  Only non-empty lists are staged, so list starts are distinct: a lane's
-// owner is i0 plus the number of list starts at or before its position in the window.
+// Walk items [it_begin, it_end) of the staged B chunk, kWalk windows of 64 entries per round:
+// item `it` is entry it - bpos[own].y of the list of b = eb[own], where own is the largest
+// index with bpos[own].y <= it.  Only non-empty lists are staged, so list starts are distinct
+// and a lane's owner is i0 (the owner of the round's first item) plus the number of list
+// starts after the round's first item and at or before its own.  The owners, the neighbour
+// loads and the first hash probes of all windows of a round are issued together.
+// A hit is queued as (owner | hash slot << 16, list position).
 __device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a, uint32_t kbits,
                            uint32_t bn, uint32_t it_begin, uint32_t it_end) {
+    constexpr uint32_t R = 64 * kWalk;
     const uint32_t lane = lane_id();
+    const uint32_t bmask = (1u << kbits) - 1u;
     uint32_t qn = 0;
     if (it_begin >= it_end) return;
     uint32_t i0 = find_seg(T.bpos, bn, it_begin);  // owner of the first item (uniform)
-    for (uint32_t base = it_begin; base < it_end; base += 64) {
-        V.mark[lane] = 0;
+    for (uint32_t base = it_begin; base < it_end; base += R) {
+#pragma unroll
+        for (uint32_t j = 0; j < kWalk; ++j) V.mark[64 * j + lane] = 0;
         wave_sync();
-        const uint32_t idx = i0 + 1 + lane;
-        if (idx < bn) {
-            const uint32_t st = T.bpos[idx].y;
-            if (st < base + 64) V.mark[st - base] = 1;
+        // lists after i0 start after `base`; the ones starting inside the round are marked
+#pragma unroll
+        for (uint32_t j = 0; j < kWalk; ++j) {
+            const uint32_t idx = i0 + 1 + lane + 64 * j;
+            if (idx < bn) {
+                const uint32_t st = T.bpos[idx].y;
+                if (st < base + R) V.mark[st - base] = 1;
+            }
         }
         wave_sync();
-        const uint32_t flag = V.mark[lane];
-        const uint32_t own = i0 + lanes_below(__ballot(flag != 0)) + flag;
-        const uint32_t it = base + lane;
-        bool hit = false;
-        uint32_t p = 0, k = 0;
-        if (it < it_end) {
-            const uint2 bp = T.bpos[own];
-            p = bp.x + (it - bp.y);
-            const int kk = hash_find(T.hkey, T.hidx, kbits, ldg(J.nbr + p));
-            hit = kk >= 0;
-            k = (uint32_t)kk;
+        uint32_t own[kWalk], p[kWalk], w[kWalk];
+        bool valid[kWalk];
+        uint32_t pre = i0;
+#pragma unroll
+        for (uint32_t j = 0; j < kWalk; ++j) {
+            const uint32_t f = V.mark[64 * j + lane];
+            const uint64_t bal = __ballot(f != 0);
+            own[j] = pre + lanes_below(bal) + f;
+            pre += (uint32_t)__popcll(bal);
         }
-        const uint64_t hm = __ballot(hit);
-        if (hit) {
-            const uint32_t pos = qn + lanes_below(hm);
-            V.qv[pos] = own | (k << 16);
-            V.qp[pos] = p;
+        // pre is now the owner of the round's last item
+#pragma unroll
+        for (uint32_t j = 0; j < kWalk; ++j) {
+            const uint32_t it = base + 64 * j + lane;
+            valid[j] = it < it_end;
+            const uint2 bp = T.bpos[own[j]];
+            p[j] = bp.x + (it - bp.y);
+            w[j] = valid[j] ? ldg(J.nbr + p[j]) : 0u;
         }
-        qn += (uint32_t)__popcll(hm);
+        // first probe of every window: a 2-slot bucket; a miss goes on only past a full bucket
+        uint32_t bk[kWalk], pos[kWalk];
+        bool hit[kWalk], more[kWalk];
+        uint2 kk[kWalk];
+#pragma unroll
+        for (uint32_t j = 0; j < kWalk; ++j) {
+            bk[j] = (w[j] * kHashMul) >> (32 - kbits);
+            kk[j] = *(const uint2*)(T.hkey + 2 * bk[j]);
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kWalk; ++j) {
+            const uint32_t key = w[j] + 1u;
+            const bool m0 = kk[j].x == key, m1 = kk[j].y == key;
+            hit[j] = valid[j] && (m0 || m1);
+            pos[j] = 2 * bk[j] + (m1 ? 1u : 0u);
+            more[j] = valid[j] && !(m0 || m1) && kk[j].y != 0u;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kWalk; ++j) {
+            const uint32_t key = w[j] + 1u;
+            uint32_t b = bk[j];
+            while (more[j]) {
+                b = (b + 1u) & bmask;
+                const uint2 k2 = *(const uint2*)(T.hkey + 2 * b);
+                if (k2.x == key || k2.y == key) {
+                    hit[j] = true;
+                    pos[j] = 2 * b + (k2.y == key ? 1u : 0u);
+                    more[j] = false;
+                } else {
+                    more[j] = k2.y != 0u;
+                }
+            }
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kWalk; ++j) {
+            const uint64_t hm = __ballot(hit[j]);
+            if (hit[j]) {
+                const uint32_t q = qn + lanes_below(hm);
+                V.qv[q] = own[j] | (pos[j] << 16);
+                V.qp[q] = p[j];
+            }
+            qn += (uint32_t)__popcll(hm);
+        }
         if (qn >= 64) {
             wave_sync();
             drain_hits(J, T, V, a, qn);
             qn = 0;
         }
-        // owner of the next window's first item
-        const uint32_t last_own = __builtin_amdgcn_readlane(own, 63);
-        const uint32_t nx = last_own + 1;
-        i0 = (nx < bn && T.bpos[nx].y <= base + 64) ? nx : last_own;
+        // owner of the next round's first item
+        const uint32_t nx = pre + 1;
+        i0 = (nx < bn && T.bpos[nx].y <= base + R) ? nx : pre;
         wave_sync();
     }
     if (qn) {
@@ -458,7 +502,7 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
     const uint32_t G = J.G;
     for (uint32_t ws = 0; ws < d; ws += T.DW) {
         const uint32_t wn = (d - ws) < T.DW ? (d - ws) : T.DW;
-        const uint32_t slots = pow2_at_least(2 * wn), kbits = log2u(slots) - 1;
+        const uint32_t slots = pow2_at_least(T.tf * wn), kbits = log2u(slots) - 1;
         for (uint32_t i = tid; i < slots; i += nt) T.hkey[i] = 0;
         team_sync<BLOCK>();
         for (uint32_t i = tid; i < wn; i += nt) {
@@ -616,7 +660,8 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const uint32_t DL = hdr->wave_cap, DW = hdr->block_cap, DB = hdr->b_chunk;
     const uint32_t GM = hdr->G_max, HC = hdr->hist_c, njobs = hdr->njobs;
-    const Layout L = count_layout(nw, DL, DW, DB, GM, HC);
+    const uint32_t LT = hdr->light_table;
+    const Layout L = count_layout(nw, DL, DW, DB, GM, HC, LT);
     const WaveView V = wave_view(lds + wid * L.misc.bytes, L.misc);
     uint8_t* uni = lds + L.union_off;
     __shared__ uint32_t s_tile;
@@ -627,7 +672,7 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
 
     // phase 1: long lists, one apex per workgroup
     {
-        const TeamView T = team_view(uni, L.heavy, DW, DB);
+        const TeamView T = team_view(uni, L.heavy, DW, DB, kHeavyTable);
         const uint32_t total = hdr->heavy_total;
         for (;;) {
             if (threadIdx.x == 0) s_tile = atomicAdd(&hdr->q_heavy, 1u);
@@ -651,7 +696,7 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
 
     // phase 2: short lists, one apex per wavefront
     {
-        const TeamView T = team_view(uni + wid * L.light.bytes, L.light, DL, DL);
+        const TeamView T = team_view(uni + wid * L.light.bytes, L.light, DL, DL, LT);
         const uint32_t total = hdr->light_total, tile_len = hdr->light_tile;
         for (;;) {
             uint32_t tile = 0;
@@ -727,8 +772,8 @@ hipError_t launch_common(uint8_t* ws, const BatchHeader& h, hipStream_t s) {
 }  // namespace
 
 uint32_t rept_count_lds(uint32_t threads, uint32_t wave_cap, uint32_t block_cap, uint32_t b_chunk, uint32_t G,
-                        uint32_t hist_c) {
-    return count_layout(threads / 64, wave_cap, block_cap, b_chunk, G, hist_c).total;
+                        uint32_t hist_c, uint32_t light_table) {
+    return count_layout(threads / 64, wave_cap, block_cap, b_chunk, G, hist_c, light_table).total;
 }
 
 uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes) {
