@@ -133,17 +133,22 @@ def rept(edges, n: int, m: int, c: int, seed: int, per_proc: bool = False, t0: i
 
 
 def rept_threads(edges, n: int, m: int, c: int, seed: int, per_proc: bool = False, t0: int = 0,
-                 t1: int | None = None, workers: int = 8):
+                 t1: int | None = None, workers: int = 8, procs: tuple | None = None):
     """Algorithm 1 with the c processors split over host threads (the C replay releases the
-    GIL).  Processors are independent, so the per-thread partial counts sum to ``rept``."""
+    GIL).  Processors are independent, so the per-thread partial counts sum to ``rept``.
+    ``procs = (lo, hi)`` replays only processors lo..hi-1 (the others' counters stay 0)."""
     import concurrent.futures as cf
     e = _edges(edges)
     E = len(e)
     t1 = E if t1 is None else t1
     G = groups(m, c)
     rows = c if per_proc else G
-    workers = max(1, min(workers, c))
-    bounds = [(c * w // workers, c * (w + 1) // workers) for w in range(workers)]
+    p_lo, p_hi = (0, c) if procs is None else procs
+    if not 0 <= p_lo <= p_hi <= c:
+        raise OracleError(EINVAL, "rept_threads: processor range")
+    span = p_hi - p_lo
+    workers = max(1, min(workers, span))
+    bounds = [(p_lo + span * w // workers, p_lo + span * (w + 1) // workers) for w in range(workers)]
 
     def run(lo_hi):
         lo, hi = lo_hi

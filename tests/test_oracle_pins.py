@@ -316,3 +316,36 @@ def test_local_estimator_unbiased():
     v = int(np.argmax(tau_v))
     sd = math.sqrt(tau_v[v] * (m - 1) / R)  # Var(tau_v_hat) = tau_v (m - 1) when c = m
     assert abs(acc[v] / R - tau_v[v]) < 4 * sd
+
+
+def test_threaded_processor_ranges_partition_the_replay():
+    """Replaying disjoint processor ranges and summing gives the full replay (processors are
+    independent trials, Section III-A); a range leaves the other processors' counters at 0."""
+    e = synth.er(60, 400, 71, 72)
+    g, l = oracle.rept(e, 60, 3, 7, 99, per_proc=True)
+    parts = [oracle.rept_threads(e, 60, 3, 7, 99, per_proc=True, workers=2, procs=r) for r in [(0, 2), (2, 5), (5, 7)]]
+    assert np.array_equal(sum(p[0] for p in parts), g) and np.array_equal(sum(p[1] for p in parts), l)
+    g02, l02 = parts[0]
+    assert not g02[2:].any() and not l02[2:].any()
+
+
+def test_hash_four_wise_collision_rate_over_seeds():
+    """Theorem 3's variance needs the slots of any four distinct edges to be independent
+    (zero covariance between semi-triangles on disjoint edge pairs).  For FIXED quadruples of
+    structured edges -- consecutive keys and a shared endpoint, where weak families fail --
+    over many independent hash functions (one per group): three edges share a slot with
+    probability 1/m^2, and given that, the fourth joins them with probability 1/m.  A
+    polynomial of degree < 3 fixes the fourth value of consecutive keys by the first three,
+    which roughly triples that conditional rate at m = 16."""
+    m, G = 16, 200_000
+    quads = [np.array([[0, 1], [0, 2], [0, 3], [0, 4]], dtype=np.uint32),        # shared endpoint
+             np.array([[5, 9], [5, 10], [5, 11], [5, 12]], dtype=np.uint32),     # consecutive keys
+             np.array([[1, 2], [3, 4], [5, 6], [7, 8]], dtype=np.uint32)]        # disjoint edges
+    for q in quads:
+        s = oracle.slots(q, m, G, 4242).astype(np.int64)  # [G][4]: one hash function per row
+        three = (s[:, 1] == s[:, 0]) & (s[:, 2] == s[:, 0])
+        r3 = three.mean()
+        assert abs(r3 - 1 / m**2) < 4.5 * math.sqrt((1 / m**2) * (1 - 1 / m**2) / G), (q, r3)
+        cond = (s[three, 3] == s[three, 0]).mean()
+        k = int(three.sum())
+        assert abs(cond - 1 / m) < 4.5 * math.sqrt((1 / m) * (1 - 1 / m) / k), (q, cond, k)
