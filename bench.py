@@ -38,6 +38,11 @@ WORKLOADS = {
 HASH_SEED = 20181122
 
 
+def say(*a):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +219,7 @@ def main():
     dev = torch.device("cuda:0")
     edges = stream_for(args.workload)
     E = len(edges)
+    say(f"workload {args.workload}: n={n} E={E} m={m} c={c}")
     params = rept.Params(m, c, HASH_SEED)
     rows = params.rows
     d_edges = rept.to_device_edges(edges, dev)
@@ -260,6 +266,7 @@ def main():
     dt = time.perf_counter() - t0
     ms_per_step = 1e3 * dt / args.steps
     value = E * args.steps / dt
+    say(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, count {sum(count_ms) / len(count_ms):.3f} ms")
 
     # exact triangle count (m = 1, untimed) for the per-launch byte model
     h = rept.rept_build(n, d_edges.data_ptr(), E, persistent.data_ptr(), pbytes, scratch.data_ptr(), sbytes, sp)
@@ -314,10 +321,13 @@ def main():
         "tau_hat": tau_hat,
     }
     if not args.no_batched:
+        say("batched workload")
         out["batched"] = bench_batched(dev)
     if not args.no_served:
+        say("served workload")
         out["served"] = bench_served(dev)
     if not args.no_cpu:
+        say("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(edges, n, m, c)
     print(json.dumps(out), flush=True)
 
