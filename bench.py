@@ -232,6 +232,11 @@ def main():
     h_loc = torch.empty((rows, n), dtype=torch.int64, pin_memory=True)
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
+    # the count workspace (slot table) depends on the built graph's size: size it once
+    h = rept.rept_build(n, d_edges.data_ptr(), E, persistent.data_ptr(), pbytes, scratch.data_ptr(), sbytes, sp)
+    wbytes = max(rept.rept_count_workspace_size(h, params), rept.rept_count_workspace_size(h, rept.Params(1, 1, 0)))
+    rept.rept_destroy(h)
+    ws = torch.empty(wbytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
     count_ms = []
@@ -243,7 +248,7 @@ def main():
         t1 = time.perf_counter()  # rept_build synchronises its stream once (validation result)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
-        rept.rept_count(h, params, glob.data_ptr(), loc.data_ptr(), sp)
+        rept.rept_count(h, params, glob.data_ptr(), loc.data_ptr(), ws.data_ptr(), wbytes, sp)
         ev1.record(stream)
         h_glob.copy_(glob, non_blocking=True)
         h_loc.copy_(loc, non_blocking=True)
@@ -273,7 +278,7 @@ def main():
     p1 = rept.Params(1, 1, 0)
     g1 = torch.empty(1, dtype=torch.int64, device=dev)
     l1 = torch.empty((1, n), dtype=torch.int64, device=dev)
-    rept.rept_count(h, p1, g1.data_ptr(), l1.data_ptr(), sp)
+    rept.rept_count(h, p1, g1.data_ptr(), l1.data_ptr(), ws.data_ptr(), wbytes, sp)
     torch.cuda.synchronize()
     tau = int(g1.item())
     rept.rept_destroy(h)

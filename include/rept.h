@@ -120,15 +120,28 @@ rept_status rept_build(uint32_t n, const uint32_t* edges, uint64_t num_edges, vo
 rept_status rept_graph_get_info(const rept_graph* graph, rept_graph_info* info);
 
 /*
+ * Device bytes of the workspace of one count of `graph` under `params`: the slot table of the
+ * graph's stored edges, h_k(e) for every edge e and group k (Section III-A's hash, one per group
+ * as in Section III-B), 16 bits per slot with the groups padded to 1, 2, 4 or 8 per edge,
+ * rounded up to 256 bytes.  Host only.  Errors: EINVAL; ENOTSUP (more than 8 groups, m > 65536).
+ */
+rept_status rept_count_workspace_size(const rept_graph* graph, const rept_params* params,
+                                      size_t* bytes);
+
+/*
  * The counting pass of Algorithm 1 (Section III-A), for every processor at once: all per-edge
  * updates of the whole stream.  Overwrites the outputs (idempotent).
- *   global: device int64[c]      -- global[i] = tau^(i)
- *   local:  device int64[rows][n] -- rows = rept_local_rows(params): per group k the sum over
- *           its processors of tau_v^(i), or tau_v^(i) per processor with REPT_LOCAL_PER_PROC.
- * Asynchronous on `stream`.  Errors: EINVAL, ENOTSUP (more than 8 groups or m > 65536), EDEVICE.
+ *   global:    device int64[c]      -- global[i] = tau^(i)
+ *   local:     device int64[rows][n] -- rows = rept_local_rows(params): per group k the sum over
+ *              its processors of tau_v^(i), or tau_v^(i) per processor with REPT_LOCAL_PER_PROC.
+ *   workspace: device, >= rept_count_workspace_size bytes, 256-byte aligned; the call rewrites it
+ *              (the slot table) and reads it; it may be reused once the call's work on `stream`
+ *              has completed.
+ * Asynchronous on `stream`.  Errors: EINVAL, ENOMEM (workspace too small), ENOTSUP (more than 8
+ * groups or m > 65536), EDEVICE.
  */
 rept_status rept_count(const rept_graph* graph, const rept_params* params, int64_t* global,
-                       int64_t* local, void* stream);
+                       int64_t* local, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * The per-edge updates of the stream edges at times t in [t0, t1) only, ADDED (+=) to the
@@ -137,7 +150,8 @@ rept_status rept_count(const rept_graph* graph, const rept_params* params, int64
  * EINVAL if t0 > t1 or t1 > num_edges.
  */
 rept_status rept_count_range(const rept_graph* graph, const rept_params* params, uint64_t t0,
-                             uint64_t t1, int64_t* global, int64_t* local, void* stream);
+                             uint64_t t1, int64_t* global, int64_t* local, void* workspace,
+                             size_t workspace_bytes, void* stream);
 
 /*
  * Estimators (host, FP64).  For c <= m (Algorithm 1) and for c > m with m | c (Section III-B,
@@ -164,7 +178,9 @@ rept_status rept_hash_slots(const rept_params* params, const uint32_t* edges, ui
 /* ------------------------------------------------------------------ batched counting ------ */
 
 /* rept_job.flags */
-#define REPT_JOB_ACCUMULATE 1u /* add to the outputs instead of overwriting them */
+#define REPT_JOB_ACCUMULATE 1u  /* add to the outputs instead of overwriting them */
+#define REPT_JOB_TABLE_READY 2u /* the workspace already holds the slot table of (graph, params),
+                                   written by an earlier count or launch: do not rewrite it */
 
 /* One counting job of a batch: the updates of stream window [t0, t1) (t1 = UINT64_MAX: to
  * the end) restricted to work units [unit0, unit1) (unit1 = UINT32_MAX: all).  Work units
@@ -173,12 +189,16 @@ rept_status rept_hash_slots(const rept_params* params, const uint32_t* edges, ui
 typedef struct rept_job {
     const rept_graph* graph;
     rept_params params;
-    int64_t* global; /* device int64[c] */
-    int64_t* local;  /* device int64[rows][n] */
+    int64_t* global;          /* device int64[c] */
+    int64_t* local;           /* device int64[rows][n] */
     uint64_t t0, t1;
     uint32_t unit0, unit1;
     uint32_t flags;
     uint32_t reserved;
+    void* workspace;          /* device, >= rept_count_workspace_size(graph, params), 256-aligned;
+                                 the job's slot table (jobs of one batch may share one only if
+                                 they have the same graph and params) */
+    uint64_t workspace_bytes;
 } rept_job;
 
 /* Launch shape of the counting kernel; zero fields take the library defaults.  The kernel is

@@ -28,15 +28,23 @@ class Job:
     unit0: int = 0
     unit1: int = rept.UINT32_MAX
     accumulate: bool = False
+    workspace: object = None     # device slot table of (graph, params); allocated on demand
+    table_ready: bool = False    # the workspace already holds it (written by an earlier launch)
 
     def ensure_outputs(self):
         if self.out is None:
             self.out = self.graph.outputs(self.params)
         return self.out
 
+    def ensure_workspace(self):
+        if self.workspace is None:
+            self.workspace = self.graph.new_workspace(self.params)
+        return self.workspace
+
     def c_job(self) -> "rept.rept_job":
-        return rept.make_job(self.graph, self.params, self.ensure_outputs(), t0=self.t0, t1=self.t1,
-                             unit0=self.unit0, unit1=self.unit1, accumulate=self.accumulate)
+        return rept.make_job(self.graph, self.params, self.ensure_outputs(), self.ensure_workspace(), t0=self.t0,
+                             t1=self.t1, unit0=self.unit0, unit1=self.unit1, accumulate=self.accumulate,
+                             table_ready=self.table_ready)
 
 
 class Batch:
@@ -174,7 +182,7 @@ def run_plain(jobs: list, stream=None):
         out = j.ensure_outputs()
         full = j.t0 == 0 and j.t1 >= j.graph.num_edges and j.unit0 == 0 and j.unit1 >= j.graph.info.num_apex
         if full and not j.accumulate:
-            j.graph.count(j.params, out, stream=stream)
+            j.graph.count(j.params, out, stream=stream, workspace=j.ensure_workspace())
         else:
             raise ValueError("plain path runs whole-stream, overwriting jobs only")
 

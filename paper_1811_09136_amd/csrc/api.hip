@@ -44,6 +44,12 @@ bool params_ok(const rept_params* p) {
 
 uint32_t groups_of(const rept_params* p) { return (p->c + p->m - 1) / p->m; }
 
+// bytes of the slot table of a graph's stored edges for G groups
+size_t table_bytes(const rept_graph* g, uint32_t G) {
+    const size_t b = (size_t)g->E * rept_slot_stride(G) * sizeof(uint16_t);
+    return b < 256 ? 256 : (b + 255) & ~(size_t)255;
+}
+
 struct Shape {
     BatchHeader hdr;
 };
@@ -105,8 +111,11 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
 rept_status make_job(const rept_job& jb, JobDev* d, uint64_t* zero_words) {
     const rept_graph* g = jb.graph;
     if (!valid_graph(g) || !params_ok(&jb.params) || !jb.global || !jb.local) return REPT_EINVAL;
+    if (jb.flags & ~(REPT_JOB_ACCUMULATE | REPT_JOB_TABLE_READY)) return REPT_EINVAL;
     const uint32_t G = groups_of(&jb.params);
     if (G > REPT_GMAX || jb.params.m > 65536) return REPT_ENOTSUP;  // slots are staged as 16-bit
+    if (!jb.workspace || ((uintptr_t)jb.workspace & 255u)) return REPT_EINVAL;
+    if (jb.workspace_bytes < table_bytes(g, G)) return REPT_ENOMEM;
     memset(d, 0, sizeof(*d));
     d->off = g->off;
     d->nbr = g->nbr;
@@ -130,12 +139,16 @@ rept_status make_job(const rept_job& jb, JobDev* d, uint64_t* zero_words) {
     if (jb.unit0 > u1) return REPT_EINVAL;
     d->unit0 = jb.unit0;
     d->unit1 = u1;
+    d->gs = rept_slot_stride(G);
+    d->tab = (uint16_t*)jb.workspace;
+    d->fill = (jb.flags & REPT_JOB_TABLE_READY) ? 0u : 1u;
     *zero_words = (uint64_t)d->c + (uint64_t)d->rows * d->n;
     return REPT_OK;
 }
 
 rept_status count_one(const rept_graph* graph, const rept_params* params, uint64_t t0, uint64_t t1,
-                      bool accumulate, int64_t* global, int64_t* local, void* stream) {
+                      bool accumulate, int64_t* global, int64_t* local, void* workspace, size_t workspace_bytes,
+                      void* stream) {
     if (!valid_graph(graph) || !params_ok(params) || !global || !local) return REPT_EINVAL;
     if (t0 > t1 || t1 > graph->E) return REPT_EINVAL;
     if (groups_of(params) > REPT_GMAX || params->m > 65536) return REPT_ENOTSUP;
@@ -150,6 +163,8 @@ rept_status count_one(const rept_graph* graph, const rept_params* params, uint64
     jb.unit0 = 0;
     jb.unit1 = UINT32_MAX;
     jb.flags = accumulate ? REPT_JOB_ACCUMULATE : 0u;
+    jb.workspace = workspace;
+    jb.workspace_bytes = workspace_bytes;
     JobDev d;
     uint64_t zw = 0;
     rept_status st = make_job(jb, &d, &zw);
@@ -157,6 +172,8 @@ rept_status count_one(const rept_graph* graph, const rept_params* params, uint64
     BatchHeader h;
     st = make_header(1, d.G, d.c, graph->max_out, zw, !accumulate, nullptr, &h);
     if (st != REPT_OK) return st;
+    h.any_fill = 1;
+    h.fill_nodes = graph->n;
     if (rept_launch_single(graph->ctrl, h, d, (hipStream_t)stream) != hipSuccess) return REPT_EDEVICE;
     return REPT_OK;
 }
@@ -214,15 +231,24 @@ rept_status rept_graph_get_info(const rept_graph* g, rept_graph_info* info) {
     return REPT_OK;
 }
 
+rept_status rept_count_workspace_size(const rept_graph* graph, const rept_params* params, size_t* bytes) {
+    if (!valid_graph(graph) || !params_ok(params) || !bytes) return REPT_EINVAL;
+    const uint32_t G = groups_of(params);
+    if (G > REPT_GMAX || params->m > 65536) return REPT_ENOTSUP;
+    *bytes = table_bytes(graph, G);
+    return REPT_OK;
+}
+
 rept_status rept_count(const rept_graph* graph, const rept_params* params, int64_t* global, int64_t* local,
-                       void* stream) {
+                       void* workspace, size_t workspace_bytes, void* stream) {
     if (!valid_graph(graph)) return REPT_EINVAL;
-    return count_one(graph, params, 0, graph->E, false, global, local, stream);
+    return count_one(graph, params, 0, graph->E, false, global, local, workspace, workspace_bytes, stream);
 }
 
 rept_status rept_count_range(const rept_graph* graph, const rept_params* params, uint64_t t0, uint64_t t1,
-                             int64_t* global, int64_t* local, void* stream) {
-    return count_one(graph, params, t0, t1, true, global, local, stream);
+                             int64_t* global, int64_t* local, void* workspace, size_t workspace_bytes,
+                             void* stream) {
+    return count_one(graph, params, t0, t1, true, global, local, workspace, workspace_bytes, stream);
 }
 
 rept_status rept_estimate(uint32_t n, const rept_params* params, const int64_t* global, const int64_t* local,
@@ -306,7 +332,8 @@ rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_
     JobDev* hj = (JobDev*)(host + sizeof(BatchHeader));
     uint32_t G_max = 1, c_max = 1, max_out = 0;
     uint64_t zero_words = 0;
-    bool any_zero = false;
+    bool any_zero = false, any_fill = false;
+    uint32_t fill_nodes = 0;
     for (uint32_t j = 0; j < njobs; ++j) {
         uint64_t zw = 0;
         rept_status st = make_job(jobs[j], &hj[j], &zw);
@@ -321,6 +348,10 @@ rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_
             any_zero = true;
             zero_words = zw > zero_words ? zw : zero_words;
         }
+        if (hj[j].fill) {
+            any_fill = true;
+            fill_nodes = hj[j].n > fill_nodes ? hj[j].n : fill_nodes;
+        }
     }
     BatchHeader h;
     rept_status st = make_header(njobs, G_max, c_max, max_out, zero_words, any_zero, tuning, &h);
@@ -328,6 +359,8 @@ rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_
         free(host);
         return st;
     }
+    h.any_fill = any_fill ? 1u : 0u;
+    h.fill_nodes = fill_nodes;
     memcpy(host, &h, sizeof(h));
     hipError_t e = hipMemcpyAsync(workspace, host, bytes, hipMemcpyHostToDevice, (hipStream_t)stream);
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);  // `host` is freed below

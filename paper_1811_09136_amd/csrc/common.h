@@ -63,6 +63,9 @@ struct JobDev {
     uint32_t light_tiles;        // set by setup
     uint32_t heavy_prefix;       // exclusive prefix of heavy units over jobs (set by setup)
     uint32_t light_prefix;       // exclusive prefix of light tiles over jobs (set by setup)
+    uint32_t gs;                 // slots per stored edge in the slot table (G padded: 1, 2, 4, 8)
+    uint16_t* tab;               // slot table [E][gs]: h_k of the edge stored at each position
+    uint32_t fill;               // 1: the launch (re)writes the slot table first
     uint32_t pad[1];
 };
 
@@ -85,7 +88,9 @@ struct BatchHeader {
     uint32_t any_zero;     // some job overwrites its outputs
     uint32_t light_table;  // hash slots per key, at least, in the light phase (2 or 4)
     uint64_t zero_words;   // max words to clear over jobs
-    uint32_t pad[14];
+    uint32_t any_fill;     // some job's slot table is written by this launch
+    uint32_t fill_nodes;   // largest node count over those jobs
+    uint32_t pad[12];
 };
 
 static_assert(sizeof(BatchHeader) % 16 == 0, "header alignment");
@@ -103,6 +108,8 @@ void rept_sizes_impl(uint32_t n, uint64_t E, size_t* persistent, size_t* scratch
 hipError_t rept_launch_batch(void* ws, const BatchHeader& host_hdr, hipStream_t stream);
 hipError_t rept_launch_single(uint8_t* ctrl, const BatchHeader& hdr, const JobDev& job,
                               hipStream_t stream);
+// slots per stored edge in a slot table for G groups (1, 2, 4 or 8)
+inline uint32_t rept_slot_stride(uint32_t G) { return G <= 1 ? 1u : (G <= 2 ? 2u : (G <= 4 ? 4u : 8u)); }
 hipError_t rept_launch_slots(const uint64_t* hp, uint32_t G, uint32_t m, const uint32_t* edges,
                              uint64_t E, uint32_t* slots, hipStream_t stream);
 // LDS bytes of the counting kernel for a launch shape

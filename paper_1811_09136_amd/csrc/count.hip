@@ -110,12 +110,11 @@ __host__ __device__ inline Area area_layout(uint32_t DW, uint32_t DB, uint32_t G
     return A;
 }
 struct Misc {  // per wavefront
-    uint32_t coef, mark, qv, qp, hist, bytes;
+    uint32_t mark, qv, qp, hist, bytes;
 };
 __host__ __device__ inline Misc misc_layout(uint32_t HC) {
     Misc M;
     uint32_t p = 0;
-    M.coef = p; p = up16(p + 8 * 4 * REPT_GMAX);
     M.mark = p; p = up16(p + 64 * kWalk);  // one byte per entry of a round
     M.qv = p; p = up16(p + 4 * kQueue);
     M.qp = p; p = up16(p + 4 * kQueue);
@@ -177,7 +176,6 @@ __device__ inline TeamView team_view(uint8_t* base, const Area& A, uint32_t DW, 
     return T;
 }
 struct WaveView {
-    uint64_t* coef;
     uint8_t* mark;
     uint32_t* qv;
     uint32_t* qp;
@@ -185,7 +183,6 @@ struct WaveView {
 };
 __device__ inline WaveView wave_view(uint8_t* base, const Misc& M) {
     WaveView V;
-    V.coef = (uint64_t*)(base + M.coef);
     V.mark = base + M.mark;
     V.qv = (uint32_t*)(base + M.qv);
     V.qp = (uint32_t*)(base + M.qp);
@@ -201,7 +198,8 @@ struct JobRegs {
     const uint32_t* apex;
     int64_t* global;
     int64_t* local;
-    uint32_t n, m, c, G, per_proc, t0, t1, last_ck, use_hist;
+    const uint16_t* tab;  // slot table of the stored edges, gs slots per edge
+    uint32_t n, m, c, G, gs, per_proc, t0, t1, last_ck, use_hist;
 };
 
 __device__ inline void load_job(const JobDev* __restrict__ j, uint32_t HC, JobRegs& r) {
@@ -211,6 +209,8 @@ __device__ inline void load_job(const JobDev* __restrict__ j, uint32_t HC, JobRe
     r.apex = j->apex;
     r.global = j->global;
     r.local = j->local;
+    r.tab = j->tab;
+    r.gs = j->gs;
     r.n = j->n;
     r.m = j->m;
     r.c = j->c;
@@ -248,8 +248,29 @@ __device__ __forceinline__ void add64(int64_t* p, uint64_t v) {
 }
 
 // loads from the graph arrays (global memory: lets the compiler emit global, not flat, loads)
-__device__ __forceinline__ uint32_t ldg(const uint32_t* p) {
-    return *(const __attribute__((address_space(1))) uint32_t*)p;
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+
+// Slots of the edge stored at position p for every group, 16 bits per group: groups 0-3 in
+// `lo`, groups 4-7 in `hi`.  gs (1, 2, 4 or 8) is uniform over the wavefront.
+__device__ __forceinline__ void load_slots(const uint16_t* tab, uint32_t gs, uint32_t p, uint64_t& lo,
+                                           uint64_t& hi) {
+    hi = 0;
+    if (gs == 1) {
+        lo = ldg(tab + p);
+    } else if (gs == 2) {
+        lo = ldg((const uint32_t*)tab + p);
+    } else if (gs == 4) {
+        lo = ldg((const uint64_t*)tab + p);
+    } else {
+        lo = ldg((const uint64_t*)tab + 2 * (uint64_t)p);
+        hi = ldg((const uint64_t*)tab + 2 * (uint64_t)p + 1);
+    }
+}
+__device__ __forceinline__ uint32_t slot_in(uint64_t lo, uint64_t hi, uint32_t g) {
+    return (uint32_t)((g < 4 ? lo >> (16 * g) : hi >> (16 * (g - 4))) & 0xffffu);
 }
 
 // ---- LDS hash table of a's list: 2-slot buckets probed linearly; keys w + 1, 0 = empty.
@@ -331,7 +352,7 @@ __device__ __forceinline__ uint32_t team_sum(uint32_t v, uint32_t* red) {
 // Attribute queued hits [0, qn) of this wavefront.  A hit is (B index ib, hash slot of the W
 // entry k, list position p): the triangle (a, b = eb[ib], w = ew[k]) with times t_ab = etb[ib],
 // t_aw = et[k], t_bw = tim[p].  Its first two edges by time decide the processor per group:
-// edges at a have their slots staged; {b, w} is hashed here.
+// edges at a have their slots staged; the slots of {b, w} come from the slot table.
 __device__ void drain_hits(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a, uint32_t qn) {
     const uint32_t lane = lane_id();
     for (uint32_t q0 = 0; q0 < qn; q0 += 64) {
@@ -346,6 +367,9 @@ __device__ void drain_hits(const JobRegs& J, const TeamView& T, const WaveView& 
             const uint32_t last = (tab > taw && tab > tbw) ? 0u : (taw > tbw ? 1u : 2u);
             const uint32_t tl = last == 0 ? tab : (last == 1 ? taw : tbw);
             if (tl >= J.t0 && tl < J.t1) {
+                // slots of {b, w}, the edge at position p, when it is one of the first two
+                uint64_t blo = 0, bhi = 0;
+                if (last != 2) load_slots(J.tab, J.gs, p, blo, bhi);
                 for (uint32_t g = 0; g < J.G; ++g) {
                     const uint32_t sab = T.bslot[g * T.DB + ib], saw = T.wslot[g * T.DW + k];
                     uint32_t s1, s2;
@@ -354,7 +378,7 @@ __device__ void drain_hits(const JobRegs& J, const TeamView& T, const WaveView& 
                         s2 = saw;
                     } else {
                         s1 = last == 0 ? saw : sab;
-                        s2 = slot_of(V.coef + 4 * g, J.m, b, w);
+                        s2 = slot_in(blo, bhi, g);
                     }
                     const uint32_t ck = (g + 1 < J.G) ? J.m : J.last_ck;
                     if (s1 == s2 && s1 < ck) {
@@ -509,8 +533,10 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
             const uint32_t w = ldg(J.nbr + s + ws + i);
             T.ew[i] = w;
             T.et[i] = ldg(J.tim + s + ws + i);
+            uint64_t lo, hi;
+            load_slots(J.tab, J.gs, s + ws + i, lo, hi);
             for (uint32_t g = 0; g < G; ++g) {
-                T.wslot[g * T.DW + i] = (uint16_t)slot_of(V.coef + 4 * g, J.m, a, w);
+                T.wslot[g * T.DW + i] = (uint16_t)slot_in(lo, hi, g);
                 T.cntw[g * T.DW + i] = 0;
             }
             hash_insert(T.hkey, T.hidx, kbits, w, i);
@@ -540,9 +566,11 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                     // the edge {a, b} is also a W entry when it falls in the current W chunk
                     const uint32_t e = bs + i;
                     const bool staged = e >= ws && e < ws + wn;
+                    uint64_t lo = 0, hi = 0;
+                    if (!staged) load_slots(J.tab, J.gs, s + e, lo, hi);
                     for (uint32_t g = 0; g < G; ++g) {
                         T.bslot[g * T.DB + pos] =
-                            staged ? T.wslot[g * T.DW + (e - ws)] : (uint16_t)slot_of(V.coef + 4 * g, J.m, a, b);
+                            staged ? T.wslot[g * T.DW + (e - ws)] : (uint16_t)slot_in(lo, hi, g);
                         T.cntb[g * T.DB + pos] = 0;
                     }
                 }
@@ -653,6 +681,45 @@ __global__ void k_zero(const BatchHeader* hdr, const JobDev* jobs) {
     }
 }
 
+// Slot table of each job whose launch writes it: tab[p * gs + k] = h_k of the edge stored at
+// position p, i.e. {b, nbr[p]} for the node b whose list holds p (Section III-A's hash, one
+// independent function per group as in Section III-B).  Grid (X, njobs) of 256 threads: a
+// block takes 256 consecutive nodes, stages their offsets in LDS and hashes their entries one
+// per thread (coalesced), finding each entry's node by binary search over the offsets.
+__global__ void __launch_bounds__(256) k_fill(const JobDev* __restrict__ jobs) {
+    __shared__ uint32_t so[257];
+    const JobDev& J = jobs[blockIdx.y];
+    if (!J.fill) return;
+    const uint32_t G = J.G, gs = J.gs, m = J.m, n = J.n;
+    const uint32_t* __restrict__ off = J.off;
+    const uint32_t* __restrict__ nbr = J.nbr;
+    uint16_t* __restrict__ tab = J.tab;
+    for (uint32_t b0 = blockIdx.x * 256u; b0 < n; b0 += gridDim.x * 256u) {
+        const uint32_t cnt = (n - b0) < 256u ? (n - b0) : 256u;
+        __syncthreads();  // the previous range's offsets are no longer read
+        if (threadIdx.x < cnt) so[threadIdx.x] = off[b0 + threadIdx.x];
+        if (threadIdx.x == 0) so[cnt] = off[b0 + cnt];
+        __syncthreads();
+        const uint32_t e1 = so[cnt];
+        for (uint32_t p = so[0] + threadIdx.x; p < e1; p += 256u) {
+            uint32_t lo = 0, hi = cnt;  // so[lo] <= p < so[hi]
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (so[mid] <= p) lo = mid; else hi = mid;
+            }
+            const uint32_t b = b0 + lo, w = nbr[p];
+            uint32_t wd[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (uint32_t g = 0; g < REPT_GMAX; ++g)
+                if (g < G) wd[g >> 1] |= slot_of(J.hp + 4 * g, m, b, w) << (16 * (g & 1));
+            if (gs == 1) tab[p] = (uint16_t)wd[0];
+            else if (gs == 2) ((uint32_t*)tab)[p] = wd[0];
+            else if (gs == 4) ((uint2*)tab)[p] = make_uint2(wd[0], wd[1]);
+            else ((uint4*)tab)[p] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+        }
+    }
+}
+
 // ======================================================================= count kernel ====
 
 __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* __restrict__ jobs) {
@@ -684,7 +751,6 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
             if ((int)j != cur) {
                 flush_hist(J, V, cur);
                 load_job(jobs + j, HC, J);
-                if (lane < 4 * REPT_GMAX) V.coef[lane] = jobs[j].hp[lane];
                 cur = (int)j;
             }
             __syncthreads();
@@ -707,7 +773,6 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
             if ((int)j != cur) {
                 flush_hist(J, V, cur);
                 load_job(jobs + j, HC, J);
-                if (lane < 4 * REPT_GMAX) V.coef[lane] = jobs[j].hp[lane];
                 cur = (int)j;
                 wave_sync();
             }
@@ -764,6 +829,12 @@ hipError_t launch_common(uint8_t* ws, const BatchHeader& h, hipStream_t s) {
         if (blocks > 1024) blocks = 1024;
         if (blocks < 1) blocks = 1;
         hipLaunchKernelGGL(k_zero, dim3((uint32_t)blocks, h.njobs), dim3(256), 0, s, hdr, jobs);
+    }
+    if (h.any_fill) {
+        uint32_t blocks = (h.fill_nodes + 255) / 256;
+        if (blocks > 16384) blocks = 16384;
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL(k_fill, dim3(blocks, h.njobs), dim3(256), 0, s, jobs);
     }
     hipLaunchKernelGGL(k_count, dim3(h.blocks), dim3(h.threads), h.lds_bytes, s, hdr, jobs);
     return report(hipGetLastError(), "counting kernel launch");

@@ -22,6 +22,7 @@ REPT_OK, REPT_EINVAL, REPT_ERANGE, REPT_ESELFLOOP, REPT_EDUP, REPT_ENOMEM, REPT_
     0, -1, -2, -3, -4, -5, -6, -7
 REPT_LOCAL_PER_PROC = 1
 REPT_JOB_ACCUMULATE = 1
+REPT_JOB_TABLE_READY = 2
 UINT64_MAX = 2**64 - 1
 UINT32_MAX = 2**32 - 1
 
@@ -47,7 +48,7 @@ class rept_job(ctypes.Structure):
     _fields_ = [("graph", ctypes.c_void_p), ("params", rept_params), ("global_", ctypes.c_void_p),
                 ("local", ctypes.c_void_p), ("t0", ctypes.c_uint64), ("t1", ctypes.c_uint64),
                 ("unit0", ctypes.c_uint32), ("unit1", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("reserved", ctypes.c_uint32), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
 
 
 class rept_tuning(ctypes.Structure):
@@ -74,8 +75,9 @@ def lib() -> ctypes.CDLL:
             "rept_query_sizes": ([u32, u64, P(sz), P(sz)], i32),
             "rept_build": ([u32, vp, u64, vp, sz, vp, sz, vp, P(vp)], i32),
             "rept_graph_get_info": ([vp, P(rept_graph_info)], i32),
-            "rept_count": ([vp, P(rept_params), vp, vp, vp], i32),
-            "rept_count_range": ([vp, P(rept_params), u64, u64, vp, vp, vp], i32),
+            "rept_count_workspace_size": ([vp, P(rept_params), P(sz)], i32),
+            "rept_count": ([vp, P(rept_params), vp, vp, vp, sz, vp], i32),
+            "rept_count_range": ([vp, P(rept_params), u64, u64, vp, vp, vp, sz, vp], i32),
             "rept_estimate": ([u32, P(rept_params), vp, vp, vp, vp], i32),
             "rept_hash_slots": ([P(rept_params), vp, u64, vp, vp], i32),
             "rept_batch_workspace_size": ([u32, P(sz)], i32),
@@ -94,7 +96,8 @@ def lib() -> ctypes.CDLL:
     return _lib
 
 
-EXPORTED = ["rept_local_rows", "rept_query_sizes", "rept_build", "rept_graph_get_info", "rept_count",
+EXPORTED = ["rept_local_rows", "rept_query_sizes", "rept_build", "rept_graph_get_info",
+            "rept_count_workspace_size", "rept_count",
             "rept_count_range", "rept_estimate", "rept_hash_slots", "rept_batch_workspace_size",
             "rept_batch_prepare", "rept_batch_launch", "rept_batch_count", "rept_destroy", "rept_status_str",
             "rept_device_cus"]
@@ -162,16 +165,25 @@ def rept_graph_get_info(handle: int) -> rept_graph_info:
     return info
 
 
-def rept_count(handle: int, params: Params, global_ptr: int, local_ptr: int, stream_ptr: int | None):
+def rept_count_workspace_size(handle: int, params: Params) -> int:
     p = params.c_struct()
-    _check(lib().rept_count(handle, ctypes.byref(p), global_ptr, local_ptr, stream_ptr), "rept_count")
+    b = ctypes.c_size_t(0)
+    _check(lib().rept_count_workspace_size(handle, ctypes.byref(p), ctypes.byref(b)), "rept_count_workspace_size")
+    return b.value
 
 
-def rept_count_range(handle: int, params: Params, t0: int, t1: int, global_ptr: int, local_ptr: int,
-                     stream_ptr: int | None):
+def rept_count(handle: int, params: Params, global_ptr: int, local_ptr: int, ws_ptr: int, ws_bytes: int,
+               stream_ptr: int | None):
     p = params.c_struct()
-    _check(lib().rept_count_range(handle, ctypes.byref(p), t0, t1, global_ptr, local_ptr, stream_ptr),
-           "rept_count_range")
+    _check(lib().rept_count(handle, ctypes.byref(p), global_ptr, local_ptr, ws_ptr, ws_bytes, stream_ptr),
+           "rept_count")
+
+
+def rept_count_range(handle: int, params: Params, t0: int, t1: int, global_ptr: int, local_ptr: int, ws_ptr: int,
+                     ws_bytes: int, stream_ptr: int | None):
+    p = params.c_struct()
+    _check(lib().rept_count_range(handle, ctypes.byref(p), t0, t1, global_ptr, local_ptr, ws_ptr, ws_bytes,
+                                  stream_ptr), "rept_count_range")
 
 
 def rept_estimate(n: int, params: Params, glob: np.ndarray, loc: np.ndarray | None):
@@ -260,6 +272,7 @@ class Graph:
         del scratch
         self.info = rept_graph_get_info(self.handle)
         self._torch = torch
+        self._ws = None  # workspace shared by this graph's count / count_range calls
 
     def outputs(self, params: Params):
         torch = self._torch
@@ -267,14 +280,32 @@ class Graph:
         l = torch.empty((params.rows, self.n), dtype=torch.int64, device=self.device)
         return g, l
 
-    def count(self, params: Params, out=None, stream=None):
+    def workspace_bytes(self, params: Params) -> int:
+        return rept_count_workspace_size(self.handle, params)
+
+    def new_workspace(self, params: Params):
+        """A device workspace (slot table) for one count of this graph under `params`."""
+        return _alloc(self.workspace_bytes(params), self.device)
+
+    def _shared_workspace(self, params: Params):
+        # one buffer for the calls below, grown on demand; calls on one graph from different
+        # streams at the same time must pass their own workspaces
+        need = self.workspace_bytes(params)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = _alloc(need, self.device)
+        return self._ws
+
+    def count(self, params: Params, out=None, stream=None, workspace=None):
         g, l = self.outputs(params) if out is None else out
-        rept_count(self.handle, params, g.data_ptr(), l.data_ptr(), _stream_ptr(stream))
+        ws = self._shared_workspace(params) if workspace is None else workspace
+        rept_count(self.handle, params, g.data_ptr(), l.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(stream))
         return g, l
 
-    def count_range(self, params: Params, t0: int, t1: int, out, stream=None):
+    def count_range(self, params: Params, t0: int, t1: int, out, stream=None, workspace=None):
         g, l = out
-        rept_count_range(self.handle, params, t0, t1, g.data_ptr(), l.data_ptr(), _stream_ptr(stream))
+        ws = self._shared_workspace(params) if workspace is None else workspace
+        rept_count_range(self.handle, params, t0, t1, g.data_ptr(), l.data_ptr(), ws.data_ptr(), ws.numel(),
+                         _stream_ptr(stream))
         return g, l
 
     def close(self):
@@ -282,6 +313,7 @@ class Graph:
             rept_destroy(self.handle)
             self.handle = None
             self.persistent = None
+            self._ws = None
 
     def __del__(self):
         try:
@@ -298,11 +330,17 @@ def hash_slots(params: Params, edges_dev, stream=None):
     return out
 
 
-def make_job(graph: Graph, params: Params, out, t0: int = 0, t1: int = UINT64_MAX, unit0: int = 0,
-             unit1: int = UINT32_MAX, accumulate: bool = False) -> rept_job:
+def make_job(graph: Graph, params: Params, out, workspace, t0: int = 0, t1: int = UINT64_MAX, unit0: int = 0,
+             unit1: int = UINT32_MAX, accumulate: bool = False, table_ready: bool = False) -> rept_job:
+    """One batch job.  `workspace` (a device tensor of at least graph.workspace_bytes(params)
+    bytes, e.g. graph.new_workspace(params)) must stay alive until the launch completed; with
+    `table_ready` it already holds this (graph, params)'s slot table from an earlier launch."""
     g, l = out
-    return rept_job(graph.handle, params.c_struct(), g.data_ptr(), l.data_ptr(), t0, t1, unit0, unit1,
-                    REPT_JOB_ACCUMULATE if accumulate else 0, 0)
+    flags = (REPT_JOB_ACCUMULATE if accumulate else 0) | (REPT_JOB_TABLE_READY if table_ready else 0)
+    job = rept_job(graph.handle, params.c_struct(), g.data_ptr(), l.data_ptr(), t0, t1, unit0, unit1, flags, 0,
+                   workspace.data_ptr(), workspace.numel())
+    job._keep = (workspace, g, l)  # the struct holds raw pointers: keep the tensors alive with it
+    return job
 
 
 def tuning(wave_cap=0, block_cap=0, b_chunk=0, blocks=0, threads=0, light_tile=0) -> rept_tuning:

@@ -71,9 +71,13 @@ class DeviceExecutor:
         self._ws_jobs = 0
 
     def bytes_needed(self, req: Request) -> int:
+        """Stream + adjacency + build scratch + slot table + counters (the table's size follows
+        rept_count_workspace_size: 16 bits per group per edge, groups padded to a power of two)."""
         p, s = self.rept.rept_query_sizes(req.n, len(req.edges))
-        rows = -(-req.c // req.m)
-        return 8 * len(req.edges) + p + s + 8 * (req.c + rows * req.n)
+        G = -(-req.c // req.m)
+        gs = 1 if G <= 1 else (2 if G <= 2 else (4 if G <= 4 else 8))
+        table = max(256, -(-2 * gs * len(req.edges) // 256) * 256)
+        return 8 * len(req.edges) + p + s + table + 8 * (req.c + G * req.n)
 
     def build(self, req: Request):
         """Upload + build (blocking this worker thread; rept_build synchronises its stream)."""
@@ -85,8 +89,10 @@ class DeviceExecutor:
             out = g.outputs(params)
             out[0].zero_()
             out[1].zero_()
+            ws = g.new_workspace(params)
         self.build_stream.synchronize()
-        return {"graph": g, "params": params, "out": out, "units": g.info.num_apex, "cursor": 0}
+        return {"graph": g, "params": params, "out": out, "ws": ws, "table_ready": False,
+                "units": g.info.num_apex, "cursor": 0}
 
     def units(self, state) -> int:
         return state["units"]
@@ -94,7 +100,9 @@ class DeviceExecutor:
     def launch(self, chunks):
         """One batched launch over [(state, unit0, unit1)]; returns when it completed."""
         torch, rept = self.torch, self.rept
-        jobs = [rept.make_job(st["graph"], st["params"], st["out"], unit0=u0, unit1=u1, accumulate=True)
+        # a request's first launch writes its slot table; its later chunks reuse it
+        jobs = [rept.make_job(st["graph"], st["params"], st["out"], st["ws"], unit0=u0, unit1=u1, accumulate=True,
+                              table_ready=st["table_ready"])
                 for st, u0, u1 in chunks]
         nb = rept.rept_batch_workspace_size(len(jobs))
         if self._ws is None or self._ws.numel() < nb:
@@ -103,6 +111,8 @@ class DeviceExecutor:
         rept.rept_batch_prepare(jobs, self.tuning, self._ws.data_ptr(), self._ws.numel(), sp)
         rept.rept_batch_launch(self._ws.data_ptr(), sp)
         self.count_stream.synchronize()
+        for st, _, _ in chunks:
+            st["table_ready"] = True
 
     def finish(self, state):
         g, params, out = state["graph"], state["params"], state["out"]

@@ -31,7 +31,7 @@ def _run(cuda, edges, n, m, c, seed, per_proc=False, tune=None, window=None):
         if tune is None:
             glob, loc = g.count_range(p, t0, t1, out)
         else:
-            job = rept.make_job(g, p, out, t0=t0, t1=t1, accumulate=True)
+            job = rept.make_job(g, p, out, g.new_workspace(p), t0=t0, t1=t1, accumulate=True)
             ws = torch.empty(rept.rept_batch_workspace_size(1), dtype=torch.uint8, device=cuda)
             rept.rept_batch_count([job], tune, ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
             glob, loc = out
@@ -170,11 +170,54 @@ def test_lds_budget_rejected(cuda):
     g = rept.Graph(rept.to_device_edges(e, cuda), 100)
     p = rept.Params(3, 6, 1)
     out = g.outputs(p)
-    job = rept.make_job(g, p, out)
+    job = rept.make_job(g, p, out, g.new_workspace(p))
     ws = torch.empty(rept.rept_batch_workspace_size(1), dtype=torch.uint8, device=cuda)
     _say("LDS budget rejection")
     with pytest.raises(rept.ReptError) as ei:
         rept.rept_batch_count([job], rept.tuning(block_cap=4096, b_chunk=1024, threads=1024), ws.data_ptr(),
                               ws.numel(), None)
     assert ei.value.code == rept.REPT_EINVAL
+    g.close()
+
+
+def test_count_workspace_contract(cuda):
+    """The count workspace holds the slot table: too small -> ENOMEM, missing or misaligned ->
+    EINVAL; a batch job flagged TABLE_READY reuses the table an earlier launch wrote and gives
+    the same integers; a table written for other params is rewritten by a job without the flag."""
+    import torch
+    from paper_1811_09136_amd import rept
+    e = synth.er(400, 5000, 41, 42)
+    g = rept.Graph(rept.to_device_edges(e, cuda), 400)
+    p = rept.Params(3, 9, 77)
+    need = g.workspace_bytes(p)
+    assert need >= 2 * 4 * len(e) and need % 256 == 0  # 3 groups -> 4 slots of 16 bits per edge
+    out = g.outputs(p)
+    small = torch.empty(need - 256, dtype=torch.uint8, device=cuda)
+    _say("workspace errors")
+    with pytest.raises(rept.ReptError) as ei:
+        rept.rept_count(g.handle, p, out[0].data_ptr(), out[1].data_ptr(), small.data_ptr(), small.numel(), None)
+    assert ei.value.code == rept.REPT_ENOMEM
+    big = torch.empty(need + 512, dtype=torch.uint8, device=cuda)
+    for ptr in (0, big.data_ptr() + 8):
+        with pytest.raises(rept.ReptError) as ei:
+            rept.rept_count(g.handle, p, out[0].data_ptr(), out[1].data_ptr(), ptr, need, None)
+        assert ei.value.code == rept.REPT_EINVAL
+    og, ol = oracle.rept(e, 400, 3, 9, 77)
+    ws = g.new_workspace(p)
+    bw = torch.empty(rept.rept_batch_workspace_size(1), dtype=torch.uint8, device=cuda)
+    sp = torch.cuda.current_stream().cuda_stream
+    _say("table ready reuse")
+    for ready in (False, True, True):
+        job = rept.make_job(g, p, out, ws, table_ready=ready)
+        rept.rept_batch_count([job], None, bw.data_ptr(), bw.numel(), sp)
+        torch.cuda.synchronize()
+        assert np.array_equal(out[0].cpu().numpy(), og) and np.array_equal(out[1].cpu().numpy(), ol)
+    # the same buffer used for other params (a new seed) is rewritten when the flag is absent
+    p2 = rept.Params(3, 9, 78)
+    og2, ol2 = oracle.rept(e, 400, 3, 9, 78)
+    out2 = g.outputs(p2)
+    job = rept.make_job(g, p2, out2, ws)
+    rept.rept_batch_count([job], None, bw.data_ptr(), bw.numel(), sp)
+    torch.cuda.synchronize()
+    assert np.array_equal(out2[0].cpu().numpy(), og2) and np.array_equal(out2[1].cpu().numpy(), ol2)
     g.close()
