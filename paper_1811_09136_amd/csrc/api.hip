@@ -4,8 +4,12 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <atomic>
 #include <mutex>
+#include <thread>
 #include <unordered_map>
+#include <vector>
 
 #include "common.h"
 
@@ -267,33 +271,52 @@ rept_status rept_estimate(uint32_t n, const rept_params* params, const int64_t* 
     }
     double* tv = tau_v_hat;
     if (tv && local) {
-        // S_v summed row by row (sequential reads) into an exact int64 buffer, then scaled
+        // per node: S_v summed exactly in int64 over the rows, then one rounding for the product
+        // and one for the quotient.  Node ranges are independent, so they are split over host
+        // threads; each thread reads its range of every row (sequential within a row).
         const uint32_t rows = rept_local_rows(params);
-        int64_t* acc = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
-        if (!acc) return REPT_ENOMEM;
-        memcpy(acc, local, sizeof(int64_t) * (size_t)n);
-        bool bad = false;
-        for (uint32_t v = 0; v < n; ++v) bad |= (acc[v] < 0 || acc[v] >= limit);
-        for (uint32_t r = 1; r < rows && !bad; ++r) {
-            const int64_t* row = local + (uint64_t)r * n;
-            for (uint32_t v = 0; v < n; ++v) {
-                const int64_t x = row[v];
-                if (x < 0 || x >= limit - acc[v]) {
-                    bad = true;
-                    break;
+        std::atomic<bool> bad{false};
+        auto run = [&](uint32_t v0, uint32_t v1) {
+            constexpr uint32_t kBlock = 4096;  // nodes per pass, kept in a stack buffer
+            int64_t acc[kBlock];
+            for (uint32_t b0 = v0; b0 < v1; b0 += kBlock) {
+                const uint32_t b1 = std::min(v1, b0 + kBlock), nb = b1 - b0;
+                for (uint32_t i = 0; i < nb; ++i) {
+                    const int64_t x = local[b0 + i];
+                    if (x < 0 || x >= limit) bad = true;
+                    acc[i] = x;
                 }
-                acc[v] += x;
+                for (uint32_t r = 1; r < rows; ++r) {
+                    const int64_t* row = local + (uint64_t)r * n + b0;
+                    for (uint32_t i = 0; i < nb; ++i) {
+                        const int64_t x = row[i];
+                        if (x < 0 || x >= limit - acc[i]) {
+                            bad = true;
+                            return;
+                        }
+                        acc[i] += x;
+                    }
+                }
+                if (bad) return;
+                for (uint32_t i = 0; i < nb; ++i) {
+                    const double prod = (double)acc[i] * num;
+                    tv[b0 + i] = prod / den;
+                }
             }
+        };
+        const uint64_t work = (uint64_t)rows * n;
+        uint32_t nt = work < (1u << 20) ? 1u : std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+        if (nt <= 1) {
+            run(0, n);
+        } else {
+            std::vector<std::thread> pool;
+            for (uint32_t t = 0; t < nt; ++t) {
+                const uint32_t v0 = (uint32_t)((uint64_t)n * t / nt), v1 = (uint32_t)((uint64_t)n * (t + 1) / nt);
+                pool.emplace_back(run, v0, v1);
+            }
+            for (auto& th : pool) th.join();
         }
-        if (bad) {
-            free(acc);
-            return REPT_ERANGE;
-        }
-        for (uint32_t v = 0; v < n; ++v) {
-            const double prod = (double)acc[v] * num;
-            tv[v] = prod / den;
-        }
-        free(acc);
+        if (bad) return REPT_ERANGE;
     }
     const double prod = (double)S * num;
     *tau_hat = prod / den;

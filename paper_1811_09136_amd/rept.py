@@ -186,8 +186,9 @@ def rept_count_range(handle: int, params: Params, t0: int, t1: int, global_ptr: 
                                   stream_ptr), "rept_count_range")
 
 
-def rept_estimate(n: int, params: Params, glob: np.ndarray, loc: np.ndarray | None):
-    """Host FP64 estimators; returns (tau_hat, tau_v_hat or None)."""
+def rept_estimate(n: int, params: Params, glob: np.ndarray, loc: np.ndarray | None, tau_v_out=None):
+    """Host FP64 estimators; returns (tau_hat, tau_v_hat or None).  `tau_v_out` (float64[n])
+    receives the local estimators when given (no allocation per call)."""
     p = params.c_struct()
     g = np.ascontiguousarray(glob, dtype=np.int64)
     th = ctypes.c_double(0.0)
@@ -195,7 +196,12 @@ def rept_estimate(n: int, params: Params, glob: np.ndarray, loc: np.ndarray | No
     lp = None
     if loc is not None:
         lo = np.ascontiguousarray(loc, dtype=np.int64)
-        tv = np.zeros(n, dtype=np.float64)
+        if tau_v_out is None:
+            tv = np.empty(n, dtype=np.float64)
+        else:
+            tv = tau_v_out
+            if tv.dtype != np.float64 or tv.shape != (n,) or not tv.flags.c_contiguous:
+                raise ValueError("tau_v_out must be a contiguous float64 array of n values")
         lp = lo.ctypes.data
     _check(lib().rept_estimate(n, ctypes.byref(p), g.ctypes.data, lp, ctypes.addressof(th),
                                None if tv is None else tv.ctypes.data), "rept_estimate")

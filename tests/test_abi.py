@@ -75,3 +75,31 @@ def test_estimate_errors_match_oracle():
     with pytest.raises(rept.ReptError) as ei:
         rept.rept_estimate(2, rept.Params(2, 2, 0), np.array([1, 1]), np.array([[2**52, 1]], np.int64) * 0 + np.array([[-1, 0]]))
     assert ei.value.code == rept.REPT_ERANGE
+
+
+def test_estimate_large_zero_ulp_and_range_errors():
+    """The local estimators at a size split over host threads (rows x n >= 2^20): 0 ulp against
+    the oracle; an out-of-range value anywhere (a late row, the last node) is ERANGE."""
+    from paper_1811_09136_amd import rept
+    rng = np.random.default_rng(7)
+    n, m, c = 300_001, 10, 40
+    glob = rng.integers(0, 2**36, size=c)
+    loc = rng.integers(0, 2**40, size=(4, n))
+    th, tv = rept.rept_estimate(n, rept.Params(m, c, 0), glob, loc)
+    oth, otv = oracle.estimate(n, m, c, glob, loc)
+    assert th == oth and np.array_equal(tv.view(np.uint64), otv.view(np.uint64))
+    out = np.full(n, np.nan)
+    th2, tv2 = rept.rept_estimate(n, rept.Params(m, c, 0), glob, loc, out)
+    assert tv2 is out and th2 == oth and np.array_equal(out.view(np.uint64), otv.view(np.uint64))
+    for r, v, val in [(3, n - 1, -1), (2, n // 2, 2**53), (0, 5, 2**53)]:
+        bad = loc.copy()
+        bad[r, v] = val
+        with pytest.raises(rept.ReptError) as ei:
+            rept.rept_estimate(n, rept.Params(m, c, 0), glob, bad)
+        assert ei.value.code == rept.REPT_ERANGE
+    # row sums that only overflow 2^53 together
+    over = np.zeros((4, n), np.int64)
+    over[:, 123] = 2**51
+    with pytest.raises(rept.ReptError) as ei:
+        rept.rept_estimate(n, rept.Params(m, c, 0), glob, over)
+    assert ei.value.code == rept.REPT_ERANGE
