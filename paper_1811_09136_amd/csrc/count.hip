@@ -499,9 +499,24 @@ __device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& 
             qn += (uint32_t)__popcll(hm);
         }
         if (qn >= 64) {
+            // drain whole batches of 64 and keep the rest (fewer than 64) for the next rounds
             wave_sync();
-            drain_hits(J, T, V, a, qn);
-            qn = 0;
+            const uint32_t full = qn & ~63u, rem = qn - full;
+            drain_hits(J, T, V, a, full);
+            if (rem) {
+                uint32_t v = 0, pp = 0;
+                if (lane < rem) {
+                    v = V.qv[full + lane];
+                    pp = V.qp[full + lane];
+                }
+                wave_sync();
+                if (lane < rem) {
+                    V.qv[lane] = v;
+                    V.qp[lane] = pp;
+                }
+                wave_sync();
+            }
+            qn = rem;
         }
         // owner of the next round's first item
         const uint32_t nx = pre + 1;
