@@ -541,7 +541,9 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
     const uint32_t G = J.G;
     for (uint32_t ws = 0; ws < d; ws += T.DW) {
         const uint32_t wn = (d - ws) < T.DW ? (d - ws) : T.DW;
-        const uint32_t slots = pow2_at_least(T.tf * wn), kbits = log2u(slots) - 1;
+        // the whole table (sized for DW keys) is used whatever wn is: a sparser table ends more
+        // probes at their first bucket
+        const uint32_t slots = pow2_at_least(T.tf * T.DW), kbits = log2u(slots) - 1;
         for (uint32_t i = tid; i < slots; i += nt) T.hkey[i] = 0;
         team_sync<BLOCK>();
         for (uint32_t i = tid; i < wn; i += nt) {
