@@ -125,6 +125,9 @@ rept_status make_job(const rept_job& jb, JobDev* d, uint64_t* zero_words) {
     d->nbr = g->nbr;
     d->tim = g->tim;
     d->apex = g->apex;
+    d->roff = g->roff;
+    d->rnode = g->rnode;
+    d->rpos = g->rpos;
     d->global = jb.global;
     d->local = jb.local;
     group_params(jb.params.seed, G, d->hp);

@@ -257,10 +257,56 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scatter(const uint2* __restric
         uint32_t a = xa ? e.x : e.y, b = xa ? e.y : e.x;
         uint32_t pos = off[a] + atomicAdd(&cursor[a], 1u);
         packed[pos] = ((unsigned long long)b << 32) | (uint32_t)t;
-        work += dout[b];
+        // the counting pass walks the shorter out-list of the pair (see k_rev)
+        work += dout[b] <= dout[a] ? dout[b] : dout[a];
     }
     unsigned long long s = block_reduce_sum256<unsigned long long>(work);
     if (threadIdx.x == 0 && s) atomicAdd(&st->work, s);
+}
+
+// Reverse lists.  The counting pass finds a triangle from its lowest-ranked oriented pair
+// a -> b by walking the shorter of out(a), out(b) against a hash of the other.  Pairs with
+// out(a) shorter are counted at b: rev(b) lists them as (a, position of b in a's list).
+// Hubs receive many such pairs, so each target's list is cut into REV_SHARDS shards (by a mod
+// REV_SHARDS) with a counter each: a hub's increments spread over that many addresses.  Both
+// passes visit every stored entry once: a block takes 256 consecutive nodes, stages their
+// offsets in LDS and finds each entry's node by binary search.
+constexpr uint32_t REV_SHARDS = 8;
+template <bool SCATTER>
+__global__ void __launch_bounds__(256) k_rev(const uint32_t* __restrict__ off, const uint32_t* __restrict__ nbr,
+                                             uint32_t n, uint32_t* cnt, const uint32_t* __restrict__ sofs,
+                                             uint32_t* __restrict__ rnode, uint32_t* __restrict__ rpos) {
+    __shared__ uint32_t so[257];
+    for (uint32_t b0 = blockIdx.x * 256u; b0 < n; b0 += gridDim.x * 256u) {
+        const uint32_t c = (n - b0) < 256u ? (n - b0) : 256u;
+        __syncthreads();
+        if (threadIdx.x < c) so[threadIdx.x] = off[b0 + threadIdx.x];
+        if (threadIdx.x == 0) so[c] = off[b0 + c];
+        __syncthreads();
+        const uint32_t e1 = so[c];
+        for (uint32_t p = so[0] + threadIdx.x; p < e1; p += 256u) {
+            uint32_t lo = 0, hi = c;  // so[lo] <= p < so[hi]
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (so[mid] <= p) lo = mid; else hi = mid;
+            }
+            const uint32_t a = b0 + lo, b = nbr[p];
+            if (so[lo + 1] - so[lo] < off[b + 1] - off[b]) {
+                const uint64_t sh = (uint64_t)b * REV_SHARDS + (a % REV_SHARDS);
+                const uint32_t k = atomicAdd(&cnt[sh], 1u);
+                if (SCATTER) {
+                    rnode[sofs[sh] + k] = a;
+                    rpos[sofs[sh] + k] = p;
+                }
+            }
+        }
+    }
+}
+
+// roff[b] = start of b's first shard (roff[n] = the number of pairs)
+__global__ void k_rev_roff(const uint32_t* __restrict__ sofs, uint32_t n, uint32_t* __restrict__ roff) {
+    for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b <= n; b += gridDim.x * blockDim.x)
+        roff[b] = sofs[(uint64_t)b * REV_SHARDS];
 }
 
 // Out-degrees below APEX_LDS_BINS are histogrammed per workgroup in LDS (the common small
@@ -502,10 +548,10 @@ __global__ void __launch_bounds__(64) k_sort_large(const uint32_t* __restrict__ 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t ctrl, off, nbr, tim, apex, total;
+    size_t ctrl, off, nbr, tim, apex, roff, rnode, rpos, total;
 };
 struct ScratchLayout {
-    size_t stats, deg, dout, cursor, ahist, aoff, part, packed, alt, medium, large, bhist, bscan, total;
+    size_t stats, deg, dout, cursor, ahist, aoff, part, packed, alt, medium, large, bhist, bscan, scnt, sofs, total;
 };
 
 // partition of endpoints for the degree count: buckets of 2^shift ids, NB <= DEG_BUCKETS of
@@ -540,6 +586,12 @@ Layout persistent_layout(uint32_t n, uint64_t E) {
     p += align256((size_t)E * 4);
     L.apex = p;
     p += align256((size_t)n * 4);
+    L.roff = p;
+    p += align256(((size_t)n + 1) * 4);
+    L.rnode = p;
+    p += align256((size_t)E * 4);
+    L.rpos = p;
+    p += align256((size_t)E * 4);
     L.total = p;
     return L;
 }
@@ -548,8 +600,8 @@ ScratchLayout scratch_layout(uint32_t n, uint64_t E) {
     ScratchLayout S;
     size_t p = 0;
     const DegPlan D = deg_plan(n, E);
-    const size_t nhist = (size_t)D.NB * D.nblk;
-    const size_t scan_max = (nhist > (size_t)n ? nhist : (size_t)n) + 1;
+    const size_t nhist = (size_t)D.NB * D.nblk, nshard = (size_t)n * REV_SHARDS;
+    const size_t scan_max = (nhist > nshard ? nhist : nshard) + 1;
     const size_t nparts = (scan_max + SCAN_TILE - 1) / SCAN_TILE + 1;
     S.stats = p;
     p += align256(sizeof(BuildStats));
@@ -577,6 +629,10 @@ ScratchLayout scratch_layout(uint32_t n, uint64_t E) {
     p += align256(nhist * 4);
     S.bscan = p;
     p += align256((nhist + 1) * 4);
+    S.scnt = p;  // reverse-list shard counters (then cursors)
+    p += align256(nshard * 4);
+    S.sofs = p;  // their exclusive scan
+    p += align256((nshard + 1) * 4);
     S.total = p;
     return S;
 }
@@ -616,6 +672,9 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     uint32_t* nbr = (uint32_t*)(P + L.nbr);
     uint32_t* tim = (uint32_t*)(P + L.tim);
     uint32_t* apex = (uint32_t*)(P + L.apex);
+    uint32_t* roff = (uint32_t*)(P + L.roff);
+    uint32_t* rnode = (uint32_t*)(P + L.rnode);
+    uint32_t* rpos = (uint32_t*)(P + L.rpos);
     BuildStats* st = (BuildStats*)(X + S.stats);
     uint32_t* deg = (uint32_t*)(X + S.deg);
     uint32_t* dout = (uint32_t*)(X + S.dout);
@@ -629,6 +688,8 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     uint32_t* large = (uint32_t*)(X + S.large);
     uint32_t* bhist = (uint32_t*)(X + S.bhist);
     uint32_t* bscan = (uint32_t*)(X + S.bscan);
+    uint32_t* scnt = (uint32_t*)(X + S.scnt);
+    uint32_t* sofs = (uint32_t*)(X + S.sofs);
     const uint2* e2 = (const uint2*)edges;
 
     const uint32_t cus = rept_num_cus();
@@ -669,6 +730,16 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     if (scan_u32(ahist, n, part, aoff, s) != hipSuccess) return REPT_EDEVICE;
     hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, cursor, (uint64_t)n, 0u);
     hipLaunchKernelGGL(k_apex_scatter, dim3(gA), dim3(256), 0, s, off, n, aoff, cursor, apex);
+    // reverse lists: count per target shard, scan, scatter
+    const uint64_t nsh = (uint64_t)n * REV_SHARDS;
+    const uint32_t gR = grid_for(n, 256, 16384), gS = grid_for(nsh, 256, cap);
+    hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
+    hipLaunchKernelGGL(k_rev<false>, dim3(gR), dim3(256), 0, s, off, nbr, n, scnt, (const uint32_t*)nullptr,
+                       (uint32_t*)nullptr, (uint32_t*)nullptr);
+    if (scan_u32(scnt, nsh, part, sofs, s) != hipSuccess) return REPT_EDEVICE;
+    hipLaunchKernelGGL(k_rev_roff, dim3(gN), dim3(256), 0, s, sofs, n, roff);
+    hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
+    hipLaunchKernelGGL(k_rev<true>, dim3(gR), dim3(256), 0, s, off, nbr, n, scnt, sofs, rnode, rpos);
     if (hipGetLastError() != hipSuccess) return REPT_EDEVICE;
 
     BuildStats hs;
@@ -688,6 +759,9 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     g->nbr = nbr;
     g->tim = tim;
     g->apex = apex;
+    g->roff = roff;
+    g->rnode = rnode;
+    g->rpos = rpos;
     g->num_apex = hs.num_apex;
     g->max_out = hs.max_out;
     g->work = hs.work;

@@ -24,7 +24,7 @@ struct BuildStats {
     uint32_t n_medium;  // segments sorted by a workgroup in LDS
     uint32_t n_large;   // segments sorted by a workgroup in global memory
     uint32_t pad[3];
-    unsigned long long work;        // sum over oriented edges a->b of outdeg(b)
+    unsigned long long work;        // sum over oriented edges a->b of min(outdeg(a), outdeg(b))
     unsigned long long sum_out_sq;  // sum over nodes of outdeg^2
 };
 
@@ -38,6 +38,9 @@ struct rept_graph {
     const uint32_t* nbr; // [E] higher-ranked neighbour ids, sorted within each segment
     const uint32_t* tim; // [E] arrival time of that edge
     const uint32_t* apex;// [num_apex] nodes with outdeg >= 2, by outdeg descending
+    const uint32_t* roff;  // [n+1] reverse lists: pairs a -> b with outdeg(a) < outdeg(b), at b
+    const uint32_t* rnode; // [.] a
+    const uint32_t* rpos;  // [.] position of b in a's list
     uint32_t num_apex;
     uint32_t max_out;
     uint64_t work;
@@ -50,6 +53,9 @@ struct JobDev {
     const uint32_t* nbr;
     const uint32_t* tim;
     const uint32_t* apex;
+    const uint32_t* roff;
+    const uint32_t* rnode;
+    const uint32_t* rpos;
     int64_t* global;
     int64_t* local;
     uint64_t hp[4 * REPT_GMAX];  // polynomial hash coefficients (a0, a1, a2, a3) per group
@@ -66,7 +72,7 @@ struct JobDev {
     uint32_t gs;                 // slots per stored edge in the slot table (G padded: 1, 2, 4, 8)
     uint16_t* tab;               // slot table [E][gs]: h_k of the edge stored at each position
     uint32_t fill;               // 1: the launch (re)writes the slot table first
-    uint32_t pad[1];
+    uint32_t pad[3];
 };
 
 // Batch header, followed in memory by JobDev[njobs].

@@ -196,6 +196,9 @@ struct JobRegs {
     const uint32_t* nbr;
     const uint32_t* tim;
     const uint32_t* apex;
+    const uint32_t* roff;
+    const uint32_t* rnode;
+    const uint32_t* rpos;
     int64_t* global;
     int64_t* local;
     const uint16_t* tab;  // slot table of the stored edges, gs slots per edge
@@ -207,6 +210,9 @@ __device__ inline void load_job(const JobDev* __restrict__ j, uint32_t HC, JobRe
     r.nbr = j->nbr;
     r.tim = j->tim;
     r.apex = j->apex;
+    r.roff = j->roff;
+    r.rnode = j->rnode;
+    r.rpos = j->rpos;
     r.global = j->global;
     r.local = j->local;
     r.tab = j->tab;
@@ -538,6 +544,7 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
     const uint32_t tid = BLOCK ? threadIdx.x : lane_id();
     const uint32_t nw = nt >> 6, wid = BLOCK ? (threadIdx.x >> 6) : 0;
     const uint32_t s = J.off[a], d = J.off[a + 1] - s;
+    const uint32_t r0 = J.roff[a], nbtot = d + (J.roff[a + 1] - r0);
     const uint32_t G = J.G;
     for (uint32_t ws = 0; ws < d; ws += T.DW) {
         const uint32_t wn = (d - ws) < T.DW ? (d - ws) : T.DW;
@@ -559,19 +566,31 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
             hash_insert(T.hkey, T.hidx, kbits, w, i);
         }
         team_sync<BLOCK>();
-        for (uint32_t bs = 0; bs < d; bs += T.DB) {
-            const uint32_t braw = (d - bs) < T.DB ? (d - bs) : T.DB;
-            // stage the non-empty lists of this chunk: compact by a scan of "non-empty", then
-            // scan their lengths
+        // B entries: first a's own pairs a -> b whose out(b) is not longer than out(a) (walk
+        // out(b)), then the reverse pairs y -> a with out(y) shorter than out(a) (walk out(y)):
+        // every triangle is found once, from its lowest pair, walking the shorter list
+        for (uint32_t bs = 0; bs < nbtot; bs += T.DB) {
+            const uint32_t braw = (nbtot - bs) < T.DB ? (nbtot - bs) : T.DB;
+            // stage the lists to walk in this chunk: compact by a scan of "walked", then scan
+            // their lengths
             uint32_t nb = 0, items = 0;
             for (uint32_t c0 = 0; c0 < braw; c0 += nt) {
                 const uint32_t i = c0 + tid;
-                uint32_t b = 0, bo = 0, bd = 0, tb = 0;
+                uint32_t b = 0, bo = 0, bd = 0, tb = 0, pab = 0;
+                const uint32_t e = bs + i;  // B entry index
                 if (i < braw) {
-                    b = ldg(J.nbr + s + bs + i);
-                    tb = ldg(J.tim + s + bs + i);
+                    if (e < d) {
+                        pab = s + e;
+                        b = ldg(J.nbr + pab);
+                    } else {
+                        const uint32_t q = r0 + (e - d);
+                        b = ldg(J.rnode + q);
+                        pab = ldg(J.rpos + q);
+                    }
+                    tb = ldg(J.tim + pab);
                     bo = ldg(J.off + b);
                     bd = ldg(J.off + b + 1) - bo;
+                    if (e < d && bd > d) bd = 0;  // out(a) is shorter: counted at b
                 }
                 uint32_t tot_nb, tot_items;
                 const uint32_t pos = nb + team_excl_scan<BLOCK>(bd ? 1u : 0u, T.red, tot_nb);
@@ -580,11 +599,10 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                     T.eb[pos] = b;
                     T.etb[pos] = tb;
                     T.bpos[pos] = make_uint2(bo, sc);
-                    // the edge {a, b} is also a W entry when it falls in the current W chunk
-                    const uint32_t e = bs + i;
+                    // an own pair {a, b} is also a W entry when it falls in the current W chunk
                     const bool staged = e >= ws && e < ws + wn;
                     uint64_t lo = 0, hi = 0;
-                    if (!staged) load_slots(J.tab, J.gs, s + e, lo, hi);
+                    if (!staged) load_slots(J.tab, J.gs, pab, lo, hi);
                     for (uint32_t g = 0; g < G; ++g) {
                         T.bslot[g * T.DB + pos] =
                             staged ? T.wslot[g * T.DW + (e - ws)] : (uint16_t)slot_in(lo, hi, g);
