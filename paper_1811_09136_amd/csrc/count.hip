@@ -369,13 +369,14 @@ __device__ void drain_hits(const JobRegs& J, const TeamView& T, const WaveView& 
             const uint32_t p = V.qp[q];
             const uint32_t b = T.eb[ib], w = T.ew[k];
             const uint32_t tab = T.etb[ib], taw = T.et[k], tbw = ldg(J.tim + p);
+            // slots of {b, w}, the edge at position p; loaded with its time (one latency), used
+            // when it is one of the first two edges
+            uint64_t blo, bhi;
+            load_slots(J.tab, J.gs, p, blo, bhi);
             // which edge arrived last: 0 = {a,b}, 1 = {a,w}, 2 = {b,w} (times are distinct)
             const uint32_t last = (tab > taw && tab > tbw) ? 0u : (taw > tbw ? 1u : 2u);
             const uint32_t tl = last == 0 ? tab : (last == 1 ? taw : tbw);
             if (tl >= J.t0 && tl < J.t1) {
-                // slots of {b, w}, the edge at position p, when it is one of the first two
-                uint64_t blo = 0, bhi = 0;
-                if (last != 2) load_slots(J.tab, J.gs, p, blo, bhi);
                 for (uint32_t g = 0; g < J.G; ++g) {
                     const uint32_t sab = T.bslot[g * T.DB + ib], saw = T.wslot[g * T.DW + k];
                     uint32_t s1, s2;
