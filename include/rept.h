@@ -77,7 +77,8 @@ typedef struct rept_graph_info {
     uint64_t num_edges;     /* stream edges */
     uint32_t num_apex;      /* nodes with at least two higher-ranked neighbours */
     uint32_t max_out_degree;/* largest oriented out-degree */
-    uint64_t oriented_work; /* sum over oriented edges (a->b) of outdeg(b): entries the count reads */
+    uint64_t oriented_work; /* sum over oriented edges (a->b) of min(outdeg(a), outdeg(b)): list
+                               entries the count probes (it walks the shorter list of each pair) */
     uint64_t sum_out_sq;    /* sum over nodes of outdeg^2 */
 } rept_graph_info;
 
@@ -88,8 +89,8 @@ uint32_t rept_local_rows(const rept_params* params);
 
 /*
  * Device bytes needed to build a graph of n nodes and num_edges stream edges.
- *   persistent_bytes: kept by the built graph (oriented adjacency: 8 bytes per edge plus
- *                     8 bytes per node, rounded up);
+ *   persistent_bytes: kept by the built graph (oriented adjacency and reverse lists: 16 bytes
+ *                     per edge plus 12 bytes per node, rounded up);
  *   scratch_bytes:    needed only during rept_build.
  * Host only, no device work.  EINVAL if n == 0, n > 2^29 or num_edges >= 2^31.
  */
@@ -100,7 +101,9 @@ rept_status rept_query_sizes(uint32_t n, uint64_t num_edges, size_t* persistent_
  * Validate the stream (Section II: a simple undirected graph) and build the device data the
  * counting pass reads: every edge oriented from its lower- to its higher-ranked endpoint
  * (rank = (degree, id)), grouped by the lower endpoint and sorted by neighbour id, with each
- * entry holding (neighbour id, arrival time t).
+ * entry holding (neighbour id, arrival time t); and, for each node b, the reverse list of the
+ * pairs a -> b whose out-list of a is shorter than b's (the counting pass walks the shorter list
+ * of every pair).
  *
  * edges:      device, uint32[num_edges][2], read only, not retained after return.
  * persistent: device, >= persistent_bytes from rept_query_sizes, 256-byte aligned; owned by the
