@@ -91,12 +91,15 @@ def traffic_from_profile(workload: str):
 
 
 def algorithmic_bytes(info, tau: int, c: int, rows: int, n: int) -> float:
-    """Bytes the counting pass must move per launch (per-unit model of the recast):
-    16 B per oriented edge staged at its apex (neighbour id, arrival time, the neighbour's two
-    offsets), 12 B per apex (id and its two offsets), 4 B per list entry probed (neighbour id),
-    4 B per triangle found (arrival time of its third edge), 8 B per output counter."""
+    """Bytes the counting pass must move per launch (per-unit model of the recast): per oriented
+    edge 8 B staged in its unit's hash table (neighbour id, arrival time) and 16 B staged as a list
+    to walk (node id, arrival time, that node's two offsets), 4 B more when it comes from a reverse
+    list (its position); 20 B per unit (id, two offsets, two reverse-list offsets); 4 B per list
+    entry probed (neighbour id); 4 B per triangle found (arrival time of the walked edge); 8 B per
+    output counter."""
     E = info.num_edges
-    return 16.0 * E + 12.0 * info.num_apex + 4.0 * info.oriented_work + 4.0 * tau + 8.0 * (c + rows * n)
+    return (24.0 * E + 4.0 * info.num_reverse + 20.0 * info.num_apex + 4.0 * info.oriented_work + 4.0 * tau
+            + 8.0 * (c + rows * n))
 
 
 def streaming_model_bytes(deg_sq_half_sum: int, E: int, groups: int, semi: int, c: int, n: int) -> float:
@@ -344,7 +347,7 @@ def main():
                      "traffic": traffic},
         "kernel": {"count_ms": avg_count_ms, "count_kernel_ms": avg_kernel_ms, "build_ms": float(np.mean(build_ms)),
                    "count_edges_per_s": E / (avg_count_ms * 1e-3), "algorithmic_bytes": alg,
-                   "oriented_work": int(info.oriented_work), "triangles": tau, "semi_triangles": semi,
+                   "oriented_work": int(info.oriented_work), "num_reverse": int(info.num_reverse), "triangles": tau, "semi_triangles": semi,
                    "streaming_model_bytes": sm_bytes,
                    "streaming_model_equiv_gbps": sm_bytes / (avg_kernel_ms * 1e-3) / 1e9,
                    "source_digest": count_kernel_source_digest()},

@@ -80,6 +80,7 @@ typedef struct rept_graph_info {
     uint64_t oriented_work; /* sum over oriented edges (a->b) of min(outdeg(a), outdeg(b)): list
                                entries the count probes (it walks the shorter list of each pair) */
     uint64_t sum_out_sq;    /* sum over nodes of outdeg^2 */
+    uint64_t num_reverse;   /* pairs in the reverse lists (counted from the longer list's side) */
 } rept_graph_info;
 
 /* Number of local-counter rows for `params`: G = ceil(c/m), or c with REPT_LOCAL_PER_PROC.

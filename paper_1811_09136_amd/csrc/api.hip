@@ -235,6 +235,7 @@ rept_status rept_graph_get_info(const rept_graph* g, rept_graph_info* info) {
     info->max_out_degree = g->max_out;
     info->oriented_work = g->work;
     info->sum_out_sq = g->sum_out_sq;
+    info->num_reverse = g->num_rev;
     return REPT_OK;
 }
 

@@ -304,9 +304,12 @@ __global__ void __launch_bounds__(256) k_rev(const uint32_t* __restrict__ off, c
 }
 
 // roff[b] = start of b's first shard (roff[n] = the number of pairs)
-__global__ void k_rev_roff(const uint32_t* __restrict__ sofs, uint32_t n, uint32_t* __restrict__ roff) {
-    for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b <= n; b += gridDim.x * blockDim.x)
+__global__ void k_rev_roff(const uint32_t* __restrict__ sofs, uint32_t n, uint32_t* __restrict__ roff,
+                           BuildStats* st) {
+    for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b <= n; b += gridDim.x * blockDim.x) {
         roff[b] = sofs[(uint64_t)b * REV_SHARDS];
+        if (b == n) st->num_rev = roff[b];
+    }
 }
 
 // Out-degrees below APEX_LDS_BINS are histogrammed per workgroup in LDS (the common small
@@ -737,7 +740,7 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     hipLaunchKernelGGL(k_rev<false>, dim3(gR), dim3(256), 0, s, off, nbr, n, scnt, (const uint32_t*)nullptr,
                        (uint32_t*)nullptr, (uint32_t*)nullptr);
     if (scan_u32(scnt, nsh, part, sofs, s) != hipSuccess) return REPT_EDEVICE;
-    hipLaunchKernelGGL(k_rev_roff, dim3(gN), dim3(256), 0, s, sofs, n, roff);
+    hipLaunchKernelGGL(k_rev_roff, dim3(gN), dim3(256), 0, s, sofs, n, roff, st);
     hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
     hipLaunchKernelGGL(k_rev<true>, dim3(gR), dim3(256), 0, s, off, nbr, n, scnt, sofs, rnode, rpos);
     if (hipGetLastError() != hipSuccess) return REPT_EDEVICE;
@@ -764,6 +767,7 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     g->rpos = rpos;
     g->num_apex = hs.num_apex;
     g->max_out = hs.max_out;
+    g->num_rev = hs.num_rev;
     g->work = hs.work;
     g->sum_out_sq = hs.sum_out_sq;
     *out = g;

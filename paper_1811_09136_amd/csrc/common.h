@@ -23,7 +23,8 @@ struct BuildStats {
     uint32_t max_out;
     uint32_t n_medium;  // segments sorted by a workgroup in LDS
     uint32_t n_large;   // segments sorted by a workgroup in global memory
-    uint32_t pad[3];
+    uint32_t num_rev;   // pairs in the reverse lists
+    uint32_t pad[2];
     unsigned long long work;        // sum over oriented edges a->b of min(outdeg(a), outdeg(b))
     unsigned long long sum_out_sq;  // sum over nodes of outdeg^2
 };
@@ -43,6 +44,7 @@ struct rept_graph {
     const uint32_t* rpos;  // [.] position of b in a's list
     uint32_t num_apex;
     uint32_t max_out;
+    uint32_t num_rev;
     uint64_t work;
     uint64_t sum_out_sq;
 };

@@ -41,7 +41,7 @@ class rept_params(ctypes.Structure):
 class rept_graph_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("num_edges", ctypes.c_uint64), ("num_apex", ctypes.c_uint32),
                 ("max_out_degree", ctypes.c_uint32), ("oriented_work", ctypes.c_uint64),
-                ("sum_out_sq", ctypes.c_uint64)]
+                ("sum_out_sq", ctypes.c_uint64), ("num_reverse", ctypes.c_uint64)]
 
 
 class rept_job(ctypes.Structure):

@@ -221,3 +221,32 @@ def test_count_workspace_contract(cuda):
     torch.cuda.synchronize()
     assert np.array_equal(out2[0].cpu().numpy(), og2) and np.array_equal(out2[1].cpu().numpy(), ol2)
     g.close()
+
+
+def _orientation_stats(e, n):
+    """Statistics of the degree orientation from their definitions: rank = (degree, id); an
+    edge points from its lower- to its higher-ranked endpoint."""
+    e = e.astype(np.int64)
+    deg = np.bincount(e.ravel(), minlength=n)
+    key = deg * n + np.arange(n)
+    lo = np.where(key[e[:, 0]] < key[e[:, 1]], e[:, 0], e[:, 1])
+    hi = np.where(key[e[:, 0]] < key[e[:, 1]], e[:, 1], e[:, 0])
+    dout = np.bincount(lo, minlength=n)
+    return dict(work=int(np.minimum(dout[lo], dout[hi]).sum()), reverse=int((dout[lo] < dout[hi]).sum()),
+                sum_out_sq=int((dout * dout).sum()), max_out=int(dout.max()), units=int((dout >= 2).sum()))
+
+
+@pytest.mark.parametrize("kind", ["er", "chung_lu"])
+def test_build_statistics_match_definitions(cuda, kind):
+    from paper_1811_09136_amd import rept
+    if kind == "er":
+        e, n = synth.er(3000, 30000, 61, 62), 3000
+    else:
+        e, n = synth.scaled_chung_lu(80_000, 63)
+    g = rept.Graph(rept.to_device_edges(e, cuda), n)
+    ref = _orientation_stats(e, n)
+    _say(f"build statistics {kind}")
+    i = g.info
+    assert (i.oriented_work, i.num_reverse, i.sum_out_sq, i.max_out_degree, i.num_apex) == \
+        (ref["work"], ref["reverse"], ref["sum_out_sq"], ref["max_out"], ref["units"])
+    g.close()
