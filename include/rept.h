@@ -90,7 +90,7 @@ uint32_t rept_local_rows(const rept_params* params);
 
 /*
  * Device bytes needed to build a graph of n nodes and num_edges stream edges.
- *   persistent_bytes: kept by the built graph (oriented adjacency and reverse lists: 16 bytes
+ *   persistent_bytes: kept by the built graph (oriented adjacency and reverse lists: 28 bytes
  *                     per edge plus 12 bytes per node, rounded up);
  *   scratch_bytes:    needed only during rept_build.
  * Host only, no device work.  EINVAL if n == 0, n > 2^29 or num_edges >= 2^31.

@@ -126,7 +126,7 @@ rept_status make_job(const rept_job& jb, JobDev* d, uint64_t* zero_words) {
     d->tim = g->tim;
     d->apex = g->apex;
     d->roff = g->roff;
-    d->rnode = g->rnode;
+    d->rrec = g->rrec;
     d->rpos = g->rpos;
     d->global = jb.global;
     d->local = jb.local;

@@ -272,10 +272,13 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scatter(const uint2* __restric
 // passes visit every stored entry once: a block takes 256 consecutive nodes, stages their
 // offsets in LDS and finds each entry's node by binary search.
 constexpr uint32_t REV_SHARDS = 8;
+// A reverse entry carries what the counting pass stages for it -- a, the arrival time of a-b,
+// the offset and length of a's list -- so the staging reads it in one coalesced record.
 template <bool SCATTER>
 __global__ void __launch_bounds__(256) k_rev(const uint32_t* __restrict__ off, const uint32_t* __restrict__ nbr,
-                                             uint32_t n, uint32_t* cnt, const uint32_t* __restrict__ sofs,
-                                             uint32_t* __restrict__ rnode, uint32_t* __restrict__ rpos) {
+                                             const uint32_t* __restrict__ tim, uint32_t n, uint32_t* cnt,
+                                             const uint32_t* __restrict__ sofs, uint4* __restrict__ rrec,
+                                             uint32_t* __restrict__ rpos) {
     __shared__ uint32_t so[257];
     for (uint32_t b0 = blockIdx.x * 256u; b0 < n; b0 += gridDim.x * 256u) {
         const uint32_t c = (n - b0) < 256u ? (n - b0) : 256u;
@@ -291,11 +294,12 @@ __global__ void __launch_bounds__(256) k_rev(const uint32_t* __restrict__ off, c
                 if (so[mid] <= p) lo = mid; else hi = mid;
             }
             const uint32_t a = b0 + lo, b = nbr[p];
-            if (so[lo + 1] - so[lo] < off[b + 1] - off[b]) {
+            const uint32_t da = so[lo + 1] - so[lo];
+            if (da < off[b + 1] - off[b]) {
                 const uint64_t sh = (uint64_t)b * REV_SHARDS + (a % REV_SHARDS);
                 const uint32_t k = atomicAdd(&cnt[sh], 1u);
                 if (SCATTER) {
-                    rnode[sofs[sh] + k] = a;
+                    rrec[sofs[sh] + k] = make_uint4(a, tim[p], so[lo], da);
                     rpos[sofs[sh] + k] = p;
                 }
             }
@@ -551,7 +555,7 @@ __global__ void __launch_bounds__(64) k_sort_large(const uint32_t* __restrict__ 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t ctrl, off, nbr, tim, apex, roff, rnode, rpos, total;
+    size_t ctrl, off, nbr, tim, apex, roff, rrec, rpos, total;
 };
 struct ScratchLayout {
     size_t stats, deg, dout, cursor, ahist, aoff, part, packed, alt, medium, large, bhist, bscan, scnt, sofs, total;
@@ -591,8 +595,8 @@ Layout persistent_layout(uint32_t n, uint64_t E) {
     p += align256((size_t)n * 4);
     L.roff = p;
     p += align256(((size_t)n + 1) * 4);
-    L.rnode = p;
-    p += align256((size_t)E * 4);
+    L.rrec = p;
+    p += align256((size_t)E * 16);
     L.rpos = p;
     p += align256((size_t)E * 4);
     L.total = p;
@@ -676,7 +680,7 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     uint32_t* tim = (uint32_t*)(P + L.tim);
     uint32_t* apex = (uint32_t*)(P + L.apex);
     uint32_t* roff = (uint32_t*)(P + L.roff);
-    uint32_t* rnode = (uint32_t*)(P + L.rnode);
+    uint4* rrec = (uint4*)(P + L.rrec);
     uint32_t* rpos = (uint32_t*)(P + L.rpos);
     BuildStats* st = (BuildStats*)(X + S.stats);
     uint32_t* deg = (uint32_t*)(X + S.deg);
@@ -737,12 +741,12 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     const uint64_t nsh = (uint64_t)n * REV_SHARDS;
     const uint32_t gR = grid_for(n, 256, 16384), gS = grid_for(nsh, 256, cap);
     hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
-    hipLaunchKernelGGL(k_rev<false>, dim3(gR), dim3(256), 0, s, off, nbr, n, scnt, (const uint32_t*)nullptr,
-                       (uint32_t*)nullptr, (uint32_t*)nullptr);
+    hipLaunchKernelGGL(k_rev<false>, dim3(gR), dim3(256), 0, s, off, nbr, tim, n, scnt, (const uint32_t*)nullptr,
+                       (uint4*)nullptr, (uint32_t*)nullptr);
     if (scan_u32(scnt, nsh, part, sofs, s) != hipSuccess) return REPT_EDEVICE;
     hipLaunchKernelGGL(k_rev_roff, dim3(gN), dim3(256), 0, s, sofs, n, roff, st);
     hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
-    hipLaunchKernelGGL(k_rev<true>, dim3(gR), dim3(256), 0, s, off, nbr, n, scnt, sofs, rnode, rpos);
+    hipLaunchKernelGGL(k_rev<true>, dim3(gR), dim3(256), 0, s, off, nbr, tim, n, scnt, sofs, rrec, rpos);
     if (hipGetLastError() != hipSuccess) return REPT_EDEVICE;
 
     BuildStats hs;
@@ -763,7 +767,7 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     g->tim = tim;
     g->apex = apex;
     g->roff = roff;
-    g->rnode = rnode;
+    g->rrec = rrec;
     g->rpos = rpos;
     g->num_apex = hs.num_apex;
     g->max_out = hs.max_out;

@@ -40,7 +40,7 @@ struct rept_graph {
     const uint32_t* tim; // [E] arrival time of that edge
     const uint32_t* apex;// [num_apex] nodes with outdeg >= 2, by outdeg descending
     const uint32_t* roff;  // [n+1] reverse lists: pairs a -> b with outdeg(a) < outdeg(b), at b
-    const uint32_t* rnode; // [.] a
+    const uint4* rrec;     // [.] (a, arrival time of a-b, offset of a's list, length of a's list)
     const uint32_t* rpos;  // [.] position of b in a's list
     uint32_t num_apex;
     uint32_t max_out;
@@ -56,7 +56,7 @@ struct JobDev {
     const uint32_t* tim;
     const uint32_t* apex;
     const uint32_t* roff;
-    const uint32_t* rnode;
+    const uint4* rrec;
     const uint32_t* rpos;
     int64_t* global;
     int64_t* local;

@@ -197,7 +197,7 @@ struct JobRegs {
     const uint32_t* tim;
     const uint32_t* apex;
     const uint32_t* roff;
-    const uint32_t* rnode;
+    const uint4* rrec;
     const uint32_t* rpos;
     int64_t* global;
     int64_t* local;
@@ -211,7 +211,7 @@ __device__ inline void load_job(const JobDev* __restrict__ j, uint32_t HC, JobRe
     r.tim = j->tim;
     r.apex = j->apex;
     r.roff = j->roff;
-    r.rnode = j->rnode;
+    r.rrec = j->rrec;
     r.rpos = j->rpos;
     r.global = j->global;
     r.local = j->local;
@@ -583,15 +583,19 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                     if (e < d) {
                         pab = s + e;
                         b = ldg(J.nbr + pab);
+                        tb = ldg(J.tim + pab);
+                        bo = ldg(J.off + b);
+                        bd = ldg(J.off + b + 1) - bo;
+                        if (bd > d) bd = 0;  // out(a) is shorter: counted at b
                     } else {
                         const uint32_t q = r0 + (e - d);
-                        b = ldg(J.rnode + q);
+                        const uint4 r = J.rrec[q];
+                        b = r.x;
+                        tb = r.y;
+                        bo = r.z;
+                        bd = r.w;
                         pab = ldg(J.rpos + q);
                     }
-                    tb = ldg(J.tim + pab);
-                    bo = ldg(J.off + b);
-                    bd = ldg(J.off + b + 1) - bo;
-                    if (e < d && bd > d) bd = 0;  // out(a) is shorter: counted at b
                 }
                 uint32_t tot_nb, tot_items;
                 const uint32_t pos = nb + team_excl_scan<BLOCK>(bd ? 1u : 0u, T.red, tot_nb);
