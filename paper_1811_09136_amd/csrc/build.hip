@@ -229,6 +229,10 @@ __global__ void __launch_bounds__(1024) k_deg_count(const uint32_t* __restrict__
     }
 }
 
+// Reverse-list counters per target: REV_SHARDS shards (by source mod REV_SHARDS), so a hub's
+// increments spread over that many addresses.
+constexpr uint32_t REV_SHARDS = 8;
+
 // out-degree of each lower-ranked endpoint
 __global__ void k_orient_count(const uint2* __restrict__ edges, uint64_t E, uint32_t n,
                                const uint32_t* __restrict__ deg, uint32_t* dout) {
@@ -241,13 +245,14 @@ __global__ void k_orient_count(const uint2* __restrict__ edges, uint64_t E, uint
     }
 }
 
-// place every oriented entry (b, t) in its apex segment (unordered within the segment)
+// place every oriented entry (b, t) in its apex segment (unordered within the segment), and
+// count the reverse pairs (out(a) shorter than out(b)) per target shard
 __global__ void __launch_bounds__(SCAN_THREADS) k_scatter(const uint2* __restrict__ edges, uint64_t E, uint32_t n,
                                                           const uint32_t* __restrict__ deg,
                                                           const uint32_t* __restrict__ dout,
                                                           const uint32_t* __restrict__ off, uint32_t* cursor,
                                                           unsigned long long* __restrict__ packed,
-                                                          BuildStats* st) {
+                                                          uint32_t* __restrict__ rcnt, BuildStats* st) {
     unsigned long long work = 0;
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < E;
          t += (uint64_t)gridDim.x * blockDim.x) {
@@ -258,7 +263,9 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scatter(const uint2* __restric
         uint32_t pos = off[a] + atomicAdd(&cursor[a], 1u);
         packed[pos] = ((unsigned long long)b << 32) | (uint32_t)t;
         // the counting pass walks the shorter out-list of the pair (see k_rev)
-        work += dout[b] <= dout[a] ? dout[b] : dout[a];
+        const uint32_t da = dout[a], db = dout[b];
+        work += db <= da ? db : da;
+        if (da < db) atomicAdd(&rcnt[(uint64_t)b * REV_SHARDS + (a % REV_SHARDS)], 1u);
     }
     unsigned long long s = block_reduce_sum256<unsigned long long>(work);
     if (threadIdx.x == 0 && s) atomicAdd(&st->work, s);
@@ -266,15 +273,11 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scatter(const uint2* __restric
 
 // Reverse lists.  The counting pass finds a triangle from its lowest-ranked oriented pair
 // a -> b by walking the shorter of out(a), out(b) against a hash of the other.  Pairs with
-// out(a) shorter are counted at b: rev(b) lists them as (a, position of b in a's list).
-// Hubs receive many such pairs, so each target's list is cut into REV_SHARDS shards (by a mod
-// REV_SHARDS) with a counter each: a hub's increments spread over that many addresses.  Both
-// passes visit every stored entry once: a block takes 256 consecutive nodes, stages their
-// offsets in LDS and finds each entry's node by binary search.
-constexpr uint32_t REV_SHARDS = 8;
+// out(a) shorter are counted at b: rev(b) lists them, cut into REV_SHARDS shards (counted per
+// shard by k_scatter).  The scatter below visits every sorted entry once: a block takes 256
+// consecutive nodes, stages their offsets in LDS and finds each entry's node by binary search.
 // A reverse entry carries what the counting pass stages for it -- a, the arrival time of a-b,
 // the offset and length of a's list -- so the staging reads it in one coalesced record.
-template <bool SCATTER>
 __global__ void __launch_bounds__(256) k_rev(const uint32_t* __restrict__ off, const uint32_t* __restrict__ nbr,
                                              const uint32_t* __restrict__ tim, uint32_t n, uint32_t* cnt,
                                              const uint32_t* __restrict__ sofs, uint4* __restrict__ rrec,
@@ -298,10 +301,8 @@ __global__ void __launch_bounds__(256) k_rev(const uint32_t* __restrict__ off, c
             if (da < off[b + 1] - off[b]) {
                 const uint64_t sh = (uint64_t)b * REV_SHARDS + (a % REV_SHARDS);
                 const uint32_t k = atomicAdd(&cnt[sh], 1u);
-                if (SCATTER) {
-                    rrec[sofs[sh] + k] = make_uint4(a, tim[p], so[lo], da);
-                    rpos[sofs[sh] + k] = p;
-                }
+                rrec[sofs[sh] + k] = make_uint4(a, tim[p], so[lo], da);
+                rpos[sofs[sh] + k] = p;
             }
         }
     }
@@ -724,7 +725,10 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
 
     hipLaunchKernelGGL(k_orient_count, dim3(gE), dim3(256), 0, s, e2, E, n, deg, dout);
     if (scan_u32(dout, n, part, off, s) != hipSuccess) return REPT_EDEVICE;
-    hipLaunchKernelGGL(k_scatter, dim3(gE), dim3(256), 0, s, e2, E, n, deg, dout, off, cursor, packed, st);
+    const uint64_t nsh = (uint64_t)n * REV_SHARDS;
+    const uint32_t gS = grid_for(nsh, 256, cap);
+    hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
+    hipLaunchKernelGGL(k_scatter, dim3(gE), dim3(256), 0, s, e2, E, n, deg, dout, off, cursor, packed, scnt, st);
     hipLaunchKernelGGL(k_classify, dim3(gA), dim3(256), 0, s, off, n, ahist, medium, large, st);
     hipLaunchKernelGGL(k_sort_small, dim3(grid_for((uint64_t)n, 4, cap * 4)), dim3(256), 0, s, off, n, packed,
                        nbr, tim, st);
@@ -737,16 +741,12 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     if (scan_u32(ahist, n, part, aoff, s) != hipSuccess) return REPT_EDEVICE;
     hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, cursor, (uint64_t)n, 0u);
     hipLaunchKernelGGL(k_apex_scatter, dim3(gA), dim3(256), 0, s, off, n, aoff, cursor, apex);
-    // reverse lists: count per target shard, scan, scatter
-    const uint64_t nsh = (uint64_t)n * REV_SHARDS;
-    const uint32_t gR = grid_for(n, 256, 16384), gS = grid_for(nsh, 256, cap);
-    hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
-    hipLaunchKernelGGL(k_rev<false>, dim3(gR), dim3(256), 0, s, off, nbr, tim, n, scnt, (const uint32_t*)nullptr,
-                       (uint4*)nullptr, (uint32_t*)nullptr);
+    // reverse lists: shard counts (from k_scatter) scanned, then the scatter after the sorts
+    const uint32_t gR = grid_for(n, 256, 16384);
     if (scan_u32(scnt, nsh, part, sofs, s) != hipSuccess) return REPT_EDEVICE;
     hipLaunchKernelGGL(k_rev_roff, dim3(gN), dim3(256), 0, s, sofs, n, roff, st);
     hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
-    hipLaunchKernelGGL(k_rev<true>, dim3(gR), dim3(256), 0, s, off, nbr, tim, n, scnt, sofs, rrec, rpos);
+    hipLaunchKernelGGL(k_rev, dim3(gR), dim3(256), 0, s, off, nbr, tim, n, scnt, sofs, rrec, rpos);
     if (hipGetLastError() != hipSuccess) return REPT_EDEVICE;
 
     BuildStats hs;
