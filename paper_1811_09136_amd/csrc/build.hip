@@ -262,7 +262,7 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scatter(const uint2* __restric
         uint32_t a = xa ? e.x : e.y, b = xa ? e.y : e.x;
         uint32_t pos = off[a] + atomicAdd(&cursor[a], 1u);
         packed[pos] = ((unsigned long long)b << 32) | (uint32_t)t;
-        // the counting pass walks the shorter out-list of the pair (see k_rev)
+        // the counting pass walks the shorter out-list of the pair (see emit_rev)
         const uint32_t da = dout[a], db = dout[b];
         work += db <= da ? db : da;
         if (da < db) atomicAdd(&rcnt[(uint64_t)b * REV_SHARDS + (a % REV_SHARDS)], 1u);
@@ -273,40 +273,11 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scatter(const uint2* __restric
 
 // Reverse lists.  The counting pass finds a triangle from its lowest-ranked oriented pair
 // a -> b by walking the shorter of out(a), out(b) against a hash of the other.  Pairs with
-// out(a) shorter are counted at b: rev(b) lists them, cut into REV_SHARDS shards (counted per
-// shard by k_scatter).  The scatter below visits every sorted entry once: a block takes 256
-// consecutive nodes, stages their offsets in LDS and finds each entry's node by binary search.
-// A reverse entry carries what the counting pass stages for it -- a, the arrival time of a-b,
-// the offset and length of a's list -- so the staging reads it in one coalesced record.
-__global__ void __launch_bounds__(256) k_rev(const uint32_t* __restrict__ off, const uint32_t* __restrict__ nbr,
-                                             const uint32_t* __restrict__ tim, uint32_t n, uint32_t* cnt,
-                                             const uint32_t* __restrict__ sofs, uint4* __restrict__ rrec,
-                                             uint32_t* __restrict__ rpos) {
-    __shared__ uint32_t so[257];
-    for (uint32_t b0 = blockIdx.x * 256u; b0 < n; b0 += gridDim.x * 256u) {
-        const uint32_t c = (n - b0) < 256u ? (n - b0) : 256u;
-        __syncthreads();
-        if (threadIdx.x < c) so[threadIdx.x] = off[b0 + threadIdx.x];
-        if (threadIdx.x == 0) so[c] = off[b0 + c];
-        __syncthreads();
-        const uint32_t e1 = so[c];
-        for (uint32_t p = so[0] + threadIdx.x; p < e1; p += 256u) {
-            uint32_t lo = 0, hi = c;  // so[lo] <= p < so[hi]
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (so[mid] <= p) lo = mid; else hi = mid;
-            }
-            const uint32_t a = b0 + lo, b = nbr[p];
-            const uint32_t da = so[lo + 1] - so[lo];
-            if (da < off[b + 1] - off[b]) {
-                const uint64_t sh = (uint64_t)b * REV_SHARDS + (a % REV_SHARDS);
-                const uint32_t k = atomicAdd(&cnt[sh], 1u);
-                rrec[sofs[sh] + k] = make_uint4(a, tim[p], so[lo], da);
-                rpos[sofs[sh] + k] = p;
-            }
-        }
-    }
-}
+// out(a) shorter are counted at b: rev(b) lists them, cut into REV_SHARDS shards.  k_scatter
+// counts each shard, a scan gives the shard starts, and the segment sorts, which know each
+// entry's final position, write the records (emit_rev).  A record carries what the counting
+// pass stages for the pair -- a, the arrival time of a-b, the offset and length of a's list --
+// and the position of b in a's list.
 
 // roff[b] = start of b's first shard (roff[n] = the number of pairs)
 __global__ void k_rev_roff(const uint32_t* __restrict__ sofs, uint32_t n, uint32_t* __restrict__ roff,
@@ -408,11 +379,31 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_apex_scatter(const uint32_t* _
     }
 }
 
-__device__ __forceinline__ void emit_sorted(unsigned long long v, uint32_t idx, uint32_t seg, uint32_t d,
-                                            uint32_t* nbr, uint32_t* tim) {
+// Where the sorts emit the entry (b, t) at position s + i of a's list (length d): when out(a) is
+// shorter than out(b), also the reverse record of the pair in the next free slot of b's shard.
+struct RevOut {
+    const uint32_t* off;
+    uint32_t* cur;         // per target shard, from 0
+    const uint32_t* sofs;  // shard starts
+    uint4* rrec;
+    uint32_t* rpos;
+};
+__device__ __forceinline__ void emit_rev(const RevOut& R, uint32_t a, uint32_t s, uint32_t d, uint32_t i, uint32_t b,
+                                         uint32_t t) {
+    if (d < R.off[b + 1] - R.off[b]) {
+        const uint64_t sh = (uint64_t)b * REV_SHARDS + (a % REV_SHARDS);
+        const uint32_t q = R.sofs[sh] + atomicAdd(&R.cur[sh], 1u);
+        R.rrec[q] = make_uint4(a, t, s, d);
+        R.rpos[q] = s + i;
+    }
+}
+
+__device__ __forceinline__ void emit_sorted(unsigned long long v, uint32_t idx, uint32_t a, uint32_t seg, uint32_t d,
+                                            uint32_t* nbr, uint32_t* tim, const RevOut& R) {
     if (idx < d) {
         nbr[seg + idx] = (uint32_t)(v >> 32);
         tim[seg + idx] = (uint32_t)v;
+        emit_rev(R, a, seg, d, idx, (uint32_t)(v >> 32), (uint32_t)v);
     }
 }
 
@@ -420,7 +411,7 @@ __device__ __forceinline__ void emit_sorted(unsigned long long v, uint32_t idx, 
 __global__ void __launch_bounds__(256) k_sort_small(const uint32_t* __restrict__ off, uint32_t n,
                                                     const unsigned long long* __restrict__ packed,
                                                     uint32_t* __restrict__ nbr, uint32_t* __restrict__ tim,
-                                                    BuildStats* st) {
+                                                    RevOut R, BuildStats* st) {
     const int lane = threadIdx.x & 63;
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
     uint32_t dup = 0;
@@ -439,7 +430,7 @@ __global__ void __launch_bounds__(256) k_sort_small(const uint32_t* __restrict__
         }
         unsigned long long prev = __shfl_up(v, 1, 64);
         if (lane > 0 && lane < (int)d && (prev >> 32) == (v >> 32)) dup = 1;
-        emit_sorted(v, lane, s, d, nbr, tim);
+        emit_sorted(v, lane, a, s, d, nbr, tim, R);
     }
     if (dup) atomicOr(&st->flags, RF_DUP);
 }
@@ -448,7 +439,7 @@ __global__ void __launch_bounds__(256) k_sort_small(const uint32_t* __restrict__
 __global__ void __launch_bounds__(512) k_sort_medium(const uint32_t* __restrict__ off, const uint32_t* __restrict__ list,
                                                      const unsigned long long* __restrict__ packed,
                                                      uint32_t* __restrict__ nbr, uint32_t* __restrict__ tim,
-                                                     BuildStats* st) {
+                                                     RevOut R, BuildStats* st) {
     __shared__ unsigned long long buf[MEDIUM_MAX];
     const uint32_t cnt = st->n_medium;
     for (uint32_t q = blockIdx.x; q < cnt; q += gridDim.x) {
@@ -478,8 +469,7 @@ __global__ void __launch_bounds__(512) k_sort_medium(const uint32_t* __restrict_
         for (uint32_t i = threadIdx.x; i < d; i += blockDim.x) {
             unsigned long long v = buf[i];
             if (i > 0 && (buf[i - 1] >> 32) == (v >> 32)) dup = 1;
-            nbr[s + i] = (uint32_t)(v >> 32);
-            tim[s + i] = (uint32_t)v;
+            emit_sorted(v, i, a, s, d, nbr, tim, R);
         }
         if (dup) atomicOr(&st->flags, RF_DUP);
         __syncthreads();
@@ -491,7 +481,7 @@ __global__ void __launch_bounds__(512) k_sort_medium(const uint32_t* __restrict_
 __global__ void __launch_bounds__(64) k_sort_large(const uint32_t* __restrict__ off, const uint32_t* __restrict__ list,
                                                    unsigned long long* packed, unsigned long long* alt,
                                                    uint32_t id_bits, uint32_t* __restrict__ nbr,
-                                                   uint32_t* __restrict__ tim, BuildStats* st) {
+                                                   uint32_t* __restrict__ tim, RevOut R, BuildStats* st) {
     __shared__ uint32_t base[256];
     const int lane = threadIdx.x;
     const uint32_t cnt = st->n_large;
@@ -545,8 +535,7 @@ __global__ void __launch_bounds__(64) k_sort_large(const uint32_t* __restrict__ 
         for (uint32_t i = lane; i < d; i += 64) {
             unsigned long long v = src[i];
             if (i > 0 && (src[i - 1] >> 32) == (v >> 32)) dup = 1;
-            nbr[s + i] = (uint32_t)(v >> 32);
-            tim[s + i] = (uint32_t)v;
+            emit_sorted(v, i, a, s, d, nbr, tim, R);
         }
         if (dup) atomicOr(&st->flags, RF_DUP);
         __syncthreads();
@@ -729,24 +718,23 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     const uint32_t gS = grid_for(nsh, 256, cap);
     hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
     hipLaunchKernelGGL(k_scatter, dim3(gE), dim3(256), 0, s, e2, E, n, deg, dout, off, cursor, packed, scnt, st);
-    hipLaunchKernelGGL(k_classify, dim3(gA), dim3(256), 0, s, off, n, ahist, medium, large, st);
-    hipLaunchKernelGGL(k_sort_small, dim3(grid_for((uint64_t)n, 4, cap * 4)), dim3(256), 0, s, off, n, packed,
-                       nbr, tim, st);
-    hipLaunchKernelGGL(k_sort_medium, dim3(cus ? cus * 4 : 1024), dim3(512), 0, s, off, medium, packed, nbr,
-                       tim, st);
-    uint32_t id_bits = 1;
-    while (id_bits < 32 && ((uint64_t)1 << id_bits) < (uint64_t)n) ++id_bits;
-    hipLaunchKernelGGL(k_sort_large, dim3(cus ? cus : 256), dim3(64), 0, s, off, large, packed, alt, id_bits,
-                       nbr, tim, st);
-    if (scan_u32(ahist, n, part, aoff, s) != hipSuccess) return REPT_EDEVICE;
-    hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, cursor, (uint64_t)n, 0u);
-    hipLaunchKernelGGL(k_apex_scatter, dim3(gA), dim3(256), 0, s, off, n, aoff, cursor, apex);
-    // reverse lists: shard counts (from k_scatter) scanned, then the scatter after the sorts
-    const uint32_t gR = grid_for(n, 256, 16384);
+    // reverse lists: shard starts from k_scatter's counts; the sorts place the records
     if (scan_u32(scnt, nsh, part, sofs, s) != hipSuccess) return REPT_EDEVICE;
     hipLaunchKernelGGL(k_rev_roff, dim3(gN), dim3(256), 0, s, sofs, n, roff, st);
     hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
-    hipLaunchKernelGGL(k_rev, dim3(gR), dim3(256), 0, s, off, nbr, tim, n, scnt, sofs, rrec, rpos);
+    const RevOut RO{off, scnt, sofs, rrec, rpos};
+    hipLaunchKernelGGL(k_classify, dim3(gA), dim3(256), 0, s, off, n, ahist, medium, large, st);
+    hipLaunchKernelGGL(k_sort_small, dim3(grid_for((uint64_t)n, 4, cap * 4)), dim3(256), 0, s, off, n, packed,
+                       nbr, tim, RO, st);
+    hipLaunchKernelGGL(k_sort_medium, dim3(cus ? cus * 4 : 1024), dim3(512), 0, s, off, medium, packed, nbr,
+                       tim, RO, st);
+    uint32_t id_bits = 1;
+    while (id_bits < 32 && ((uint64_t)1 << id_bits) < (uint64_t)n) ++id_bits;
+    hipLaunchKernelGGL(k_sort_large, dim3(cus ? cus : 256), dim3(64), 0, s, off, large, packed, alt, id_bits,
+                       nbr, tim, RO, st);
+    if (scan_u32(ahist, n, part, aoff, s) != hipSuccess) return REPT_EDEVICE;
+    hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, cursor, (uint64_t)n, 0u);
+    hipLaunchKernelGGL(k_apex_scatter, dim3(gA), dim3(256), 0, s, off, n, aoff, cursor, apex);
     if (hipGetLastError() != hipSuccess) return REPT_EDEVICE;
 
     BuildStats hs;
