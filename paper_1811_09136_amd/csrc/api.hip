@@ -180,7 +180,7 @@ rept_status count_one(const rept_graph* graph, const rept_params* params, uint64
     st = make_header(1, d.G, d.c, graph->max_out, zw, !accumulate, nullptr, &h);
     if (st != REPT_OK) return st;
     h.any_fill = 1;
-    h.fill_nodes = graph->n;
+    h.fill_edges = graph->E > UINT32_MAX ? UINT32_MAX : (uint32_t)graph->E;
     if (rept_launch_single(graph->ctrl, h, d, (hipStream_t)stream) != hipSuccess) return REPT_EDEVICE;
     return REPT_OK;
 }
@@ -360,7 +360,7 @@ rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_
     uint32_t G_max = 1, c_max = 1, max_out = 0;
     uint64_t zero_words = 0;
     bool any_zero = false, any_fill = false;
-    uint32_t fill_nodes = 0;
+    uint64_t fill_edges = 0;
     for (uint32_t j = 0; j < njobs; ++j) {
         uint64_t zw = 0;
         rept_status st = make_job(jobs[j], &hj[j], &zw);
@@ -377,7 +377,7 @@ rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_
         }
         if (hj[j].fill) {
             any_fill = true;
-            fill_nodes = hj[j].n > fill_nodes ? hj[j].n : fill_nodes;
+            fill_edges = jobs[j].graph->E > fill_edges ? jobs[j].graph->E : fill_edges;
         }
     }
     BatchHeader h;
@@ -387,7 +387,7 @@ rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_
         return st;
     }
     h.any_fill = any_fill ? 1u : 0u;
-    h.fill_nodes = fill_nodes;
+    h.fill_edges = fill_edges > UINT32_MAX ? UINT32_MAX : (uint32_t)fill_edges;
     memcpy(host, &h, sizeof(h));
     hipError_t e = hipMemcpyAsync(workspace, host, bytes, hipMemcpyHostToDevice, (hipStream_t)stream);
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);  // `host` is freed below

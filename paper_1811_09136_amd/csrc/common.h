@@ -97,7 +97,7 @@ struct BatchHeader {
     uint32_t light_table;  // hash slots per key, at least, in the light phase (2 or 4)
     uint64_t zero_words;   // max words to clear over jobs
     uint32_t any_fill;     // some job's slot table is written by this launch
-    uint32_t fill_nodes;   // largest node count over those jobs
+    uint32_t fill_edges;   // largest stream length over those jobs (bounds their stored edges)
     uint32_t pad[12];
 };
 

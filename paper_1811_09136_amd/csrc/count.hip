@@ -229,14 +229,19 @@ __device__ inline void load_job(const JobDev* __restrict__ j, uint32_t HC, JobRe
 }
 
 // ---- edge hash: degree-3 polynomial over GF(2^61 - 1), Horner form ---------------------------
-__device__ __forceinline__ uint64_t fold61(uint64_t r) {  // r < 2^62 -> [0, p)
+__device__ __forceinline__ uint64_t fold61(uint64_t r) {  // r < 2^64 -> [0, p)
     r = (r & kP61) + (r >> 61);
     return r >= kP61 ? r - kP61 : r;
 }
-__device__ __forceinline__ uint64_t mulmod61(uint64_t a, uint64_t b) {  // a, b < 2^61
-    const uint64_t lo = a * b;
-    const uint64_t hi = __umul64hi(a, b);  // product < 2^122
-    return fold61((lo & kP61) + ((hi << 3) | (lo >> 61)));
+// a * b mod p for a, b < 2^61, from the four 32 x 32 -> 64 bit partial products.  With
+// 2^61 = 1 and 2^64 = 8 (mod p): a * b = 8 hh + mid 2^32 + ll, and mid 2^32 = (mid >> 29) +
+// (mid mod 2^29) 2^32 (mod p); the five terms sum below 2^63.
+__device__ __forceinline__ uint64_t mulmod61(uint64_t a, uint64_t b) {
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    const uint64_t ll = (uint64_t)a0 * b0;                       // < 2^64
+    const uint64_t mid = (uint64_t)a0 * b1 + (uint64_t)a1 * b0;  // < 2^62
+    const uint64_t hh = (uint64_t)a1 * b1;                       // < 2^58
+    return fold61((hh << 3) + (mid >> 29) + ((mid & 0x1fffffffull) << 32) + (ll & kP61) + (ll >> 61));
 }
 // slot of the undirected edge {x, y} for the group whose coefficients are c4[0..3]
 __device__ __forceinline__ uint32_t slot_of(const uint64_t* c4, uint32_t m, uint32_t x, uint32_t y) {
@@ -723,39 +728,67 @@ __global__ void k_zero(const BatchHeader* hdr, const JobDev* jobs) {
 
 // Slot table of each job whose launch writes it: tab[p * gs + k] = h_k of the edge stored at
 // position p, i.e. {b, nbr[p]} for the node b whose list holds p (Section III-A's hash, one
-// independent function per group as in Section III-B).  Grid (X, njobs) of 256 threads: a
-// block takes 256 consecutive nodes, stages their offsets in LDS and hashes their entries one
-// per thread (coalesced), finding each entry's node by binary search over the offsets.
+// independent function per group as in Section III-B).  Grid (X, njobs) of 256 threads.  A
+// workgroup takes FILL_CHUNK consecutive positions (so a range of long lists is spread over
+// many workgroups), finds the nodes owning its first and last positions, stages the offsets of
+// that node range in LDS, FILL_NODES at a time, and hashes one position per thread (coalesced),
+// finding each position's node by binary search over the staged offsets.
+constexpr uint32_t FILL_CHUNK = 4096;
+constexpr uint32_t FILL_NODES = 1024;
+
+// the node whose list holds position p (the largest b < n with off[b] <= p), for p < off[n]:
+// each round samples the candidate node range at 256 evenly spaced nodes, one per thread, and
+// keeps the interval between the last sample at or below p and the next
+__device__ uint32_t fill_owner(const uint32_t* off, uint32_t n, uint32_t p) {
+    uint32_t L = 0, R = n;  // off[L] <= p < off[R]
+    while (R - L > 1) {
+        const uint32_t step = (R - L + 255u) / 256u;
+        const uint32_t b = L + threadIdx.x * step;
+        const uint32_t k = (uint32_t)__syncthreads_count(b < R && ldg(off + b) <= p);  // >= 1
+        const uint32_t L2 = L + (k - 1u) * step;
+        R = (L2 + step) < R ? (L2 + step) : R;
+        L = L2;
+    }
+    return L;
+}
+
 __global__ void __launch_bounds__(256) k_fill(const JobDev* __restrict__ jobs) {
-    __shared__ uint32_t so[257];
+    __shared__ uint32_t so[FILL_NODES + 1];
     const JobDev& J = jobs[blockIdx.y];
     if (!J.fill) return;
     const uint32_t G = J.G, gs = J.gs, m = J.m, n = J.n;
     const uint32_t* __restrict__ off = J.off;
     const uint32_t* __restrict__ nbr = J.nbr;
     uint16_t* __restrict__ tab = J.tab;
-    for (uint32_t b0 = blockIdx.x * 256u; b0 < n; b0 += gridDim.x * 256u) {
-        const uint32_t cnt = (n - b0) < 256u ? (n - b0) : 256u;
-        __syncthreads();  // the previous range's offsets are no longer read
-        if (threadIdx.x < cnt) so[threadIdx.x] = off[b0 + threadIdx.x];
-        if (threadIdx.x == 0) so[cnt] = off[b0 + cnt];
-        __syncthreads();
-        const uint32_t e1 = so[cnt];
-        for (uint32_t p = so[0] + threadIdx.x; p < e1; p += 256u) {
-            uint32_t lo = 0, hi = cnt;  // so[lo] <= p < so[hi]
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (so[mid] <= p) lo = mid; else hi = mid;
-            }
-            const uint32_t b = b0 + lo, w = nbr[p];
-            uint32_t wd[4] = {0u, 0u, 0u, 0u};
+    uint64_t cf[4 * REPT_GMAX];  // coefficients read once (the table stores cannot change them)
 #pragma unroll
-            for (uint32_t g = 0; g < REPT_GMAX; ++g)
-                if (g < G) wd[g >> 1] |= slot_of(J.hp + 4 * g, m, b, w) << (16 * (g & 1));
-            if (gs == 1) tab[p] = (uint16_t)wd[0];
-            else if (gs == 2) ((uint32_t*)tab)[p] = wd[0];
-            else if (gs == 4) ((uint2*)tab)[p] = make_uint2(wd[0], wd[1]);
-            else ((uint4*)tab)[p] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+    for (uint32_t i = 0; i < 4 * REPT_GMAX; ++i) cf[i] = i < 4 * G ? J.hp[i] : 0;
+    const uint32_t Es = ldg(off + n);
+    for (uint64_t c0 = (uint64_t)blockIdx.x * FILL_CHUNK; c0 < Es; c0 += (uint64_t)gridDim.x * FILL_CHUNK) {
+        const uint32_t p0 = (uint32_t)c0, p1 = (c0 + FILL_CHUNK) < Es ? (uint32_t)(c0 + FILL_CHUNK) : Es;
+        const uint32_t bf = fill_owner(off, n, p0), bl = fill_owner(off, n, p1 - 1u);
+        for (uint32_t w0 = bf; w0 <= bl; w0 += FILL_NODES) {
+            const uint32_t cnt = (bl + 1u - w0) < FILL_NODES ? (bl + 1u - w0) : FILL_NODES;
+            __syncthreads();  // the previous window's offsets are no longer read
+            for (uint32_t i = threadIdx.x; i <= cnt; i += 256u) so[i] = ldg(off + w0 + i);
+            __syncthreads();
+            const uint32_t q0 = so[0] > p0 ? so[0] : p0, q1 = so[cnt] < p1 ? so[cnt] : p1;
+            for (uint32_t p = q0 + threadIdx.x; p < q1; p += 256u) {
+                uint32_t lo = 0, hi = cnt;  // so[lo] <= p < so[hi]
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (so[mid] <= p) lo = mid; else hi = mid;
+                }
+                const uint32_t b = w0 + lo, w = ldg(nbr + p);
+                uint32_t wd[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (uint32_t g = 0; g < REPT_GMAX; ++g)
+                    if (g < G) wd[g >> 1] |= slot_of(cf + 4 * g, m, b, w) << (16 * (g & 1));
+                if (gs == 1) tab[p] = (uint16_t)wd[0];
+                else if (gs == 2) ((uint32_t*)tab)[p] = wd[0];
+                else if (gs == 4) ((uint2*)tab)[p] = make_uint2(wd[0], wd[1]);
+                else ((uint4*)tab)[p] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+            }
         }
     }
 }
@@ -871,10 +904,10 @@ hipError_t launch_common(uint8_t* ws, const BatchHeader& h, hipStream_t s) {
         hipLaunchKernelGGL(k_zero, dim3((uint32_t)blocks, h.njobs), dim3(256), 0, s, hdr, jobs);
     }
     if (h.any_fill) {
-        uint32_t blocks = (h.fill_nodes + 255) / 256;
-        if (blocks > 16384) blocks = 16384;
+        uint64_t blocks = (h.fill_edges + FILL_CHUNK - 1) / FILL_CHUNK;
+        if (blocks > 8192) blocks = 8192;
         if (blocks < 1) blocks = 1;
-        hipLaunchKernelGGL(k_fill, dim3(blocks, h.njobs), dim3(256), 0, s, jobs);
+        hipLaunchKernelGGL(k_fill, dim3((uint32_t)blocks, h.njobs), dim3(256), 0, s, jobs);
     }
     hipLaunchKernelGGL(k_count, dim3(h.blocks), dim3(h.threads), h.lds_bytes, s, hdr, jobs);
     return report(hipGetLastError(), "counting kernel launch");
