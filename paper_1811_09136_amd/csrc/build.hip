@@ -233,39 +233,90 @@ __global__ void __launch_bounds__(1024) k_deg_count(const uint32_t* __restrict__
 // increments spread over that many addresses.
 constexpr uint32_t REV_SHARDS = 8;
 
-// out-degree of each lower-ranked endpoint
-__global__ void k_orient_count(const uint2* __restrict__ edges, uint64_t E, uint32_t n,
-                               const uint32_t* __restrict__ deg, uint32_t* dout) {
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < E;
-         t += (uint64_t)gridDim.x * blockDim.x) {
-        uint2 e = edges[t];
-        if (e.x >= n || e.y >= n || e.x == e.y) continue;
-        uint32_t a = rank_less(e.x, deg[e.x], e.y, deg[e.y]) ? e.x : e.y;
-        atomicAdd(&dout[a], 1u);
+// out-degree of each lower-ranked endpoint, and each edge's orientation ab[t] = (a, b) from
+// its lower- to its higher-ranked endpoint (NO_EDGE for an invalid edge), so the scatter
+// below need not look the degrees up again
+constexpr uint32_t NO_EDGE = 0xffffffffu;
+// Both edge passes take EDGE_UNROLL edges per thread per step, one grid stride apart, so the
+// independent scattered loads and atomics of those edges are in flight together.
+constexpr uint32_t EDGE_UNROLL = 4;
+__global__ void __launch_bounds__(256) k_orient_count(const uint2* __restrict__ edges, uint64_t E, uint32_t n,
+                                                      const uint32_t* __restrict__ deg, uint32_t* dout,
+                                                      uint2* __restrict__ ab) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t0 < E; t0 += EDGE_UNROLL * stride) {
+        uint2 e[EDGE_UNROLL];
+        bool ok[EDGE_UNROLL];
+        uint32_t dx[EDGE_UNROLL], dy[EDGE_UNROLL];
+#pragma unroll
+        for (uint32_t u = 0; u < EDGE_UNROLL; ++u) {
+            const uint64_t t = t0 + u * stride;
+            e[u] = t < E ? edges[t] : make_uint2(0u, 0u);
+            ok[u] = t < E && e[u].x < n && e[u].y < n && e[u].x != e[u].y;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < EDGE_UNROLL; ++u) {
+            dx[u] = ok[u] ? deg[e[u].x] : 0u;
+            dy[u] = ok[u] ? deg[e[u].y] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < EDGE_UNROLL; ++u) {
+            const uint64_t t = t0 + u * stride;
+            if (t >= E) continue;
+            if (!ok[u]) {
+                ab[t] = make_uint2(NO_EDGE, NO_EDGE);
+                continue;
+            }
+            const bool xa = rank_less(e[u].x, dx[u], e[u].y, dy[u]);
+            const uint32_t a = xa ? e[u].x : e[u].y, b = xa ? e[u].y : e[u].x;
+            ab[t] = make_uint2(a, b);
+            atomicAdd(&dout[a], 1u);
+        }
     }
 }
 
-// place every oriented entry (b, t) in its apex segment (unordered within the segment), and
-// count the reverse pairs (out(a) shorter than out(b)) per target shard
-__global__ void __launch_bounds__(SCAN_THREADS) k_scatter(const uint2* __restrict__ edges, uint64_t E, uint32_t n,
-                                                          const uint32_t* __restrict__ deg,
-                                                          const uint32_t* __restrict__ dout,
-                                                          const uint32_t* __restrict__ off, uint32_t* cursor,
+__global__ void k_copy_u32(const uint32_t* __restrict__ src, uint64_t count, uint32_t* __restrict__ dst) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// place every oriented entry in its apex segment (unordered within the segment) as
+// b << 32 | rev << 31 | t, where rev marks a reverse pair (out(a) shorter than out(b); the
+// stream position t is below 2^31, and rev, a function of b within a's segment, leaves the
+// order by (b, t) unchanged), and count the reverse pairs per target shard.  cursor[a] starts
+// at off[a].
+constexpr uint32_t REV_BIT = 0x80000000u;
+__global__ void __launch_bounds__(SCAN_THREADS) k_scatter(const uint2* __restrict__ ab, uint64_t E,
+                                                          const uint32_t* __restrict__ dout, uint32_t* cursor,
                                                           unsigned long long* __restrict__ packed,
                                                           uint32_t* __restrict__ rcnt, BuildStats* st) {
     unsigned long long work = 0;
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < E;
-         t += (uint64_t)gridDim.x * blockDim.x) {
-        uint2 e = edges[t];
-        if (e.x >= n || e.y >= n || e.x == e.y) continue;
-        bool xa = rank_less(e.x, deg[e.x], e.y, deg[e.y]);
-        uint32_t a = xa ? e.x : e.y, b = xa ? e.y : e.x;
-        uint32_t pos = off[a] + atomicAdd(&cursor[a], 1u);
-        packed[pos] = ((unsigned long long)b << 32) | (uint32_t)t;
-        // the counting pass walks the shorter out-list of the pair (see emit_rev)
-        const uint32_t da = dout[a], db = dout[b];
-        work += db <= da ? db : da;
-        if (da < db) atomicAdd(&rcnt[(uint64_t)b * REV_SHARDS + (a % REV_SHARDS)], 1u);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t0 < E; t0 += EDGE_UNROLL * stride) {
+        uint2 e[EDGE_UNROLL];
+        uint32_t pos[EDGE_UNROLL], da[EDGE_UNROLL], db[EDGE_UNROLL];
+#pragma unroll
+        for (uint32_t u = 0; u < EDGE_UNROLL; ++u) {
+            const uint64_t t = t0 + u * stride;
+            e[u] = t < E ? ab[t] : make_uint2(NO_EDGE, NO_EDGE);
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < EDGE_UNROLL; ++u) {
+            const bool ok = e[u].x != NO_EDGE;
+            pos[u] = ok ? atomicAdd(&cursor[e[u].x], 1u) : 0u;
+            // the counting pass walks the shorter out-list of the pair (see emit_rev)
+            da[u] = ok ? dout[e[u].x] : 0u;
+            db[u] = ok ? dout[e[u].y] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < EDGE_UNROLL; ++u) {
+            if (e[u].x == NO_EDGE) continue;
+            const uint32_t a = e[u].x, b = e[u].y;
+            const bool rev = da[u] < db[u];
+            packed[pos[u]] = ((unsigned long long)b << 32) | (rev ? REV_BIT : 0u) | (uint32_t)(t0 + u * stride);
+            work += db[u] <= da[u] ? db[u] : da[u];
+            if (rev) atomicAdd(&rcnt[(uint64_t)b * REV_SHARDS + (a % REV_SHARDS)], 1u);
+        }
     }
     unsigned long long s = block_reduce_sum256<unsigned long long>(work);
     if (threadIdx.x == 0 && s) atomicAdd(&st->work, s);
@@ -379,31 +430,28 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_apex_scatter(const uint32_t* _
     }
 }
 
-// Where the sorts emit the entry (b, t) at position s + i of a's list (length d): when out(a) is
-// shorter than out(b), also the reverse record of the pair in the next free slot of b's shard.
+// Where the sorts emit the entry (b, t) at position s + i of a's list (length d): for a reverse
+// pair (out(a) shorter than out(b)), also the reverse record in the next free slot of b's shard.
 struct RevOut {
-    const uint32_t* off;
-    uint32_t* cur;         // per target shard, from 0
-    const uint32_t* sofs;  // shard starts
+    uint32_t* cur;  // per target shard, from the shard's start
     uint4* rrec;
     uint32_t* rpos;
 };
 __device__ __forceinline__ void emit_rev(const RevOut& R, uint32_t a, uint32_t s, uint32_t d, uint32_t i, uint32_t b,
                                          uint32_t t) {
-    if (d < R.off[b + 1] - R.off[b]) {
-        const uint64_t sh = (uint64_t)b * REV_SHARDS + (a % REV_SHARDS);
-        const uint32_t q = R.sofs[sh] + atomicAdd(&R.cur[sh], 1u);
-        R.rrec[q] = make_uint4(a, t, s, d);
-        R.rpos[q] = s + i;
-    }
+    const uint64_t sh = (uint64_t)b * REV_SHARDS + (a % REV_SHARDS);
+    const uint32_t q = atomicAdd(&R.cur[sh], 1u);
+    R.rrec[q] = make_uint4(a, t, s, d);
+    R.rpos[q] = s + i;
 }
 
 __device__ __forceinline__ void emit_sorted(unsigned long long v, uint32_t idx, uint32_t a, uint32_t seg, uint32_t d,
                                             uint32_t* nbr, uint32_t* tim, const RevOut& R) {
     if (idx < d) {
-        nbr[seg + idx] = (uint32_t)(v >> 32);
-        tim[seg + idx] = (uint32_t)v;
-        emit_rev(R, a, seg, d, idx, (uint32_t)(v >> 32), (uint32_t)v);
+        const uint32_t b = (uint32_t)(v >> 32), t = (uint32_t)v & ~REV_BIT;
+        nbr[seg + idx] = b;
+        tim[seg + idx] = t;
+        if ((uint32_t)v & REV_BIT) emit_rev(R, a, seg, d, idx, b, t);
     }
 }
 
@@ -699,7 +747,6 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)st,
                        (uint64_t)(sizeof(BuildStats) / 4), 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, dout, (uint64_t)n, 0u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, cursor, (uint64_t)n, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, ahist, (uint64_t)n, 0u);
 
     // degrees: partition endpoints by id bucket (reusing `packed` as the partition), count in LDS
@@ -712,17 +759,20 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     hipLaunchKernelGGL(k_deg_count, dim3(grid_for(2 * E, DEG_SLICE, 4096)), dim3(1024), 0, s, ends, bscan, D.nblk,
                        D.NB, D.shift, n, deg);
 
-    hipLaunchKernelGGL(k_orient_count, dim3(gE), dim3(256), 0, s, e2, E, n, deg, dout);
+    // orientation of every edge into `alt` (free until the large-segment sort)
+    uint2* ab = (uint2*)alt;
+    hipLaunchKernelGGL(k_orient_count, dim3(gE), dim3(256), 0, s, e2, E, n, deg, dout, ab);
     if (scan_u32(dout, n, part, off, s) != hipSuccess) return REPT_EDEVICE;
+    hipLaunchKernelGGL(k_copy_u32, dim3(gN), dim3(256), 0, s, off, (uint64_t)n, cursor);
     const uint64_t nsh = (uint64_t)n * REV_SHARDS;
     const uint32_t gS = grid_for(nsh, 256, cap);
     hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
-    hipLaunchKernelGGL(k_scatter, dim3(gE), dim3(256), 0, s, e2, E, n, deg, dout, off, cursor, packed, scnt, st);
+    hipLaunchKernelGGL(k_scatter, dim3(gE), dim3(256), 0, s, ab, E, dout, cursor, packed, scnt, st);
     // reverse lists: shard starts from k_scatter's counts; the sorts place the records
     if (scan_u32(scnt, nsh, part, sofs, s) != hipSuccess) return REPT_EDEVICE;
     hipLaunchKernelGGL(k_rev_roff, dim3(gN), dim3(256), 0, s, sofs, n, roff, st);
-    hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
-    const RevOut RO{off, scnt, sofs, rrec, rpos};
+    hipLaunchKernelGGL(k_copy_u32, dim3(gS), dim3(256), 0, s, sofs, nsh, scnt);  // shard cursors
+    const RevOut RO{scnt, rrec, rpos};
     hipLaunchKernelGGL(k_classify, dim3(gA), dim3(256), 0, s, off, n, ahist, medium, large, st);
     hipLaunchKernelGGL(k_sort_small, dim3(grid_for((uint64_t)n, 4, cap * 4)), dim3(256), 0, s, off, n, packed,
                        nbr, tim, RO, st);
