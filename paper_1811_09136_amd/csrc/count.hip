@@ -80,6 +80,8 @@ __host__ __device__ inline uint32_t log2u(uint32_t p) {
     return l;
 }
 __host__ __device__ inline uint32_t up16(uint32_t x) { return (x + 15u) & ~15u; }
+// 16-bit slots per staged edge: G padded to 1, 2, 4 or 8 (the slot table's row width)
+__host__ __device__ inline uint32_t slot_width(uint32_t G) { return G <= 1 ? 1u : (G <= 2 ? 2u : (G <= 4 ? 4u : 8u)); }
 
 // ---- LDS layout (shared by host sizing and device carving) --------------------------------
 // [per-wave misc] x nwaves, then one union region: the workgroup's heavy team area or the
@@ -98,11 +100,11 @@ __host__ __device__ inline Area area_layout(uint32_t DW, uint32_t DB, uint32_t G
     A.hidx = p; p = up16(p + 2 * H);
     A.ew = p; p = up16(p + 4 * DW);
     A.et = p; p = up16(p + 4 * DW);
-    A.wslot = p; p = up16(p + 2 * G * DW);
+    A.wslot = p; p = up16(p + 2 * slot_width(G) * DW);
     A.cntw = p; p = up16(p + 4 * G * DW);
     A.eb = p; p = up16(p + 4 * DB);
     A.etb = p; p = up16(p + 4 * DB);
-    A.bslot = p; p = up16(p + 2 * G * DB);
+    A.bslot = p; p = up16(p + 2 * slot_width(G) * DB);
     A.cntb = p; p = up16(p + 4 * G * DB);
     A.bpos = p; p = up16(p + 8 * (DB + 1));  // (list offset, first item) per staged list
     A.red = p; p = up16(p + 4 * 64);
@@ -145,11 +147,11 @@ struct TeamView {
     uint16_t* hidx;
     uint32_t* ew;
     uint32_t* et;
-    uint16_t* wslot;
+    uint16_t* wslot;  // [DW][gs] slot rows of the W entries
     uint32_t* cntw;
     uint32_t* eb;
     uint32_t* etb;
-    uint16_t* bslot;
+    uint16_t* bslot;  // [DB][gs] slot rows of the B entries
     uint32_t* cntb;
     uint2* bpos;  // .x: offset of b's list, .y: index of its first item in the chunk's walk
     uint32_t* red;
@@ -280,8 +282,73 @@ __device__ __forceinline__ void load_slots(const uint16_t* tab, uint32_t gs, uin
         hi = ldg((const uint64_t*)tab + 2 * (uint64_t)p + 1);
     }
 }
-__device__ __forceinline__ uint32_t slot_in(uint64_t lo, uint64_t hi, uint32_t g) {
-    return (uint32_t)((g < 4 ? lo >> (16 * g) : hi >> (16 * (g - 4))) & 0xffffu);
+// staged slot rows in LDS, in the slot table's format; GS: row width known at compile time
+template <uint32_t GS>
+__device__ __forceinline__ void lds_row_t(const uint16_t* rows, uint32_t i, uint64_t& lo, uint64_t& hi) {
+    hi = 0;
+    if (GS == 1) {
+        lo = rows[i];
+    } else if (GS == 2) {
+        lo = ((const uint32_t*)rows)[i];
+    } else if (GS == 4) {
+        lo = ((const uint64_t*)rows)[i];
+    } else {
+        const uint4 r = ((const uint4*)rows)[i];
+        lo = ((uint64_t)r.y << 32) | r.x;
+        hi = ((uint64_t)r.w << 32) | r.z;
+    }
+}
+template <uint32_t GS>
+__device__ __forceinline__ void load_slots_t(const uint16_t* tab, uint32_t p, uint64_t& lo, uint64_t& hi) {
+    hi = 0;
+    if (GS == 1) {
+        lo = ldg(tab + p);
+    } else if (GS == 2) {
+        lo = ldg((const uint32_t*)tab + p);
+    } else if (GS == 4) {
+        lo = ldg((const uint64_t*)tab + p);
+    } else {
+        lo = ldg((const uint64_t*)tab + 2 * (uint64_t)p);
+        hi = ldg((const uint64_t*)tab + 2 * (uint64_t)p + 1);
+    }
+}
+__device__ __forceinline__ void lds_row(const uint16_t* rows, uint32_t gs, uint32_t i, uint64_t& lo, uint64_t& hi) {
+    hi = 0;
+    if (gs == 1) {
+        lo = rows[i];
+    } else if (gs == 2) {
+        lo = ((const uint32_t*)rows)[i];
+    } else if (gs == 4) {
+        lo = ((const uint64_t*)rows)[i];
+    } else {
+        lo = ((const uint64_t*)rows)[2 * i];
+        hi = ((const uint64_t*)rows)[2 * i + 1];
+    }
+}
+__device__ __forceinline__ void store_row(uint16_t* rows, uint32_t gs, uint32_t i, uint64_t lo, uint64_t hi) {
+    if (gs == 1) {
+        rows[i] = (uint16_t)lo;
+    } else if (gs == 2) {
+        ((uint32_t*)rows)[i] = (uint32_t)lo;
+    } else if (gs == 4) {
+        ((uint64_t*)rows)[i] = lo;
+    } else {
+        ((uint64_t*)rows)[2 * i] = lo;
+        ((uint64_t*)rows)[2 * i + 1] = hi;
+    }
+}
+// bit 16g + 15 set for each 16-bit field g where x and y agree (exact per field: adding 0x7fff
+// to a field's low 15 bits cannot carry into the next field)
+__device__ __forceinline__ uint64_t eq_fields(uint64_t x, uint64_t y) {
+    constexpr uint64_t kLow15 = 0x7fff7fff7fff7fffull;
+    const uint64_t z = x ^ y;
+    return ~(((z & kLow15) + kLow15) | z) & ~kLow15;
+}
+// field bits (bit 16g + 15) of the groups g < G, in the low and high words of a row
+__device__ __forceinline__ void group_masks(uint32_t G, uint64_t& lo, uint64_t& hi) {
+    constexpr uint64_t kHigh = 0x8000800080008000ull;
+    lo = G >= 4 ? kHigh : kHigh & ((1ull << (16 * G)) - 1ull);
+    hi = G <= 4 ? 0ull : (G >= 8 ? kHigh : kHigh & ((1ull << (16 * (G - 4))) - 1ull));
 }
 
 // ---- LDS hash table of a's list: 2-slot buckets probed linearly; keys w + 1, 0 = empty.
@@ -364,7 +431,8 @@ __device__ __forceinline__ uint32_t team_sum(uint32_t v, uint32_t* red) {
 // entry k, list position p): the triangle (a, b = eb[ib], w = ew[k]) with times t_ab = etb[ib],
 // t_aw = et[k], t_bw = tim[p].  Its first two edges by time decide the processor per group:
 // edges at a have their slots staged; the slots of {b, w} come from the slot table.
-__device__ void drain_hits(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a, uint32_t qn) {
+template <uint32_t GS>
+__device__ void drain_hits_t(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a, uint32_t qn) {
     const uint32_t lane = lane_id();
     for (uint32_t q0 = 0; q0 < qn; q0 += 64) {
         const uint32_t q = q0 + lane;
@@ -374,26 +442,39 @@ __device__ void drain_hits(const JobRegs& J, const TeamView& T, const WaveView& 
             const uint32_t p = V.qp[q];
             const uint32_t b = T.eb[ib], w = T.ew[k];
             const uint32_t tab = T.etb[ib], taw = T.et[k], tbw = ldg(J.tim + p);
-            // slots of {b, w}, the edge at position p; loaded with its time (one latency), used
-            // when it is one of the first two edges
+            // slots of {b, w}, the edge at position p, loaded with its time (one latency): the
+            // branch below depends on both
             uint64_t blo, bhi;
-            load_slots(J.tab, J.gs, p, blo, bhi);
+            load_slots_t<GS>(J.tab, p, blo, bhi);
+            uint64_t alo, ahi, wlo, whi;
+            lds_row_t<GS>(T.bslot, ib, alo, ahi);
+            lds_row_t<GS>(T.wslot, k, wlo, whi);
             // which edge arrived last: 0 = {a,b}, 1 = {a,w}, 2 = {b,w} (times are distinct)
             const uint32_t last = (tab > taw && tab > tbw) ? 0u : (taw > tbw ? 1u : 2u);
             const uint32_t tl = last == 0 ? tab : (last == 1 ? taw : tbw);
-            if (tl >= J.t0 && tl < J.t1) {
-                for (uint32_t g = 0; g < J.G; ++g) {
-                    const uint32_t sab = T.bslot[g * T.DB + ib], saw = T.wslot[g * T.DW + k];
-                    uint32_t s1, s2;
-                    if (last == 2) {
-                        s1 = sab;
-                        s2 = saw;
+            // slot rows of the first two edges; the groups where their slots agree, all at once
+            const uint64_t xlo = last == 0 ? wlo : alo, xhi = last == 0 ? whi : ahi;
+            const uint64_t ylo = last == 2 ? wlo : blo, yhi = last == 2 ? whi : bhi;
+            uint64_t glo, ghi;
+            group_masks(J.G, glo, ghi);
+            if (!(tl >= J.t0 && tl < J.t1)) glo = ghi = 0;
+            uint64_t mlo = eq_fields(xlo, ylo) & glo, mhi = GS == 8 ? eq_fields(xhi, yhi) & ghi : 0ull;
+            {
+                while (mlo | mhi) {
+                    uint32_t g, s1;
+                    if (mlo) {
+                        const uint32_t bit = (uint32_t)__builtin_ctzll(mlo);
+                        g = bit >> 4;
+                        s1 = (uint32_t)(xlo >> (bit - 15)) & 0xffffu;
+                        mlo &= mlo - 1;
                     } else {
-                        s1 = last == 0 ? saw : sab;
-                        s2 = slot_in(blo, bhi, g);
+                        const uint32_t bit = (uint32_t)__builtin_ctzll(mhi);
+                        g = 4 + (bit >> 4);
+                        s1 = (uint32_t)(xhi >> (bit - 15)) & 0xffffu;
+                        mhi &= mhi - 1;
                     }
                     const uint32_t ck = (g + 1 < J.G) ? J.m : J.last_ck;
-                    if (s1 == s2 && s1 < ck) {
+                    if (s1 < ck) {
                         const uint32_t proc = g * J.m + s1;
                         if (J.use_hist) atomicAdd(&V.hist[proc], 1u);
                         else add64(J.global + proc, 1);
@@ -412,6 +493,15 @@ __device__ void drain_hits(const JobRegs& J, const TeamView& T, const WaveView& 
         }
     }
     wave_sync();
+}
+
+// the drain for the job's slot-row width (uniform over the wavefront)
+__device__ __forceinline__ void drain_hits(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a,
+                                           uint32_t qn) {
+    if (J.gs == 1) drain_hits_t<1>(J, T, V, a, qn);
+    else if (J.gs == 2) drain_hits_t<2>(J, T, V, a, qn);
+    else if (J.gs == 4) drain_hits_t<4>(J, T, V, a, qn);
+    else drain_hits_t<8>(J, T, V, a, qn);
 }
 
 // popcount of the bits of `m` below this lane
@@ -565,10 +655,8 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
             T.et[i] = ldg(J.tim + s + ws + i);
             uint64_t lo, hi;
             load_slots(J.tab, J.gs, s + ws + i, lo, hi);
-            for (uint32_t g = 0; g < G; ++g) {
-                T.wslot[g * T.DW + i] = (uint16_t)slot_in(lo, hi, g);
-                T.cntw[g * T.DW + i] = 0;
-            }
+            store_row(T.wslot, J.gs, i, lo, hi);
+            for (uint32_t g = 0; g < G; ++g) T.cntw[g * T.DW + i] = 0;
             hash_insert(T.hkey, T.hidx, kbits, w, i);
         }
         team_sync<BLOCK>();
@@ -612,12 +700,10 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                     // an own pair {a, b} is also a W entry when it falls in the current W chunk
                     const bool staged = e >= ws && e < ws + wn;
                     uint64_t lo = 0, hi = 0;
-                    if (!staged) load_slots(J.tab, J.gs, pab, lo, hi);
-                    for (uint32_t g = 0; g < G; ++g) {
-                        T.bslot[g * T.DB + pos] =
-                            staged ? T.wslot[g * T.DW + (e - ws)] : (uint16_t)slot_in(lo, hi, g);
-                        T.cntb[g * T.DB + pos] = 0;
-                    }
+                    if (staged) lds_row(T.wslot, J.gs, e - ws, lo, hi);
+                    else load_slots(J.tab, J.gs, pab, lo, hi);
+                    store_row(T.bslot, J.gs, pos, lo, hi);
+                    for (uint32_t g = 0; g < G; ++g) T.cntb[g * T.DB + pos] = 0;
                 }
                 nb += tot_nb;
                 items += tot_items;
