@@ -2,7 +2,9 @@
 
 One step = the whole hot path over one synthetic stream already resident in HBM:
 validate + orient + build (rept_build), the counting pass for all c processors (rept_count),
-the device-to-host copy of the integer counters and the FP64 estimators (rept_estimate).
+the reduction of the local rows to node sums on the device (rept_reduce_local), the
+device-to-host copy of the c global counters and the n sums, and the FP64 estimators on the
+host (rept_estimate_sums).
 
 Default workload: Chung-Lu power-law stream, 1,000,000 nodes, 20,000,000 edges, exponent 2.1,
 random order, m = 10 (p = 0.1), c = 40 (four hash groups).  Prints one JSON line.
@@ -231,8 +233,9 @@ def main():
     scratch = torch.empty(sbytes, dtype=torch.uint8, device=dev)
     glob = torch.empty(c, dtype=torch.int64, device=dev)
     loc = torch.empty((rows, n), dtype=torch.int64, device=dev)
+    sums = torch.empty(n, dtype=torch.int64, device=dev)
     h_glob = torch.empty(c, dtype=torch.int64, pin_memory=True)
-    h_loc = torch.empty((rows, n), dtype=torch.int64, pin_memory=True)
+    h_sums = torch.empty(n, dtype=torch.int64, pin_memory=True)
     h_tau_v = np.zeros(n, dtype=np.float64)  # local estimators, written by rept_estimate
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
@@ -254,10 +257,11 @@ def main():
         ev0.record(stream)
         rept.rept_count(h, params, glob.data_ptr(), loc.data_ptr(), ws.data_ptr(), wbytes, sp)
         ev1.record(stream)
+        rept.rept_reduce_local(loc.data_ptr(), rows, n, sums.data_ptr(), sp)
         h_glob.copy_(glob, non_blocking=True)
-        h_loc.copy_(loc, non_blocking=True)
+        h_sums.copy_(sums, non_blocking=True)
         stream.synchronize()
-        tau_hat, tau_v = rept.rept_estimate(n, params, h_glob.numpy(), h_loc.numpy(), h_tau_v)
+        tau_hat, tau_v = rept.rept_estimate_sums(n, params, h_glob.numpy(), h_sums.numpy(), h_tau_v)
         info = rept.rept_graph_get_info(h)
         rept.rept_destroy(h)
         if record:

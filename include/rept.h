@@ -171,6 +171,27 @@ rept_status rept_estimate(uint32_t n, const rept_params* params, const int64_t* 
                           const int64_t* local, double* tau_hat, double* tau_v_hat);
 
 /*
+ * The same estimators from node sums already reduced over the local rows (rept_reduce_local):
+ * sums[v] = S_v.  Results are identical to rept_estimate on the rows.
+ *   global: host int64[c]; sums: host int64[n] or NULL; tau_v_hat: host double[n] or NULL.
+ * Errors: as rept_estimate (ERANGE if a sum is negative or >= 2^53).
+ */
+rept_status rept_estimate_sums(uint32_t n, const rept_params* params, const int64_t* global,
+                               const int64_t* sums, double* tau_hat, double* tau_v_hat);
+
+/*
+ * The reduction of the local estimator's sums on the device (Sections III-A, III-B: S_v sums
+ * a node's counters over all processors): sums[v] = sum over r < rows of local[r][v], exact in
+ * int64, so that n counters rather than rows x n cross to the host.
+ *   local: device int64[rows][n]; sums: device int64[n], either local's first row (in place) or
+ *          memory that does not overlap local.  Both 8-byte aligned.
+ * Asynchronous on `stream`.  Errors: EINVAL (null or misaligned pointers, rows or n zero),
+ * EDEVICE.
+ */
+rept_status rept_reduce_local(const int64_t* local, uint32_t rows, uint32_t n, int64_t* sums,
+                              void* stream);
+
+/*
  * The edge-to-processor hash of every stream edge for every group (Section III-A: h(u, v)
  * picks the processor that stores the edge; Section III-B: one independent h_k per group).
  *   edges: device uint32[num_edges][2]; slots: device uint32[G][num_edges].

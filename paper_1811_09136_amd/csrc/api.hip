@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
+#include <functional>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -259,8 +261,78 @@ rept_status rept_count_range(const rept_graph* graph, const rept_params* params,
     return count_one(graph, params, t0, t1, true, global, local, workspace, workspace_bytes, stream);
 }
 
-rept_status rept_estimate(uint32_t n, const rept_params* params, const int64_t* global, const int64_t* local,
-                          double* tau_hat, double* tau_v_hat) {
+namespace {
+
+// Host workers for the estimators: started on first use and kept for the life of the process
+// (idle workers wait on a condition variable), so a call pays no thread start-up.  The pool is
+// never destroyed: threads still waiting at exit end with the process.
+class HostPool {
+   public:
+    static HostPool& get() {
+        static HostPool* pool = new HostPool();
+        return *pool;
+    }
+    uint32_t threads() const { return (uint32_t)workers_.size() + 1; }
+    // fn(k) for every k in [0, parts), on the workers and the calling thread; returns when all
+    // parts are done.  One job runs at a time.
+    void run(uint32_t parts, const std::function<void(uint32_t)>& fn) {
+        std::lock_guard<std::mutex> one(call_);
+        if (workers_.empty() || parts <= 1) {
+            for (uint32_t k = 0; k < parts; ++k) fn(k);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            fn_ = &fn;
+            parts_ = parts;
+            next_ = 0;
+            active_ = (uint32_t)workers_.size();
+            ++gen_;
+        }
+        start_.notify_all();
+        for (uint32_t k; (k = next_.fetch_add(1)) < parts;) fn(k);
+        std::unique_lock<std::mutex> lk(mu_);
+        done_.wait(lk, [&] { return active_ == 0; });
+        fn_ = nullptr;
+    }
+
+   private:
+    HostPool() {
+        const uint32_t hw = std::max(1u, std::thread::hardware_concurrency());
+        const uint32_t total = std::min(16u, hw);
+        for (uint32_t i = 1; i < total; ++i) workers_.emplace_back([this] { work(); });
+    }
+    void work() {
+        uint64_t seen = 0;
+        for (;;) {
+            const std::function<void(uint32_t)>* fn;
+            uint32_t parts;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                start_.wait(lk, [&] { return gen_ != seen; });
+                seen = gen_;
+                fn = fn_;
+                parts = parts_;
+            }
+            for (uint32_t k; (k = next_.fetch_add(1)) < parts;) (*fn)(k);
+            std::lock_guard<std::mutex> lk(mu_);
+            if (--active_ == 0) done_.notify_one();
+        }
+    }
+    std::vector<std::thread> workers_;
+    std::mutex call_, mu_;
+    std::condition_variable start_, done_;
+    const std::function<void(uint32_t)>* fn_ = nullptr;
+    uint32_t parts_ = 0, active_ = 0;
+    std::atomic<uint32_t> next_{0};
+    uint64_t gen_ = 0;
+};
+
+// The estimators' common part.  S = sum of global (exact int64), tau_hat = RN(RN(S m^2) / c);
+// with `local` (rows x n, row stride n) and tau_v_hat: S_v = sum over the rows at v (exact),
+// tau_v_hat[v] = RN(RN(S_v m^2) / c).  Node ranges are independent and run on the host pool.
+rept_status estimate_core(uint32_t n, const rept_params* params, const int64_t* global, const int64_t* local,
+                          uint32_t rows, double* tau_hat, double* tau_v_hat) {
     if (!params_ok(params) || n == 0 || !global || !tau_hat) return REPT_EINVAL;
     const uint32_t m = params->m, c = params->c;
     if (c > m && c % m != 0) return REPT_ENOTSUP;
@@ -275,55 +347,64 @@ rept_status rept_estimate(uint32_t n, const rept_params* params, const int64_t* 
     }
     double* tv = tau_v_hat;
     if (tv && local) {
-        // per node: S_v summed exactly in int64 over the rows, then one rounding for the product
-        // and one for the quotient.  Node ranges are independent, so they are split over host
-        // threads; each thread reads its range of every row (sequential within a row).
-        const uint32_t rows = rept_local_rows(params);
         std::atomic<bool> bad{false};
-        auto run = [&](uint32_t v0, uint32_t v1) {
+        constexpr uint32_t kPart = 32768;  // nodes per part of the node range
+        const uint32_t parts = (uint32_t)(((uint64_t)n + kPart - 1) / kPart);
+        const std::function<void(uint32_t)> part = [&](uint32_t k) {
+            const uint32_t v0 = k * kPart, v1 = std::min<uint64_t>((uint64_t)v0 + kPart, n);
             constexpr uint32_t kBlock = 4096;  // nodes per pass, kept in a stack buffer
             int64_t acc[kBlock];
             for (uint32_t b0 = v0; b0 < v1; b0 += kBlock) {
                 const uint32_t b1 = std::min(v1, b0 + kBlock), nb = b1 - b0;
+                bool ok = true;
                 for (uint32_t i = 0; i < nb; ++i) {
                     const int64_t x = local[b0 + i];
-                    if (x < 0 || x >= limit) bad = true;
+                    ok &= x >= 0 && x < limit;
                     acc[i] = x;
                 }
                 for (uint32_t r = 1; r < rows; ++r) {
                     const int64_t* row = local + (uint64_t)r * n + b0;
                     for (uint32_t i = 0; i < nb; ++i) {
                         const int64_t x = row[i];
-                        if (x < 0 || x >= limit - acc[i]) {
-                            bad = true;
-                            return;
-                        }
-                        acc[i] += x;
+                        ok &= x >= 0 && x < limit - acc[i];
+                        acc[i] += ok ? x : 0;
                     }
                 }
-                if (bad) return;
+                if (!ok) {
+                    bad = true;
+                    return;
+                }
                 for (uint32_t i = 0; i < nb; ++i) {
                     const double prod = (double)acc[i] * num;
                     tv[b0 + i] = prod / den;
                 }
             }
         };
-        const uint64_t work = (uint64_t)rows * n;
-        uint32_t nt = work < (1u << 20) ? 1u : std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
-        if (nt <= 1) {
-            run(0, n);
-        } else {
-            std::vector<std::thread> pool;
-            for (uint32_t t = 0; t < nt; ++t) {
-                const uint32_t v0 = (uint32_t)((uint64_t)n * t / nt), v1 = (uint32_t)((uint64_t)n * (t + 1) / nt);
-                pool.emplace_back(run, v0, v1);
-            }
-            for (auto& th : pool) th.join();
-        }
+        HostPool::get().run(parts, part);
         if (bad) return REPT_ERANGE;
     }
     const double prod = (double)S * num;
     *tau_hat = prod / den;
+    return REPT_OK;
+}
+
+}  // namespace
+
+rept_status rept_estimate(uint32_t n, const rept_params* params, const int64_t* global, const int64_t* local,
+                          double* tau_hat, double* tau_v_hat) {
+    if (!params_ok(params)) return REPT_EINVAL;
+    return estimate_core(n, params, global, local, rept_local_rows(params), tau_hat, tau_v_hat);
+}
+
+rept_status rept_estimate_sums(uint32_t n, const rept_params* params, const int64_t* global, const int64_t* sums,
+                               double* tau_hat, double* tau_v_hat) {
+    return estimate_core(n, params, global, sums, 1u, tau_hat, tau_v_hat);
+}
+
+rept_status rept_reduce_local(const int64_t* local, uint32_t rows, uint32_t n, int64_t* sums, void* stream) {
+    if (!local || !sums || rows == 0 || n == 0) return REPT_EINVAL;
+    if (((uintptr_t)local | (uintptr_t)sums) & 7u) return REPT_EINVAL;
+    if (rept_launch_reduce(local, rows, n, sums, (hipStream_t)stream) != hipSuccess) return REPT_EDEVICE;
     return REPT_OK;
 }
 

@@ -118,6 +118,7 @@ hipError_t rept_launch_single(uint8_t* ctrl, const BatchHeader& hdr, const JobDe
                               hipStream_t stream);
 // slots per stored edge in a slot table for G groups (1, 2, 4 or 8)
 inline uint32_t rept_slot_stride(uint32_t G) { return G <= 1 ? 1u : (G <= 2 ? 2u : (G <= 4 ? 4u : 8u)); }
+hipError_t rept_launch_reduce(const int64_t* local, uint32_t rows, uint32_t n, int64_t* sums, hipStream_t stream);
 hipError_t rept_launch_slots(const uint64_t* hp, uint32_t G, uint32_t m, const uint32_t* edges,
                              uint64_t E, uint32_t* slots, hipStream_t stream);
 // LDS bytes of the counting kernel for a launch shape

@@ -959,6 +959,16 @@ __global__ void k_slots(HashParams P, uint32_t G, uint32_t m, const uint2* __res
     }
 }
 
+// sums[v] = sum over the rows of local[r][v] (exact int64).  Each thread reads every row at its
+// own v before writing sums[v], so sums may be local's first row.
+__global__ void k_reduce_rows(const int64_t* local, uint32_t rows, uint32_t n, int64_t* sums) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        int64_t acc = 0;
+        for (uint32_t r = 0; r < rows; ++r) acc += local[(uint64_t)r * n + v];
+        sums[v] = acc;
+    }
+}
+
 bool g_attr_set = false;
 
 hipError_t report(hipError_t e, const char* what) {
@@ -1026,6 +1036,14 @@ hipError_t rept_launch_batch(void* ws, const BatchHeader& h, hipStream_t s) {
 hipError_t rept_launch_single(uint8_t* ctrl, const BatchHeader& hdr, const JobDev& job, hipStream_t s) {
     hipLaunchKernelGGL(k_write_ctrl, dim3(1), dim3(64), 0, s, ctrl, hdr, job);
     return launch_common(ctrl, hdr, s);
+}
+
+hipError_t rept_launch_reduce(const int64_t* local, uint32_t rows, uint32_t n, int64_t* sums, hipStream_t s) {
+    (void)hipGetLastError();
+    uint32_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_reduce_rows, dim3(blocks), dim3(256), 0, s, local, rows, n, sums);
+    return hipGetLastError();
 }
 
 hipError_t rept_launch_slots(const uint64_t* hp, uint32_t G, uint32_t m, const uint32_t* edges, uint64_t E,

@@ -79,6 +79,8 @@ def lib() -> ctypes.CDLL:
             "rept_count": ([vp, P(rept_params), vp, vp, vp, sz, vp], i32),
             "rept_count_range": ([vp, P(rept_params), u64, u64, vp, vp, vp, sz, vp], i32),
             "rept_estimate": ([u32, P(rept_params), vp, vp, vp, vp], i32),
+            "rept_estimate_sums": ([u32, P(rept_params), vp, vp, vp, vp], i32),
+            "rept_reduce_local": ([vp, u32, u32, vp, vp], i32),
             "rept_hash_slots": ([P(rept_params), vp, u64, vp, vp], i32),
             "rept_batch_workspace_size": ([u32, P(sz)], i32),
             "rept_batch_prepare": ([P(rept_job), u32, P(rept_tuning), vp, sz, vp], i32),
@@ -98,7 +100,7 @@ def lib() -> ctypes.CDLL:
 
 EXPORTED = ["rept_local_rows", "rept_query_sizes", "rept_build", "rept_graph_get_info",
             "rept_count_workspace_size", "rept_count",
-            "rept_count_range", "rept_estimate", "rept_hash_slots", "rept_batch_workspace_size",
+            "rept_count_range", "rept_estimate", "rept_estimate_sums", "rept_reduce_local", "rept_hash_slots", "rept_batch_workspace_size",
             "rept_batch_prepare", "rept_batch_launch", "rept_batch_count", "rept_destroy", "rept_status_str",
             "rept_device_cus"]
 
@@ -206,6 +208,35 @@ def rept_estimate(n: int, params: Params, glob: np.ndarray, loc: np.ndarray | No
     _check(lib().rept_estimate(n, ctypes.byref(p), g.ctypes.data, lp, ctypes.addressof(th),
                                None if tv is None else tv.ctypes.data), "rept_estimate")
     return th.value, tv
+
+
+def rept_estimate_sums(n: int, params: Params, glob: np.ndarray, sums: np.ndarray | None, tau_v_out=None):
+    """Host FP64 estimators from node sums S_v (rept_reduce_local's output); returns
+    (tau_hat, tau_v_hat or None), identical to rept_estimate on the rows."""
+    p = params.c_struct()
+    g = np.ascontiguousarray(glob, dtype=np.int64)
+    th = ctypes.c_double(0.0)
+    tv = None
+    sp = None
+    if sums is not None:
+        sv = np.ascontiguousarray(sums, dtype=np.int64)
+        if sv.shape != (n,):
+            raise ValueError("sums must hold n values")
+        if tau_v_out is None:
+            tv = np.empty(n, dtype=np.float64)
+        else:
+            tv = tau_v_out
+            if tv.dtype != np.float64 or tv.shape != (n,) or not tv.flags.c_contiguous:
+                raise ValueError("tau_v_out must be a contiguous float64 array of n values")
+        sp = sv.ctypes.data
+    _check(lib().rept_estimate_sums(n, ctypes.byref(p), g.ctypes.data, sp, ctypes.addressof(th),
+                                    None if tv is None else tv.ctypes.data), "rept_estimate_sums")
+    return th.value, tv
+
+
+def rept_reduce_local(local_ptr: int, rows: int, n: int, sums_ptr: int, stream_ptr: int | None):
+    """sums[v] = sum of the rows of local at v, on the device (exact int64)."""
+    _check(lib().rept_reduce_local(local_ptr, rows, n, sums_ptr, stream_ptr), "rept_reduce_local")
 
 
 def rept_hash_slots(params: Params, edges_ptr: int, num_edges: int, slots_ptr: int, stream_ptr: int | None):

@@ -103,3 +103,58 @@ def test_estimate_large_zero_ulp_and_range_errors():
     with pytest.raises(rept.ReptError) as ei:
         rept.rept_estimate(n, rept.Params(m, c, 0), glob, over)
     assert ei.value.code == rept.REPT_ERANGE
+
+
+@pytest.mark.parametrize("m,c", [(10, 40), (7, 3), (10, 10)])
+def test_estimate_sums_zero_ulp_against_oracle(m, c):
+    """Estimators from node sums S_v (the device reduction's output) equal the oracle's on the
+    rows, bit for bit, at a size split over the host pool; a sum at 2^53 or below 0 is ERANGE."""
+    from paper_1811_09136_amd import rept
+    rng = np.random.default_rng(11 * m + c)
+    n = 200_003
+    G = -(-c // m)
+    glob = rng.integers(0, 2**38, size=c)
+    loc = rng.integers(0, 2**40, size=(G, n))
+    sums = loc.sum(axis=0)
+    th, tv = rept.rept_estimate_sums(n, rept.Params(m, c, 0), glob, sums)
+    oth, otv = oracle.estimate(n, m, c, glob, loc)
+    assert th == oth and np.array_equal(tv.view(np.uint64), otv.view(np.uint64))
+    th0, tv0 = rept.rept_estimate_sums(n, rept.Params(m, c, 0), glob, None)
+    assert th0 == oth and tv0 is None
+    for v, val in [(n - 1, 2**53), (0, -1), (n // 3, 2**53 + 5)]:
+        bad = sums.copy()
+        bad[v] = val
+        with pytest.raises(rept.ReptError) as ei:
+            rept.rept_estimate_sums(n, rept.Params(m, c, 0), glob, bad)
+        assert ei.value.code == rept.REPT_ERANGE
+
+
+def test_estimators_from_concurrent_host_threads():
+    """The estimators share one host worker pool: calls from several threads at once each get
+    their own results."""
+    import threading
+    from paper_1811_09136_amd import rept
+    n, m, c = 150_001, 10, 40
+    cases = []
+    for k in range(4):
+        rng = np.random.default_rng(100 + k)
+        glob = rng.integers(0, 2**30, size=c)
+        loc = rng.integers(0, 2**30, size=(4, n))
+        cases.append((glob, loc, oracle.estimate(n, m, c, glob, loc)))
+    errors = []
+
+    def worker(k):
+        glob, loc, (oth, otv) = cases[k]
+        for _ in range(5):
+            th, tv = rept.rept_estimate(n, rept.Params(m, c, 0), glob, loc)
+            th2, tv2 = rept.rept_estimate_sums(n, rept.Params(m, c, 0), glob, loc.sum(axis=0))
+            if not (th == oth == th2 and np.array_equal(tv.view(np.uint64), otv.view(np.uint64))
+                    and np.array_equal(tv2.view(np.uint64), otv.view(np.uint64))):
+                errors.append(k)
+
+    ts = [threading.Thread(target=worker, args=(k,)) for k in range(4)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errors

@@ -250,3 +250,54 @@ def test_build_statistics_match_definitions(cuda, kind):
     assert (i.oriented_work, i.num_reverse, i.sum_out_sq, i.max_out_degree, i.num_apex) == \
         (ref["work"], ref["reverse"], ref["sum_out_sq"], ref["max_out"], ref["units"])
     g.close()
+
+
+def test_reduce_local_exact(cuda):
+    """The device reduction of the local rows (exact int64), into its own buffer and in place
+    over the first row; bad pointers are EINVAL before any launch."""
+    import torch
+    from paper_1811_09136_amd import rept
+    rng = np.random.default_rng(5)
+    for rows, n in [(1, 1), (4, 1000), (3, 70001), (40, 5003)]:
+        _say(f"reduce_local rows={rows} n={n}")
+        loc = rng.integers(0, 2**45, size=(rows, n))
+        d = torch.from_numpy(loc).to(cuda)
+        out = torch.full((n,), -1, dtype=torch.int64, device=cuda)
+        rept.rept_reduce_local(d.data_ptr(), rows, n, out.data_ptr(), None)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), loc.sum(axis=0))
+        rept.rept_reduce_local(d.data_ptr(), rows, n, d.data_ptr(), None)
+        torch.cuda.synchronize()
+        assert np.array_equal(d[0].cpu().numpy(), loc.sum(axis=0))
+        assert np.array_equal(d[1:].cpu().numpy(), loc[1:])
+    d = torch.zeros(8, dtype=torch.int64, device=cuda)
+    for args in [(0, 1, 1, d.data_ptr()), (d.data_ptr(), 0, 1, d.data_ptr()), (d.data_ptr(), 1, 0, d.data_ptr()),
+                 (d.data_ptr() + 4, 1, 1, d.data_ptr())]:
+        with pytest.raises(rept.ReptError) as ei:
+            rept.rept_reduce_local(*args, None)
+        assert ei.value.code == rept.REPT_EINVAL
+
+
+@pytest.mark.parametrize("m,c,per_proc", [(10, 40, False), (3, 7, True)])
+def test_count_reduce_estimate_path(cuda, m, c, per_proc):
+    """Count, reduce the local rows on the device, estimate from the sums: the estimators equal
+    the oracle's on the oracle's rows (0 ulp)."""
+    import torch
+    from paper_1811_09136_amd import rept
+    n = 3000
+    e = synth.chung_lu(n, 30000, 2.1, 300.0, seed=31, order_seed=32)
+    _say(f"count_reduce_estimate chung_lu n={n} E={len(e)} m={m} c={c} per_proc={per_proc}")
+    p = rept.Params(m, c, 77, per_proc)
+    g = rept.Graph(rept.to_device_edges(e, cuda), n)
+    glob, loc = g.count(p)
+    sums = torch.empty(n, dtype=torch.int64, device=cuda)
+    rept.rept_reduce_local(loc.data_ptr(), p.rows, n, sums.data_ptr(), None)
+    torch.cuda.synchronize()
+    og, ol = oracle.rept(e, n, m, c, 77, per_proc=per_proc)
+    assert np.array_equal(sums.cpu().numpy(), ol.sum(axis=0))
+    g.close()
+    if c > m and c % m:
+        return
+    th, tv = rept.rept_estimate_sums(n, p, glob.cpu().numpy(), sums.cpu().numpy())
+    oth, otv = oracle.estimate(n, m, c, og, ol)
+    assert th == oth and np.array_equal(tv.view(np.uint64), otv.view(np.uint64))
