@@ -77,8 +77,16 @@ struct JobDev {
     uint32_t pad[3];
 };
 
+// Work queues of the counting kernel: each phase's tiles are split over kQueues interleaved
+// sub-queues (tile t is the (t / kQueues)-th of sub-queue t % kQueues) whose counters sit on
+// separate 128-byte lines, so claims spread over kQueues addresses instead of one.
+constexpr uint32_t kQueues = 16;
+constexpr uint32_t kQueueStride = 32;  // words per counter line
+constexpr uint32_t kLightQueue = 0;    // word of the light phase's counter within a line
+constexpr uint32_t kHeavyQueue = 16;   // word of the heavy phase's counter within a line
+
 // Batch header, followed in memory by JobDev[njobs].
-struct BatchHeader {
+struct alignas(128) BatchHeader {
     uint32_t njobs;
     uint32_t wave_cap;     // apexes with out-degree <= wave_cap are counted by one wavefront
     uint32_t block_cap;    // adjacency entries staged per hash-table chunk by a workgroup
@@ -91,14 +99,12 @@ struct BatchHeader {
     uint32_t lds_bytes;    // dynamic LDS bytes per workgroup
     uint32_t heavy_total;  // set by setup
     uint32_t light_total;  // set by setup
-    uint32_t q_heavy;      // queue counters, reset by setup
-    uint32_t q_light;
     uint32_t any_zero;     // some job overwrites its outputs
     uint32_t light_table;  // hash slots per key, at least, in the light phase (2 or 4)
     uint64_t zero_words;   // max words to clear over jobs
     uint32_t any_fill;     // some job's slot table is written by this launch
     uint32_t fill_edges;   // largest stream length over those jobs (bounds their stored edges)
-    uint32_t pad[12];
+    uint32_t queues[kQueues * kQueueStride];  // sub-queue counters, reset by setup
 };
 
 static_assert(sizeof(BatchHeader) % 16 == 0, "header alignment");

@@ -796,8 +796,10 @@ __global__ void k_setup(BatchHeader* hdr, JobDev* jobs) {
     }
     hdr->heavy_total = hp;
     hdr->light_total = lp;
-    hdr->q_heavy = 0;
-    hdr->q_light = 0;
+    for (uint32_t q = 0; q < kQueues; ++q) {
+        hdr->queues[q * kQueueStride + kLightQueue] = 0;
+        hdr->queues[q * kQueueStride + kHeavyQueue] = 0;
+    }
 }
 
 // clear the outputs of jobs that overwrite: grid (X, njobs)
@@ -881,6 +883,22 @@ __global__ void __launch_bounds__(256) k_fill(const JobDev* __restrict__ jobs) {
 
 // ======================================================================= count kernel ====
 
+// Claim the next tile of a phase's queue (counters at ctr[q * kQueueStride]).  The caller starts
+// at its own sub-queue `q` with `left` = kQueues and moves on to the next sub-queue when one is
+// exhausted; returns `total` once it has found every sub-queue exhausted.
+__device__ uint32_t claim_tile(uint32_t* ctr, uint32_t total, uint32_t& q, uint32_t& left) {
+    while (left) {
+        const uint32_t cnt = total > q ? (total - q + kQueues - 1u) / kQueues : 0u;  // tiles of sub-queue q
+        if (cnt) {
+            const uint32_t k = atomicAdd(&ctr[q * kQueueStride], 1u);
+            if (k < cnt) return q + kQueues * k;
+        }
+        q = (q + 1u) % kQueues;
+        --left;
+    }
+    return total;
+}
+
 __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* __restrict__ jobs) {
     extern __shared__ __align__(16) uint8_t lds[];
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -900,8 +918,9 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
     {
         const TeamView T = team_view(uni, L.heavy, DW, DB, kHeavyTable);
         const uint32_t total = hdr->heavy_total;
+        uint32_t q = blockIdx.x % kQueues, left = kQueues;  // used by thread 0
         for (;;) {
-            if (threadIdx.x == 0) s_tile = atomicAdd(&hdr->q_heavy, 1u);
+            if (threadIdx.x == 0) s_tile = claim_tile(hdr->queues + kHeavyQueue, total, q, left);
             __syncthreads();
             const uint32_t tile = s_tile;
             __syncthreads();
@@ -923,9 +942,10 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
     {
         const TeamView T = team_view(uni + wid * L.light.bytes, L.light, DL, DL, LT);
         const uint32_t total = hdr->light_total, tile_len = hdr->light_tile;
+        uint32_t q = (blockIdx.x * nw + wid) % kQueues, left = kQueues;  // used by lane 0
         for (;;) {
             uint32_t tile = 0;
-            if (lane == 0) tile = atomicAdd(&hdr->q_light, 1u);
+            if (lane == 0) tile = claim_tile(hdr->queues + kLightQueue, total, q, left);
             tile = __shfl(tile, 0, 64);
             if (tile >= total) break;
             const uint32_t j = find_job(jobs, njobs, tile, false);
