@@ -237,7 +237,7 @@ typedef struct rept_tuning {
     uint32_t b_chunk;    /* 16..1024: neighbour lists staged per chunk by a workgroup (default 128) */
     uint32_t blocks;     /* persistent workgroups (default: as many as fit, up to 4 per CU) */
     uint32_t threads;    /* 64..1024, a multiple of 64 (default 256) */
-    uint32_t light_tile; /* 1..256: apexes taken per queue pop by a wavefront (default 8) */
+    uint32_t light_tile; /* 1..64: apexes taken per queue pop by a wavefront (default 8) */
     uint32_t reserved[2];
 } rept_tuning;
 

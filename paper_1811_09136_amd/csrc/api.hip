@@ -81,7 +81,7 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     if (block_cap < 64 || block_cap > 4096) return REPT_EINVAL;
     if (b_chunk < 16 || b_chunk > 1024) return REPT_EINVAL;
     if (threads < 64 || threads > 1024 || threads % 64) return REPT_EINVAL;
-    if (light_tile < 1 || light_tile > 256) return REPT_EINVAL;
+    if (light_tile < 1 || light_tile > 64) return REPT_EINVAL;  // one unit per lane of a wavefront
     const uint32_t hist_c = c_max <= REPT_HIST_CAP ? c_max : 0;
     // the light phase's hash tables are sparser (fewer probes) where the LDS budget allows
     uint32_t light_table = 4;

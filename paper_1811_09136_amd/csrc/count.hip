@@ -634,13 +634,14 @@ __device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& 
 // Count every triangle whose lowest-ranked node is a.  The team is the workgroup (BLOCK) or
 // this wavefront.  a's list is hashed into LDS in chunks of DW entries (W side); for each W
 // chunk the lists of all of a's out-neighbours are walked in chunks of DB entries (B side).
+// (s, d): offset and length of a's list; (r0, rn): offset and length of a's reverse list.
 template <bool BLOCK>
-__device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a) {
+__device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a, uint32_t s,
+                           uint32_t d, uint32_t r0, uint32_t rn) {
     const uint32_t nt = BLOCK ? blockDim.x : 64;
     const uint32_t tid = BLOCK ? threadIdx.x : lane_id();
     const uint32_t nw = nt >> 6, wid = BLOCK ? (threadIdx.x >> 6) : 0;
-    const uint32_t s = J.off[a], d = J.off[a + 1] - s;
-    const uint32_t r0 = J.roff[a], nbtot = d + (J.roff[a + 1] - r0);
+    const uint32_t nbtot = d + rn;
     const uint32_t G = J.G;
     for (uint32_t ws = 0; ws < d; ws += T.DW) {
         const uint32_t wn = (d - ws) < T.DW ? (d - ws) : T.DW;
@@ -675,8 +676,13 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                 if (i < braw) {
                     if (e < d) {
                         pab = s + e;
-                        b = ldg(J.nbr + pab);
-                        tb = ldg(J.tim + pab);
+                        if (e >= ws && e < ws + wn) {  // staged as a W entry of this chunk
+                            b = T.ew[e - ws];
+                            tb = T.et[e - ws];
+                        } else {
+                            b = ldg(J.nbr + pab);
+                            tb = ldg(J.tim + pab);
+                        }
                         bo = ldg(J.off + b);
                         bd = ldg(J.off + b + 1) - bo;
                         if (bd > d) bd = 0;  // out(a) is shorter: counted at b
@@ -933,7 +939,8 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
             }
             __syncthreads();
             const uint32_t a = J.apex[jobs[j].unit0 + (tile - jobs[j].heavy_prefix)];
-            count_apex<true>(J, T, V, a);
+            const uint32_t s0 = J.off[a], r0 = J.roff[a];
+            count_apex<true>(J, T, V, a, s0, J.off[a + 1] - s0, r0, J.roff[a + 1] - r0);
         }
     }
     __syncthreads();  // the union area changes owners
@@ -958,7 +965,18 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
             const JobDev& JD = jobs[j];
             const uint32_t ub = JD.unit0 + JD.n_heavy + (tile - JD.light_prefix) * tile_len;
             const uint32_t ue = (ub + tile_len) < JD.unit1 ? (ub + tile_len) : JD.unit1;
-            for (uint32_t u = ub; u < ue; ++u) count_apex<false>(J, T, V, J.apex[u]);
+            // the tile's apexes and their list bounds, loaded together (lane i: unit ub + i)
+            uint32_t ta = 0, ts = 0, td = 0, tr = 0, trn = 0;
+            if (ub + lane < ue) {
+                ta = ldg(J.apex + ub + lane);
+                ts = ldg(J.off + ta);
+                td = ldg(J.off + ta + 1) - ts;
+                tr = ldg(J.roff + ta);
+                trn = ldg(J.roff + ta + 1) - tr;
+            }
+            for (uint32_t u = 0; u < ue - ub; ++u)
+                count_apex<false>(J, T, V, __shfl(ta, u, 64), __shfl(ts, u, 64), __shfl(td, u, 64), __shfl(tr, u, 64),
+                                  __shfl(trn, u, 64));
         }
     }
     flush_hist(J, V, cur);

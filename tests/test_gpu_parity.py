@@ -102,7 +102,7 @@ def test_windows_additive(cuda):
                                   dict(wave_cap=32, block_cap=128, b_chunk=64, threads=1024, light_tile=1),
                                   dict(wave_cap=8, block_cap=64, b_chunk=1024, threads=64, blocks=3),
                                   dict(wave_cap=256, block_cap=2048, b_chunk=256, threads=512, blocks=1,
-                                       light_tile=256)])
+                                       light_tile=64)])
 def test_launch_shapes(cuda, tune):
     from paper_1811_09136_amd import rept
     e, n = synth.scaled_chung_lu(120_000, 31)
@@ -176,6 +176,10 @@ def test_lds_budget_rejected(cuda):
     with pytest.raises(rept.ReptError) as ei:
         rept.rept_batch_count([job], rept.tuning(block_cap=4096, b_chunk=1024, threads=1024), ws.data_ptr(),
                               ws.numel(), None)
+    assert ei.value.code == rept.REPT_EINVAL
+    # a light tile is loaded one unit per lane: more than 64 units is refused
+    with pytest.raises(rept.ReptError) as ei:
+        rept.rept_batch_count([job], rept.tuning(light_tile=65), ws.data_ptr(), ws.numel(), None)
     assert ei.value.code == rept.REPT_EINVAL
     g.close()
 
