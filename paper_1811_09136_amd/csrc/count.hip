@@ -776,35 +776,52 @@ __global__ void k_write_ctrl(uint8_t* ctrl, BatchHeader hdr, JobDev job) {
     }
 }
 
-__global__ void k_setup(BatchHeader* hdr, JobDev* jobs) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Per job: its units split into heavy units (out-degree above wave_cap) and light tiles, and
+// its offsets in both queues.  One block: a thread per job finds the split by binary search
+// over the job's apex order, then thread 0 forms the offsets from the counts in LDS.
+__global__ void __launch_bounds__(1024) k_setup(BatchHeader* hdr, JobDev* jobs) {
+    __shared__ uint32_t cnt[2][1024];  // heavy units and light tiles of the chunk's jobs
     const uint32_t nj = hdr->njobs, cap = hdr->wave_cap, lt = hdr->light_tile;
-    uint32_t hp = 0, lp = 0;
-    for (uint32_t j = 0; j < nj; ++j) {
-        JobDev& J = jobs[j];
-        // apexes are sorted by out-degree, descending: the ones above `cap` form a prefix
-        uint32_t lo = 0, hi = J.unit1;  // first index whose out-degree <= cap (unit1 <= num_apex)
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            const uint32_t a = J.apex[mid];
-            if (J.off[a + 1] - J.off[a] > cap) lo = mid + 1; else hi = mid;
+    uint32_t hp = 0, lp = 0;  // running prefixes (thread 0)
+    for (uint32_t j0 = 0; j0 < nj; j0 += blockDim.x) {
+        const uint32_t j = j0 + threadIdx.x;
+        if (j < nj) {
+            JobDev& J = jobs[j];
+            // apexes are sorted by out-degree, descending: the ones above `cap` form a prefix
+            uint32_t lo = 0, hi = J.unit1;  // first index whose out-degree <= cap (unit1 <= num_apex)
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                const uint32_t a = J.apex[mid];
+                if (J.off[a + 1] - J.off[a] > cap) lo = mid + 1; else hi = mid;
+            }
+            const uint32_t u0 = J.unit0, u1 = J.unit1;
+            const uint32_t hend = u1 < lo ? u1 : lo;
+            const uint32_t nh = hend > u0 ? hend - u0 : 0;
+            const uint32_t tiles = (u1 - u0 - nh + lt - 1) / lt;
+            J.n_heavy = nh;
+            J.light_tiles = tiles;
+            cnt[0][threadIdx.x] = nh;
+            cnt[1][threadIdx.x] = tiles;
         }
-        const uint32_t hb = lo;
-        const uint32_t u0 = J.unit0, u1 = J.unit1;
-        const uint32_t hend = u1 < hb ? u1 : hb;
-        J.n_heavy = hend > u0 ? hend - u0 : 0;
-        const uint32_t lunits = u1 - u0 - J.n_heavy;
-        J.light_tiles = (lunits + lt - 1) / lt;
-        J.heavy_prefix = hp;
-        J.light_prefix = lp;
-        hp += J.n_heavy;
-        lp += J.light_tiles;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t m = (nj - j0) < blockDim.x ? (nj - j0) : blockDim.x;
+            for (uint32_t i = 0; i < m; ++i) {
+                jobs[j0 + i].heavy_prefix = hp;
+                jobs[j0 + i].light_prefix = lp;
+                hp += cnt[0][i];
+                lp += cnt[1][i];
+            }
+        }
+        __syncthreads();
     }
-    hdr->heavy_total = hp;
-    hdr->light_total = lp;
-    for (uint32_t q = 0; q < kQueues; ++q) {
-        hdr->queues[q * kQueueStride + kLightQueue] = 0;
-        hdr->queues[q * kQueueStride + kHeavyQueue] = 0;
+    if (threadIdx.x == 0) {
+        hdr->heavy_total = hp;
+        hdr->light_total = lp;
+        for (uint32_t q = 0; q < kQueues; ++q) {
+            hdr->queues[q * kQueueStride + kLightQueue] = 0;
+            hdr->queues[q * kQueueStride + kHeavyQueue] = 0;
+        }
     }
 }
 
@@ -1030,7 +1047,7 @@ hipError_t launch_common(uint8_t* ws, const BatchHeader& h, hipStream_t s) {
     if (e != hipSuccess) return e;
     BatchHeader* hdr = (BatchHeader*)ws;
     JobDev* jobs = (JobDev*)(ws + sizeof(BatchHeader));
-    hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, s, hdr, jobs);
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(1024), 0, s, hdr, jobs);
     if (h.any_zero) {
         uint64_t blocks = (h.zero_words + 255) / 256;
         if (blocks > 1024) blocks = 1024;
