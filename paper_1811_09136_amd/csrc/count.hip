@@ -557,6 +557,27 @@ __device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& 
             p[j] = bp.x + (it - bp.y);
             w[j] = valid[j] ? ldg(J.nbr + p[j]) : 0u;
         }
+        // the earlier rounds' whole batches of 64 hits are drained while this round's
+        // neighbour loads are in flight (one wait covers both); the rest (fewer than 64) stays
+        if (qn >= 64) {
+            wave_sync();
+            const uint32_t full = qn & ~63u, rem = qn - full;
+            drain_hits(J, T, V, a, full);
+            if (rem) {
+                uint32_t v = 0, pp = 0;
+                if (lane < rem) {
+                    v = V.qv[full + lane];
+                    pp = V.qp[full + lane];
+                }
+                wave_sync();
+                if (lane < rem) {
+                    V.qv[lane] = v;
+                    V.qp[lane] = pp;
+                }
+                wave_sync();
+            }
+            qn = rem;
+        }
         // first probe of every window: a 2-slot bucket; a miss goes on only past a full bucket
         uint32_t bk[kWalk], pos[kWalk];
         bool hit[kWalk], more[kWalk];
@@ -599,26 +620,6 @@ __device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& 
                 V.qp[q] = p[j];
             }
             qn += (uint32_t)__popcll(hm);
-        }
-        if (qn >= 64) {
-            // drain whole batches of 64 and keep the rest (fewer than 64) for the next rounds
-            wave_sync();
-            const uint32_t full = qn & ~63u, rem = qn - full;
-            drain_hits(J, T, V, a, full);
-            if (rem) {
-                uint32_t v = 0, pp = 0;
-                if (lane < rem) {
-                    v = V.qv[full + lane];
-                    pp = V.qp[full + lane];
-                }
-                wave_sync();
-                if (lane < rem) {
-                    V.qv[lane] = v;
-                    V.qp[lane] = pp;
-                }
-                wave_sync();
-            }
-            qn = rem;
         }
         // owner of the next round's first item
         const uint32_t nx = pre + 1;
