@@ -525,13 +525,17 @@ __device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& 
     if (it_begin >= it_end) return;
     uint32_t i0 = find_seg(T.bpos, bn, it_begin);  // owner of the first item (uniform)
     for (uint32_t base = it_begin; base < it_end; base += R) {
-#pragma unroll
-        for (uint32_t j = 0; j < kWalk; ++j) V.mark[64 * j + lane] = 0;
+        static_assert(kWalk == 4, "one 32-bit word of marks per lane");
+        ((uint32_t*)V.mark)[lane] = 0u;
         wave_sync();
-        // lists after i0 start after `base`; the ones starting inside the round are marked
+        // lists after i0 start after `base`; the ones starting inside the round are marked.  List
+        // starts increase, so once a candidate window's first list starts after the round, no
+        // later one starts inside it.
 #pragma unroll
         for (uint32_t j = 0; j < kWalk; ++j) {
-            const uint32_t idx = i0 + 1 + lane + 64 * j;
+            const uint32_t first = i0 + 1 + 64 * j;
+            if (first >= bn || T.bpos[first].y >= base + R) break;
+            const uint32_t idx = first + lane;
             if (idx < bn) {
                 const uint32_t st = T.bpos[idx].y;
                 if (st < base + R) V.mark[st - base] = 1;
