@@ -71,7 +71,10 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     memset(h, 0, sizeof(*h));
     const uint32_t cus = rept_num_cus() ? rept_num_cus() : 256;
     uint32_t fit = 64;
-    while (fit < max_out && fit < 1024) fit <<= 1;
+    // one W chunk per unit up to 2048 entries: re-walking a unit's B lists per extra chunk
+    // costs more than the occupancy a smaller table would buy (R-MAT scale 24, largest list
+    // 1761: 322 ms at 2048, 338 at 1024, 450 at 512; 559 at 4096, one workgroup per CU)
+    while (fit < max_out && fit < 2048) fit <<= 1;
     const uint32_t wave_cap = (tu && tu->wave_cap) ? tu->wave_cap : 64;
     const uint32_t block_cap = (tu && tu->block_cap) ? tu->block_cap : fit;
     const uint32_t b_chunk = (tu && tu->b_chunk) ? tu->b_chunk : 128;
