@@ -233,8 +233,10 @@ typedef struct rept_job {
 typedef struct rept_tuning {
     uint32_t wave_cap;   /* 8..256: largest apex list counted by one wavefront (default 64) */
     uint32_t block_cap;  /* 64..4096: apex entries hashed in LDS per chunk by a workgroup (default:
-                            smallest power of two >= the graphs' largest out-degree, at most 2048) */
-    uint32_t b_chunk;    /* 16..1024: neighbour lists staged per chunk by a workgroup (default 128) */
+                            smallest power of two >= the graphs' largest out-degree, at most 2048,
+                            halved while a workgroup would need more than half the LDS) */
+    uint32_t b_chunk;    /* 16..1024: neighbour lists staged per chunk by a workgroup (default 512
+                            with 2048-entry chunks, else 128; halved likewise) */
     uint32_t blocks;     /* persistent workgroups (default: as many as fit, up to 4 per CU) */
     uint32_t threads;    /* 64..1024, a multiple of 64 (default 256) */
     uint32_t light_tile; /* 1..64: apexes taken per queue pop by a wavefront (default 8) */

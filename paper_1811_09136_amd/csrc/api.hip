@@ -75,9 +75,13 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     // costs more than the occupancy a smaller table would buy (R-MAT scale 24, largest list
     // 1761: 322 ms at 2048, 338 at 1024, 450 at 512; 559 at 4096, one workgroup per CU)
     while (fit < max_out && fit < 2048) fit <<= 1;
+    const bool own_block_cap = tu && tu->block_cap, own_b_chunk = tu && tu->b_chunk;
     const uint32_t wave_cap = (tu && tu->wave_cap) ? tu->wave_cap : 64;
-    const uint32_t block_cap = (tu && tu->block_cap) ? tu->block_cap : fit;
-    const uint32_t b_chunk = (tu && tu->b_chunk) ? tu->b_chunk : 128;
+    uint32_t block_cap = own_block_cap ? tu->block_cap : fit;
+    // units with long lists also have many lists to walk: bigger B chunks pay there (R-MAT
+    // scale 24: 308 ms at 512, 311 at 256, 322 at 128), not on shorter lists (the 1M/20M
+    // power-law graph: 6.64 ms at 128, 7.13 at 64, 7.41 at 256)
+    uint32_t b_chunk = own_b_chunk ? tu->b_chunk : (block_cap >= 2048 ? 512u : 128u);
     const uint32_t threads = (tu && tu->threads) ? tu->threads : 256;
     const uint32_t light_tile = (tu && tu->light_tile) ? tu->light_tile : 8;
     if (wave_cap < 8 || wave_cap > 256) return REPT_EINVAL;
@@ -86,14 +90,24 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     if (threads < 64 || threads > 1024 || threads % 64) return REPT_EINVAL;
     if (light_tile < 1 || light_tile > 64) return REPT_EINVAL;  // one unit per lane of a wavefront
     const uint32_t hist_c = c_max <= REPT_HIST_CAP ? c_max : 0;
-    // the light phase's hash tables are sparser (fewer probes) where the LDS budget allows
+    // the light phase's hash tables are sparser (fewer probes) where the LDS budget allows;
+    // past the budget, the sparser tables go first, then the default chunk sizes shrink
+    // (a shape the caller chose is never changed: it is refused if it does not fit)
     uint32_t light_table = 4;
     uint32_t lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table);
-    if (lds > 160 * 1024 - 256) {
-        light_table = 2;
+    // default chunks keep two workgroups per CU where they can (down to 128 lists, 1024 entries)
+    while (lds > 80 * 1024 - 256 && ((!own_b_chunk && b_chunk > 128) || (!own_block_cap && block_cap > 1024))) {
+        if (!own_b_chunk && b_chunk > 128) b_chunk >>= 1;
+        else block_cap >>= 1;
         lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table);
     }
-    if (lds > 160 * 1024 - 256) return REPT_EINVAL;  // static LDS takes a few bytes more
+    while (lds > 160 * 1024 - 256) {  // static LDS takes a few bytes more
+        if (light_table == 4) light_table = 2;
+        else if (!own_b_chunk && b_chunk > 128) b_chunk >>= 1;
+        else if (!own_block_cap && block_cap > 64) block_cap >>= 1;
+        else return REPT_EINVAL;
+        lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table);
+    }
     uint32_t blocks = tu ? tu->blocks : 0;
     if (!blocks) {
         uint32_t per_cu = rept_count_blocks_per_cu(threads, lds);
