@@ -305,3 +305,36 @@ def test_count_reduce_estimate_path(cuda, m, c, per_proc):
     th, tv = rept.rept_estimate_sums(n, p, glob.cpu().numpy(), sums.cpu().numpy())
     oth, otv = oracle.estimate(n, m, c, og, ol)
     assert th == oth and np.array_equal(tv.view(np.uint64), otv.view(np.uint64))
+
+
+def test_default_shape_shrinks_to_fit(cuda):
+    """A graph whose longest out-list exceeds 1024 entries with 8 hash groups: the default
+    launch shape (2048-entry chunks) does not fit LDS as chosen and is shrunk, not refused.
+    The counts are shape-independent, so they equal those of an explicit smaller shape, and
+    each semi-triangle adds one to each of its three nodes."""
+    import torch
+    from paper_1811_09136_amd import rept
+    n = 1100
+    iu, ju = np.triu_indices(n, 1)
+    e = np.stack([iu, ju], 1).astype(np.uint32)
+    rng = np.random.default_rng(99)
+    e = e[rng.permutation(len(e))]
+    flip = rng.random(len(e)) < 0.5
+    e[flip] = e[flip][:, ::-1]
+    _say(f"complete graph n={n} E={len(e)} m=2 c=16 (8 groups), default vs explicit shape")
+    p = rept.Params(2, 16, 5)
+    g = rept.Graph(rept.to_device_edges(e, cuda), n)
+    assert g.info.max_out_degree > 1024
+    outs = []
+    for tune in (None, rept.tuning(block_cap=512, b_chunk=64)):
+        out = g.outputs(p)
+        out[0].zero_()
+        out[1].zero_()
+        job = rept.make_job(g, p, out, g.new_workspace(p), accumulate=True)
+        ws = torch.empty(rept.rept_batch_workspace_size(1), dtype=torch.uint8, device=cuda)
+        rept.rept_batch_count([job], tune, ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        outs.append((out[0].cpu().numpy(), out[1].cpu().numpy()))
+    g.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][0].sum() > 0 and outs[0][1].sum() == 3 * outs[0][0].sum()
