@@ -126,6 +126,24 @@ def cpu_baseline(edges, n, m, c):
                       f"one thread each, took {dt:.2f} s on {W} cores; whole job = {c}/{W} x that"}
 
 
+def cpu_single_core(edges, n, m, c):
+    """The single-threaded oracle on one pinned host core: processor 0 of the c replayed over
+    the whole stream; the whole job is c times that."""
+    import oracle
+    mask = os.sched_getaffinity(0)
+    core = min(mask)
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        oracle.rept_threads(edges, n, m, c, HASH_SEED, workers=1, procs=(0, 1))
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, mask)
+    return {"value": len(edges) / (dt * c), "unit": "stream edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"Algorithm 1 replay of processor 0 of {c} over all {len(edges)} stream edges on core {core} "
+                      f"(pinned) took {dt:.2f} s; whole job = {c} x that"}
+
+
 def bench_batched(dev, reps: int = 3):
     """512 jobs (256 independent Chung-Lu streams, 10k-2M edges log-uniform, plus 256 hash-seed
     replicas of one 5M-edge stream), m = c = 20: one rept_count per job (plain) against one
@@ -248,6 +266,8 @@ def main():
 
     count_ms = []
     build_ms = []
+    reduce_d2h_ms = []
+    estimate_ms = []
 
     def step(record):
         t0 = time.perf_counter()
@@ -260,13 +280,19 @@ def main():
         rept.rept_reduce_local(loc.data_ptr(), rows, n, sums.data_ptr(), sp)
         h_glob.copy_(glob, non_blocking=True)
         h_sums.copy_(sums, non_blocking=True)
+        ev2 = torch.cuda.Event(enable_timing=True)
+        ev2.record(stream)
         stream.synchronize()
+        t2 = time.perf_counter()
         tau_hat, tau_v = rept.rept_estimate_sums(n, params, h_glob.numpy(), h_sums.numpy(), h_tau_v)
+        t3 = time.perf_counter()
         info = rept.rept_graph_get_info(h)
         rept.rept_destroy(h)
         if record:
             count_ms.append(ev0.elapsed_time(ev1))
             build_ms.append(1e3 * (t1 - t0))
+            reduce_d2h_ms.append(ev1.elapsed_time(ev2))
+            estimate_ms.append(1e3 * (t3 - t2))
         return tau_hat, info
 
     for _ in range(args.warmup):
@@ -322,8 +348,8 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    avg_count_ms = float(np.mean(count_ms))
-    avg_kernel_ms = float(np.mean(kernel_ms))
+    avg_count_ms = float(np.median(count_ms))
+    avg_kernel_ms = float(np.median(kernel_ms))
     alg = algorithmic_bytes(info, tau, c, rows, n)
     achieved = alg / (avg_kernel_ms * 1e-3) / 1e9
     traffic = traffic_from_profile(args.workload)
@@ -331,6 +357,10 @@ def main():
     W = int((deg * (deg - 1) // 2).sum())
     semi = int(h_glob.numpy().sum())
     sm_bytes = streaming_model_bytes(W, E, params.groups, semi, c, n)
+    # context: the bytes an id-sorted merge of the per-group CSR segments would read,
+    # 8 sum_k sum_x d_x d_x^act, with d_x^act = d_x for a full group and its expectation
+    # d_x c2 / m for a partial last group
+    csr_bytes = 8.0 * float((deg * deg).sum()) * (c // m + (c % m) / m)
 
     out = {
         "metric": "stream edges/sec on 1 GPU, % HBM roofline; batched/served vs plain",
@@ -349,11 +379,17 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic},
-        "kernel": {"count_ms": avg_count_ms, "count_kernel_ms": avg_kernel_ms, "build_ms": float(np.mean(build_ms)),
+        "kernel": {"count_ms": avg_count_ms, "count_kernel_ms": avg_kernel_ms, "build_ms": float(np.median(build_ms)),
                    "count_edges_per_s": E / (avg_count_ms * 1e-3), "algorithmic_bytes": alg,
                    "oriented_work": int(info.oriented_work), "num_reverse": int(info.num_reverse), "triangles": tau, "semi_triangles": semi,
                    "streaming_model_bytes": sm_bytes,
                    "streaming_model_equiv_gbps": sm_bytes / (avg_kernel_ms * 1e-3) / 1e9,
+                   "reduce_d2h_ms": float(np.median(reduce_d2h_ms)), "estimate_ms": float(np.median(estimate_ms)),
+                   "stream_edge_processors_per_s": value * c,
+                   "traffic_frac": None if traffic is None else traffic / (avg_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                   "traffic_over_algorithmic": None if traffic is None else traffic / alg,
+                   "csr_merge_bytes": csr_bytes,
+                   "traffic_over_csr_merge": None if traffic is None else traffic / csr_bytes,
                    "source_digest": count_kernel_source_digest()},
         "tau_hat": tau_hat,
     }
@@ -366,6 +402,8 @@ def main():
     if not args.no_cpu:
         say("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(edges, n, m, c)
+        say("cpu baseline, one pinned core")
+        out["cpu_single_core"] = cpu_single_core(edges, n, m, c)
     print(json.dumps(out), flush=True)
 
 
