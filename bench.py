@@ -331,6 +331,29 @@ def main():
     if not np.array_equal(glob.cpu().numpy(), h_glob.numpy()):
         raise RuntimeError("kernel-only launches disagree with the timed steps")
 
+    # PCIe-inclusive steps (not `value`): the stream starts in pinned host memory and
+    # rept_build_host copies it in; the rest of the step as above
+    say("host-input steps")
+    ref_glob = h_glob.numpy().copy()  # the timed steps' global counters
+    h_edges = torch.from_numpy(np.ascontiguousarray(edges, dtype=np.uint32)).pin_memory().numpy()
+    host_ms = []
+    for r in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hh = rept.rept_build_host(n, h_edges, persistent.data_ptr(), pbytes, scratch.data_ptr(), sbytes, sp)
+        rept.rept_count(hh, params, glob.data_ptr(), loc.data_ptr(), ws.data_ptr(), wbytes, sp)
+        rept.rept_reduce_local(loc.data_ptr(), rows, n, sums.data_ptr(), sp)
+        h_glob.copy_(glob, non_blocking=True)
+        h_sums.copy_(sums, non_blocking=True)
+        stream.synchronize()
+        rept.rept_estimate_sums(n, params, h_glob.numpy(), h_sums.numpy(), h_tau_v)
+        rept.rept_destroy(hh)
+        if r:
+            host_ms.append(1e3 * (time.perf_counter() - t0))
+    if not np.array_equal(h_glob.numpy(), ref_glob):
+        raise RuntimeError("host-input step disagrees with the device-input steps")
+    host_step_ms = float(np.median(host_ms))
+
     # exact triangle count (m = 1, untimed) for the per-launch byte model
     p1 = rept.Params(1, 1, 0)
     g1 = torch.empty(1, dtype=torch.int64, device=dev)
@@ -389,6 +412,7 @@ def main():
                    "traffic_frac": None if traffic is None else traffic / (avg_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
                    "traffic_over_algorithmic": None if traffic is None else traffic / alg,
                    "csr_merge_bytes": csr_bytes,
+                   "host_input_step_ms": host_step_ms, "host_input_edges_per_s": E / (host_step_ms * 1e-3),
                    "traffic_over_csr_merge": None if traffic is None else traffic / csr_bytes,
                    "source_digest": count_kernel_source_digest()},
         "tau_hat": tau_hat,

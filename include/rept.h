@@ -120,6 +120,19 @@ rept_status rept_build(uint32_t n, const uint32_t* edges, uint64_t num_edges, vo
                        size_t persistent_bytes, void* scratch, size_t scratch_bytes, void* stream,
                        rept_graph** out);
 
+/*
+ * rept_build for a stream held in host memory (Section II: the stream as it arrives).  The
+ * edges are copied over PCIe into the persistent buffer (into space the build fills later, so
+ * no extra device memory is needed) on `stream`, then built as by rept_build.
+ *   host_edges: host uint32[num_edges][2], pageable or pinned, read only; the call returns
+ *               after its one stream synchronisation, when the copy has completed.
+ * Other arguments, ownership and errors as rept_build (ENOMEM if a buffer is too small,
+ * checked before the copy).
+ */
+rept_status rept_build_host(uint32_t n, const uint32_t* host_edges, uint64_t num_edges, void* persistent,
+                            size_t persistent_bytes, void* scratch, size_t scratch_bytes, void* stream,
+                            rept_graph** out);
+
 /* Statistics of a built graph (host only). */
 rept_status rept_graph_get_info(const rept_graph* graph, rept_graph_info* info);
 

@@ -246,6 +246,24 @@ rept_status rept_build(uint32_t n, const uint32_t* edges, uint64_t num_edges, vo
                            (hipStream_t)stream, out);
 }
 
+rept_status rept_build_host(uint32_t n, const uint32_t* host_edges, uint64_t num_edges, void* persistent,
+                            size_t persistent_bytes, void* scratch, size_t scratch_bytes, void* stream,
+                            rept_graph** out) {
+    if (!out || n == 0 || n > (1u << 29) || num_edges >= (1ull << 31) || !persistent || !scratch)
+        return REPT_EINVAL;
+    if (num_edges > 0 && !host_edges) return REPT_EINVAL;
+    if (((uintptr_t)persistent & 255u) || ((uintptr_t)scratch & 255u)) return REPT_EINVAL;
+    size_t pb = 0, sb = 0;
+    rept_sizes_impl(n, num_edges, &pb, &sb);
+    if (persistent_bytes < pb || scratch_bytes < sb) return REPT_ENOMEM;
+    uint32_t* staged = (uint32_t*)((uint8_t*)persistent + rept_host_stage_offset(n, num_edges));
+    if (num_edges > 0 && hipMemcpyAsync(staged, host_edges, (size_t)num_edges * 8, hipMemcpyHostToDevice,
+                                        (hipStream_t)stream) != hipSuccess)
+        return REPT_EDEVICE;
+    return rept_build_impl(n, staged, num_edges, persistent, persistent_bytes, scratch, scratch_bytes,
+                           (hipStream_t)stream, out);
+}
+
 rept_status rept_graph_get_info(const rept_graph* g, rept_graph_info* info) {
     if (!valid_graph(g) || !info) return REPT_EINVAL;
     info->n = g->n;

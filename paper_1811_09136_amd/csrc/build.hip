@@ -700,6 +700,11 @@ uint32_t grid_for(uint64_t items, uint32_t threads, uint32_t cap) {
 
 }  // namespace
 
+// Where a host-resident stream is staged in the persistent buffer: the reverse records' region
+// (16 bytes per edge), which the build writes only in the segment sorts, after every pass that
+// reads the stream.
+size_t rept_host_stage_offset(uint32_t n, uint64_t E) { return persistent_layout(n, E).rrec; }
+
 void rept_sizes_impl(uint32_t n, uint64_t E, size_t* persistent, size_t* scratch) {
     *persistent = persistent_layout(n, E).total;
     *scratch = scratch_layout(n, E).total;

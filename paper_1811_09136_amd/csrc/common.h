@@ -112,6 +112,7 @@ static_assert(sizeof(JobDev) % 16 == 0, "job alignment");
 static_assert(sizeof(BatchHeader) + sizeof(JobDev) <= REPT_CTRL_BYTES, "control block size");
 
 // ---- build (build.hip) ----
+size_t rept_host_stage_offset(uint32_t n, uint64_t E);
 rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void* persistent,
                             size_t persistent_bytes, void* scratch, size_t scratch_bytes,
                             hipStream_t stream, rept_graph** out);

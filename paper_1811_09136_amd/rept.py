@@ -74,6 +74,7 @@ def lib() -> ctypes.CDLL:
             "rept_local_rows": ([P(rept_params)], u32),
             "rept_query_sizes": ([u32, u64, P(sz), P(sz)], i32),
             "rept_build": ([u32, vp, u64, vp, sz, vp, sz, vp, P(vp)], i32),
+            "rept_build_host": ([u32, vp, u64, vp, sz, vp, sz, vp, P(vp)], i32),
             "rept_graph_get_info": ([vp, P(rept_graph_info)], i32),
             "rept_count_workspace_size": ([vp, P(rept_params), P(sz)], i32),
             "rept_count": ([vp, P(rept_params), vp, vp, vp, sz, vp], i32),
@@ -98,7 +99,7 @@ def lib() -> ctypes.CDLL:
     return _lib
 
 
-EXPORTED = ["rept_local_rows", "rept_query_sizes", "rept_build", "rept_graph_get_info",
+EXPORTED = ["rept_local_rows", "rept_query_sizes", "rept_build", "rept_build_host", "rept_graph_get_info",
             "rept_count_workspace_size", "rept_count",
             "rept_count_range", "rept_estimate", "rept_estimate_sums", "rept_reduce_local", "rept_hash_slots", "rept_batch_workspace_size",
             "rept_batch_prepare", "rept_batch_launch", "rept_batch_count", "rept_destroy", "rept_status_str",
@@ -158,6 +159,18 @@ def rept_build(n: int, edges_ptr: int, num_edges: int, persistent_ptr: int, pers
     h = ctypes.c_void_p(0)
     _check(lib().rept_build(n, edges_ptr, num_edges, persistent_ptr, persistent_bytes, scratch_ptr, scratch_bytes,
                             stream_ptr, ctypes.byref(h)), "rept_build")
+    return h.value
+
+
+def rept_build_host(n: int, host_edges: np.ndarray, persistent_ptr: int, persistent_bytes: int,
+                    scratch_ptr: int, scratch_bytes: int, stream_ptr: int | None) -> int:
+    """rept_build for a host-resident stream (uint32 [E, 2]); the library copies it over PCIe."""
+    e = np.ascontiguousarray(host_edges, dtype=np.uint32)
+    if e.ndim != 2 or e.shape[1] != 2:
+        raise ValueError("host_edges must be an [E, 2] array")
+    h = ctypes.c_void_p(0)
+    _check(lib().rept_build_host(n, e.ctypes.data if len(e) else None, len(e), persistent_ptr, persistent_bytes,
+                                 scratch_ptr, scratch_bytes, stream_ptr, ctypes.byref(h)), "rept_build_host")
     return h.value
 
 

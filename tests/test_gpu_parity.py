@@ -338,3 +338,43 @@ def test_default_shape_shrinks_to_fit(cuda):
     g.close()
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
     assert outs[0][0].sum() > 0 and outs[0][1].sum() == 3 * outs[0][0].sum()
+
+
+def test_build_from_host_stream(cuda):
+    """A host-resident stream built with rept_build_host: the same graph statistics as the
+    device-input build and the oracle's counts; an invalid stream is reported as from the
+    device path; buffers too small are refused before any copy."""
+    import torch
+    from paper_1811_09136_amd import rept
+    e = synth.er(500, 6000, 21, 22)
+    n, p = 500, rept.Params(5, 15, 3)
+    _say(f"host-input build ER n={n} E={len(e)} m=5 c=15")
+    pb, sb = rept.rept_query_sizes(n, len(e))
+    P = torch.empty(pb, dtype=torch.uint8, device=cuda)
+    S = torch.empty(sb, dtype=torch.uint8, device=cuda)
+    sp = torch.cuda.current_stream().cuda_stream
+    h = rept.rept_build_host(n, e, P.data_ptr(), pb, S.data_ptr(), sb, sp)
+    info_h = rept.rept_graph_get_info(h)
+    glob = torch.empty(p.c, dtype=torch.int64, device=cuda)
+    loc = torch.empty((p.rows, n), dtype=torch.int64, device=cuda)
+    wsb = rept.rept_count_workspace_size(h, p)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=cuda)
+    rept.rept_count(h, p, glob.data_ptr(), loc.data_ptr(), ws.data_ptr(), wsb, sp)
+    torch.cuda.synchronize()
+    got = glob.cpu().numpy(), loc.cpu().numpy()
+    rept.rept_destroy(h)
+    g = rept.Graph(rept.to_device_edges(e, cuda), n)
+    info_d = g.info
+    g.close()
+    for f in ("num_apex", "max_out_degree", "oriented_work", "num_reverse"):
+        assert getattr(info_h, f) == getattr(info_d, f), f
+    og, ol = oracle.rept(e, n, 5, 15, 3)
+    assert np.array_equal(got[0], og) and np.array_equal(got[1], ol)
+    bad = e.copy()
+    bad[17] = [9, 9]
+    with pytest.raises(rept.ReptError) as ei:
+        rept.rept_build_host(n, bad, P.data_ptr(), pb, S.data_ptr(), sb, sp)
+    assert ei.value.code == rept.REPT_ESELFLOOP
+    with pytest.raises(rept.ReptError) as ei:
+        rept.rept_build_host(n, e, P.data_ptr(), pb - 256, S.data_ptr(), sb, sp)
+    assert ei.value.code == rept.REPT_ENOMEM
