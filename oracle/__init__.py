@@ -74,6 +74,10 @@ def _load():
         L.oracle_edge_updates.restype = i32
         L.oracle_estimate.argtypes = [u32, u32, u32, u32, vp, vp, vp, vp]
         L.oracle_estimate.restype = i32
+        L.oracle_rept2_eta.argtypes = [u32, u32, u32, u64, vp, u64, vp, vp, vp, vp]
+        L.oracle_rept2_eta.restype = i32
+        L.oracle_estimate2.argtypes = [u32, u32, u32, u32, i32, vp, vp, ctypes.c_int64, vp, vp, vp]
+        L.oracle_estimate2.restype = i32
         _lib = L
     return _lib
 
@@ -200,4 +204,40 @@ def estimate(n: int, m: int, c: int, glob, loc=None):
                                  None if tv is None else tv.ctypes.data)
     if rc != OK:
         raise OracleError(rc, "oracle_estimate")
+    return th.value, tv
+
+
+def rept2_eta(edges, n: int, m: int, c: int, seed: int):
+    """Algorithm 2's triangle-pair counters (Section III-B), both readings of the counter's
+    initial value on insert: returns (eta_def[c], eta_lit[c], eta_v_def[n], eta_v_lit[n]),
+    eta_v summed over all processors."""
+    e = _edges(edges)
+    ed = np.zeros(c, dtype=np.int64)
+    el = np.zeros(c, dtype=np.int64)
+    vd = np.zeros(n, dtype=np.int64)
+    vl = np.zeros(n, dtype=np.int64)
+    rc = _load().oracle_rept2_eta(n, m, c, seed & (2**64 - 1), e.ctypes.data, len(e), ed.ctypes.data,
+                                  el.ctypes.data, vd.ctypes.data, vl.ctypes.data)
+    if rc != OK:
+        raise OracleError(rc, "oracle_rept2_eta")
+    return ed, el, vd, vl
+
+
+def estimate2(n: int, m: int, c: int, glob, loc=None, eta: int = 0, eta_v=None, per_proc: bool = False):
+    """Algorithm 2's combined estimators (c > m, m not dividing c): (tau_hat, tau_v_hat[n] or
+    None), from the counters, eta (sum of eta^(i)) and eta_v (sums over processors)."""
+    g = np.ascontiguousarray(np.asarray(glob, dtype=np.int64))
+    th = ctypes.c_double(0.0)
+    tv = lp = ep = None
+    rows = 0
+    if loc is not None and eta_v is not None:
+        lo = np.ascontiguousarray(np.asarray(loc, dtype=np.int64))
+        ev = np.ascontiguousarray(np.asarray(eta_v, dtype=np.int64))
+        rows = lo.shape[0]
+        tv = np.zeros(n, dtype=np.float64)
+        lp, ep = lo.ctypes.data, ev.ctypes.data
+    rc = _load().oracle_estimate2(n, m, c, rows, int(per_proc), g.ctypes.data, lp, int(eta), ep,
+                                  ctypes.addressof(th), None if tv is None else tv.ctypes.data)
+    if rc != OK:
+        raise OracleError(rc, "oracle_estimate2")
     return th.value, tv

@@ -444,3 +444,166 @@ int oracle_estimate(uint32_t n, uint32_t m, uint32_t c, uint32_t local_rows,
     }
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------ Algorithm 2 counters -- */
+
+/*
+ * The triangle-pair counters of Algorithm 2 (Section III-B, "Our method of computing eta^(i)
+ * and eta_v^(i)"), replayed per processor in stream order.  Each stored edge g of E^(i) has a
+ * counter tau_g^(i).  For the edge (u, v) at time t and each w in N = N_u^(i) intersect
+ * N_v^(i):
+ *   eta^(i)   += tau_(u,w) + tau_(v,w);   eta_w^(i) += tau_(u,w) + tau_(v,w);
+ *   eta_u^(i) += tau_(u,w);               eta_v^(i) += tau_(v,w);
+ *   tau_(u,w) += 1;                       tau_(v,w) += 1;
+ * then, if h_k(u, v) selects i, (u, v) joins E^(i) with its counter set to an initial value.
+ * Two readings of that initial value are computed in the same replay:
+ *   literal: tau_(u,v) = |N| (Algorithm 2 as printed), which also counts pairs whose shared
+ *            edge is the last edge of the earlier triangle;
+ *   definition: tau_(u,v) = 0, which counts exactly the pairs of distinct triangles of
+ *            Delta^(i) sharing an edge that is the last edge of neither (the definition of
+ *            eta^(i) in Section III-B).
+ * Outputs (overwritten): eta_def[i], eta_lit[i] for every processor i < c; eta_v_def[v],
+ * eta_v_lit[v] = sum over all processors of eta_v^(i).  The whole stream is replayed.
+ */
+int oracle_rept2_eta(uint32_t n, uint32_t m, uint32_t c, uint64_t seed, const uint32_t *edges, uint64_t E,
+                     int64_t *eta_def, int64_t *eta_lit, int64_t *eta_v_def, int64_t *eta_v_lit) {
+    if (n == 0 || m == 0 || c == 0 || !edges || !eta_def || !eta_lit || !eta_v_def || !eta_v_lit)
+        return OR_EINVAL;
+    int rc = oracle_validate(n, edges, E);
+    if (rc) return rc;
+    const uint32_t G = (c + m - 1) / m;
+    uint64_t *params = (uint64_t *)malloc(sizeof(uint64_t) * 4 * G);
+    adjlist *adj = (adjlist *)calloc(n, sizeof(adjlist));
+    uint32_t *slot = (uint32_t *)malloc(sizeof(uint32_t) * (E ? E : 1));
+    int64_t *cdef = (int64_t *)malloc(sizeof(int64_t) * (E ? E : 1)); /* per stored edge, by index */
+    int64_t *clit = (int64_t *)malloc(sizeof(int64_t) * (E ? E : 1));
+    if (!params || !adj || !slot || !cdef || !clit) {
+        rc = OR_ENOMEM;
+        goto done;
+    }
+    memset(eta_def, 0, sizeof(int64_t) * c);
+    memset(eta_lit, 0, sizeof(int64_t) * c);
+    memset(eta_v_def, 0, sizeof(int64_t) * n);
+    memset(eta_v_lit, 0, sizeof(int64_t) * n);
+    oracle_hash_params(seed, G, params);
+    for (uint32_t k = 0; k < G && rc == OR_OK; ++k) {
+        const uint32_t ck = (k + 1 < G) ? m : c - (G - 1) * m;
+        for (uint64_t t = 0; t < E; ++t) slot[t] = oracle_slot(params + 4 * k, m, edges[2 * t], edges[2 * t + 1]);
+        for (uint32_t j = 0; j < ck && rc == OR_OK; ++j) {
+            const uint32_t i = k * m + j;
+            uint64_t mine = 0;
+            for (uint64_t t = 0; t < E; ++t) mine += (slot[t] == j);
+            edgeset Ei; /* E^(i): pair -> index of its counters */
+            if (es_init(&Ei, mine)) {
+                rc = OR_ENOMEM;
+                break;
+            }
+            uint64_t stored = 0;
+            for (uint32_t x = 0; x < n; ++x) adj[x].len = 0;
+            for (uint64_t t = 0; t < E; ++t) {
+                const uint32_t u = edges[2 * t], v = edges[2 * t + 1];
+                const adjlist *small = adj[u].len <= adj[v].len ? &adj[u] : &adj[v];
+                const uint32_t other = adj[u].len <= adj[v].len ? v : u;
+                int64_t cnt = 0;
+                for (uint32_t q = 0; q < small->len; ++q) {
+                    const uint32_t w = small->nbr[q];
+                    uint64_t iow = 0, iuw = 0, ivw = 0;
+                    if (!es_get(&Ei, pairkey(other, w), &iow)) continue;
+                    ++cnt;
+                    es_get(&Ei, pairkey(u, w), &iuw);
+                    es_get(&Ei, pairkey(v, w), &ivw);
+                    eta_def[i] += cdef[iuw] + cdef[ivw];
+                    eta_lit[i] += clit[iuw] + clit[ivw];
+                    eta_v_def[w] += cdef[iuw] + cdef[ivw];
+                    eta_v_lit[w] += clit[iuw] + clit[ivw];
+                    eta_v_def[u] += cdef[iuw];
+                    eta_v_lit[u] += clit[iuw];
+                    eta_v_def[v] += cdef[ivw];
+                    eta_v_lit[v] += clit[ivw];
+                    cdef[iuw] += 1;
+                    clit[iuw] += 1;
+                    cdef[ivw] += 1;
+                    clit[ivw] += 1;
+                }
+                if (slot[t] == j) {
+                    cdef[stored] = 0;
+                    clit[stored] = cnt; /* |N_{u,v}^(i)| at insertion */
+                    es_put(&Ei, pairkey(u, v), stored);
+                    ++stored;
+                    if (adj_push(&adj[u], v) || adj_push(&adj[v], u)) {
+                        rc = OR_ENOMEM;
+                        break;
+                    }
+                }
+            }
+            es_free(&Ei);
+        }
+    }
+done:
+    if (adj)
+        for (uint32_t x = 0; x < n; ++x) free(adj[x].nbr);
+    free(adj);
+    free(slot);
+    free(params);
+    free(cdef);
+    free(clit);
+    return rc;
+}
+
+/*
+ * Algorithm 2's combined estimators (Section III-B, c > m with c2 = c mod m != 0), in IEEE
+ * binary64 with the operations in this order (c1 = floor(c / m), c2 = c mod m):
+ *   t1  = (S1 * m) / c1                      S1: sum of tau^(i) over the first c1 m processors
+ *   t2  = (S2 * m^2) / c2                    S2: sum over the last c2 processors
+ *   eh  = (eta * m^3) / c                    eta: sum of eta^(i) over all processors
+ *   v1  = (t1 * (m - 1)) / c1                Var(t1), tau replaced by t1
+ *   v2  = (t1 * (m^2 - c2) + (2 eh) * (m - c2)) / c2
+ *   tau_hat = (v2 t1 + v1 t2) / (v1 + v2), and t1 when v1 + v2 = 0 (its limit: the weight of
+ *             t2 is v1, which is then 0).
+ * The local estimators are the same expressions with S1_v, S2_v (the local rows of the first c1
+ * groups, resp. of the last group) and eta_v.  Integer sums are exact; any sum below 0 or at or
+ * above 2^53 is refused (ERANGE).  local: local_rows x n, either G group rows or c processor
+ * rows (per_proc).
+ */
+int oracle_estimate2(uint32_t n, uint32_t m, uint32_t c, uint32_t local_rows, int per_proc,
+                     const int64_t *global, const int64_t *local, int64_t eta, const int64_t *eta_v,
+                     double *tau_hat, double *tau_v_hat) {
+    if (n == 0 || m == 0 || c == 0 || !global || !tau_hat) return OR_EINVAL;
+    const uint32_t c1 = c / m, c2 = c % m;
+    if (c1 == 0 || c2 == 0) return OR_EINVAL; /* only c > m with m not dividing c */
+    const int64_t lim = (int64_t)1 << 53;
+    int64_t S1 = 0, S2 = 0;
+    for (uint32_t i = 0; i < c; ++i) {
+        int64_t *S = i < c1 * m ? &S1 : &S2;
+        if (global[i] < 0 || global[i] >= lim - *S) return OR_ERANGE;
+        *S += global[i];
+    }
+    if (eta < 0 || eta >= lim) return OR_ERANGE;
+    const double dm = (double)m, dm2 = (double)((uint64_t)m * m), dm3 = (double)((uint64_t)m * m * m);
+    const double dc1 = (double)c1, dc2 = (double)c2, dc = (double)c;
+    const double a2 = (double)((uint64_t)m * m - c2), b2 = (double)(m - c2), dm1 = (double)(m - 1);
+    {
+        const double t1 = ((double)S1 * dm) / dc1, t2 = ((double)S2 * dm2) / dc2;
+        const double eh = ((double)eta * dm3) / dc;
+        const double v1 = (t1 * dm1) / dc1, v2 = (t1 * a2 + (2.0 * eh) * b2) / dc2;
+        *tau_hat = (v1 + v2 == 0.0) ? t1 : (v2 * t1 + v1 * t2) / (v1 + v2);
+    }
+    if (tau_v_hat && local && eta_v) {
+        const uint32_t split = per_proc ? c1 * m : c1; /* rows before the last group */
+        for (uint32_t v = 0; v < n; ++v) {
+            int64_t A = 0, B = 0;
+            for (uint32_t r = 0; r < local_rows; ++r) {
+                const int64_t x = local[(uint64_t)r * n + v];
+                int64_t *S = r < split ? &A : &B;
+                if (x < 0 || x >= lim - *S) return OR_ERANGE;
+                *S += x;
+            }
+            if (eta_v[v] < 0 || eta_v[v] >= lim) return OR_ERANGE;
+            const double t1 = ((double)A * dm) / dc1, t2 = ((double)B * dm2) / dc2;
+            const double eh = ((double)eta_v[v] * dm3) / dc;
+            const double v1 = (t1 * dm1) / dc1, v2 = (t1 * a2 + (2.0 * eh) * b2) / dc2;
+            tau_v_hat[v] = (v1 + v2 == 0.0) ? t1 : (v2 * t1 + v1 * t2) / (v1 + v2);
+        }
+    }
+    return OR_OK;
+}

@@ -349,3 +349,135 @@ def test_hash_four_wise_collision_rate_over_seeds():
         cond = (s[three, 3] == s[three, 0]).mean()
         k = int(three.sum())
         assert abs(cond - 1 / m) < 4.5 * math.sqrt((1 / m) * (1 - 1 / m) / k), (q, cond, k)
+
+
+# ---------------------------------------------------------------- Algorithm 2 (c2 != 0) ----
+
+def _semi_sets(edges, n, m, c, seed):
+    """Per processor i: its semi-triangles as ((a, b, w), (t_ab, t_aw, t_bw)), by definition
+    (the first two edges by time hash to i), enumerated from the graph's triangles."""
+    G = -(-c // m)
+    sl = oracle.slots(edges, m, G, seed)
+    out = [[] for _ in range(c)]
+    for tri, ts in brute.triangles(edges, n):
+        first = sorted(ts)[:2]
+        for k in range(G):
+            ck = m if k + 1 < G else c - (G - 1) * m
+            if sl[k, first[0]] == sl[k, first[1]] and sl[k, first[0]] < ck:
+                out[k * m + int(sl[k, first[0]])].append((tri, ts))
+    return out
+
+
+def _eta_by_enumeration(edges, n, m, c, seed):
+    """(eta_def[c], eta_lit[c], eta_v_def[n], eta_v_lit[n]) from the semi-triangle sets.
+    Definition: unordered pairs of distinct semi-triangles of one processor sharing an edge that
+    is the last edge of neither.  Literal (counter set to |N| on insert): each edge g adds
+    s_g L_g + C(s_g, 2), with s_g the processor's semi-triangles having g as a non-last edge and
+    L_g those having g as the last edge; eta_v adds the same over the edges g containing v."""
+    sets = _semi_sets(edges, n, m, c, seed)
+    ed, el = np.zeros(c, np.int64), np.zeros(c, np.int64)
+    vd, vl = np.zeros(n, np.int64), np.zeros(n, np.int64)
+    for i, S in enumerate(sets):
+        s, L = {}, {}
+        for (a, b, w), (tab, taw, tbw) in S:
+            last = max(tab, taw, tbw)
+            for (x, y), t in (((a, b), tab), ((a, w), taw), ((b, w), tbw)):
+                d = L if t == last else s
+                d[(x, y)] = d.get((x, y), 0) + 1
+        # the definition, pair by pair
+        for p, q in itertools.combinations(range(len(S)), 2):
+            (A, ta), (B, tb) = S[p], S[q]
+            ea = {frozenset(e): t for e, t in zip(((A[0], A[1]), (A[0], A[2]), (A[1], A[2])), ta)}
+            eb = {frozenset(e): t for e, t in zip(((B[0], B[1]), (B[0], B[2]), (B[1], B[2])), tb)}
+            for g in set(ea) & set(eb):
+                if ea[g] != max(ta) and eb[g] != max(tb):
+                    ed[i] += 1
+                    for v in set(A) & set(B):
+                        vd[v] += 1
+        for g, sg in s.items():
+            f = sg * L.get(g, 0) + sg * (sg - 1) // 2
+            el[i] += f
+            vl[g[0]] += f
+            vl[g[1]] += f
+    return ed, el, vd, vl
+
+
+def test_alg2_counters_hand_streams():
+    """Two triangles {0,1,2}, {0,1,3} sharing {0,1}, one processor (m = c = 1).  When {0,1}
+    arrives first it is a non-last edge of both: eta = 1 under both readings.  When it closes
+    the first triangle, the definition excludes the pair (eta = 0) but a counter set to |N| = 1
+    on insert counts it (literal eta = 1, added at nodes 0 and 1)."""
+    e = np.array([[0, 1], [0, 2], [1, 2], [0, 3], [1, 3]], np.uint32)
+    ed, el, vd, vl = oracle.rept2_eta(e, 4, 1, 1, 0)
+    assert ed.tolist() == [1] and el.tolist() == [1] and vd.tolist() == [1, 1, 0, 0] == vl.tolist()
+    e = np.array([[0, 2], [1, 2], [0, 1], [0, 3], [1, 3]], np.uint32)
+    ed, el, vd, vl = oracle.rept2_eta(e, 4, 1, 1, 0)
+    assert ed.tolist() == [0] and el.tolist() == [1] and vd.tolist() == [0, 0, 0, 0] and vl.tolist() == [1, 1, 0, 0]
+
+
+@pytest.mark.parametrize("m,c,seed", [(2, 3, 1), (3, 7, 2), (2, 5, 3), (4, 6, 4)])
+def test_alg2_counters_match_enumeration(m, c, seed):
+    e = synth.er(40, 260, 30 + seed, 40 + seed)
+    got = oracle.rept2_eta(e, 40, m, c, seed)
+    want = _eta_by_enumeration(e, 40, m, c, seed)
+    for g, w in zip(got, want):
+        assert np.array_equal(g, w)
+    assert want[0].sum() > 0 and (want[1] >= want[0]).all()
+
+
+def test_alg2_counters_one_processor_equal_graph_eta():
+    """m = c = 1: every triangle is on the one processor, so its definition counter is the
+    graph's eta (and eta_v), enumerated independently."""
+    e = synth.er(30, 150, 7, 8)
+    ed, _, vd, _ = oracle.rept2_eta(e, 30, 1, 1, 0)
+    assert ed[0] == brute.eta(e, 30) > 0
+    assert all(vd[v] == brute.eta(e, 30, node=v) for v in range(30))
+
+
+def test_alg2_eta_estimate_unbiased_over_seeds():
+    """E(eta^(i)) = eta / m^3 for the definition counter (Section III-B), so the mean over hash
+    seeds of m^3 sum_i eta^(i) / c approaches eta; checked at 5 standard errors."""
+    e = synth.er(45, 420, 11, 12)
+    truth = brute.eta(e, 45)
+    m, c = 2, 5
+    est = [2 ** 3 * oracle.rept2_eta(e, 45, m, c, s)[0].sum() / c for s in range(400)]
+    se = np.std(est) / np.sqrt(len(est))
+    assert truth > 0 and abs(np.mean(est) - truth) < 5 * se
+
+
+def test_alg2_estimator_hand_value_and_limits():
+    """m = 2, c = 3 (c1 = c2 = 1), S1 = 8, S2 = 7, eta = 4: t1 = 16, t2 = 28, eh = 32/3,
+    v1 = 16, v2 = 48 + 64/3 = 208/3, tau_hat = (208/3 * 16 + 16 * 28) / (16 + 208/3) = 18.25
+    exactly in rationals.  Both variances zero: t1 (Q12).  The result is a weighted mean."""
+    th, tv = oracle.estimate2(2, 2, 3, [3, 5, 7], [[1, 2], [3, 4]], 4, [1, 1])
+    # local v = 1: S1_v = 2, S2_v = 4, eta_v = 1 -> 6.25 in rationals; eta_v m^3 / c = 8/3 is
+    # rounded once, so the binary64 result is within a few ulps of it (bound 4 ulps)
+    assert th == 18.25 and tv[0] == 3.5 and abs(tv[1] - 6.25) <= 4 * np.spacing(6.25)
+    th, _ = oracle.estimate2(1, 2, 3, [0, 0, 9], None, 0, None)
+    assert th == 0.0
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        m = int(rng.integers(2, 9)); c = m * int(rng.integers(1, 4)) + int(rng.integers(1, m))
+        g = rng.integers(0, 10**6, size=c)
+        th, _ = oracle.estimate2(1, m, c, g, None, int(rng.integers(0, 10**7)), None)
+        c1 = c // m
+        t1 = g[: c1 * m].sum() * m / c1
+        t2 = g[c1 * m:].sum() * m * m / (c % m)
+        assert min(t1, t2) * (1 - 1e-12) <= th <= max(t1, t2) * (1 + 1e-12)
+    with pytest.raises(oracle.OracleError):
+        oracle.estimate2(1, 2, 4, [1, 1, 1, 1], None, 0, None)
+
+
+def test_alg2_estimator_unbiased_over_seeds():
+    """Both parts are unbiased (Section III-B), so the combined global estimate averaged over
+    hash seeds approaches the exact triangle count."""
+    e = synth.er(60, 700, 21, 22)
+    tau, _ = brute.exact_counts(e, 60)
+    m, c = 3, 7
+    est = []
+    for s in range(300):
+        g, loc = oracle.rept(e, 60, m, c, s)
+        eta = int(oracle.rept2_eta(e, 60, m, c, s)[0].sum())
+        est.append(oracle.estimate2(60, m, c, g, None, eta, None)[0])
+    se = np.std(est) / np.sqrt(len(est))
+    assert tau > 0 and abs(np.mean(est) - tau) < 5 * se
