@@ -177,7 +177,7 @@ rept_status rept_count_range(const rept_graph* graph, const rept_params* params,
  *     tau_v_hat = ((double)S_v * (double)(m*m)) / (double)c,   S_v = sum of the local rows at v
  * with the sums exact in int64 and one rounding each for the product and the quotient.
  *   global: host int64[c]; local: host int64[rows][n] or NULL; tau_v_hat: host double[n] or NULL.
- * Errors: EINVAL; ENOTSUP for c > m with c % m != 0 (Algorithm 2's combined estimator);
+ * Errors: EINVAL; ENOTSUP for c > m with c % m != 0 (rept_estimate_combined covers it);
  *         ERANGE if a sum is negative or >= 2^53.
  */
 rept_status rept_estimate(uint32_t n, const rept_params* params, const int64_t* global,
@@ -191,6 +191,58 @@ rept_status rept_estimate(uint32_t n, const rept_params* params, const int64_t* 
  */
 rept_status rept_estimate_sums(uint32_t n, const rept_params* params, const int64_t* global,
                                const int64_t* sums, double* tau_hat, double* tau_v_hat);
+
+/*
+ * Device bytes of the workspace of rept_count_eta: the slot table of rept_count_workspace_size,
+ * then two uint32 counters per stored edge and group (the per-edge counts below), rounded up to
+ * 256 bytes.  Host only.  Errors: EINVAL; ENOTSUP (more than 8 groups, m > 65536).
+ */
+rept_status rept_count_eta_workspace_size(const rept_graph* graph, const rept_params* params,
+                                          size_t* bytes);
+
+/*
+ * The counting pass of rept_count together with Algorithm 2's triangle-pair counters
+ * (Section III-B, "computing eta^(i) and eta_v^(i)").  For a stored edge g of processor i let
+ * s_g be the number of semi-triangles of i in which g is one of the two earlier edges, and
+ * L_g the number whose last edge is g (its |N| when g arrives, g being stored by i).  Then
+ *   eta[0][i]   = sum over g of C(s_g, 2)             the pairs of semi-triangles of i that share
+ *                                                      an edge that is the last of neither (the
+ *                                                      definition of eta^(i); E = eta / m^3)
+ *   eta[1][i]   = sum over g of s_g L_g + C(s_g, 2)   Algorithm 2 as printed, whose counter
+ *                                                      starts at |N| when g is inserted
+ *   eta_v[r][v] = sum over processors and over the stored edges g at v of the same terms.
+ *   global, local: as rept_count (overwritten).
+ *   eta:       device int64[2][c], overwritten; 8-byte aligned.
+ *   eta_v:     device int64[2][n], overwritten, or NULL; 8-byte aligned.
+ *   workspace: device, >= rept_count_eta_workspace_size bytes, 256-byte aligned, rewritten.
+ *   tuning:    launch shape (rept_tuning, below) or NULL for the default shape; a shape that
+ *              does not fit the LDS is EINVAL.
+ * The combined estimator (rept_estimate_combined) takes the sums of row 0.  Any c is
+ * accepted.  Asynchronous on `stream`.  Errors: EINVAL, ENOMEM (workspace too small), ENOTSUP
+ * (more than 8 groups or m > 65536), EDEVICE.
+ */
+struct rept_tuning;
+rept_status rept_count_eta(const rept_graph* graph, const rept_params* params, int64_t* global,
+                           int64_t* local, int64_t* eta, int64_t* eta_v, void* workspace,
+                           size_t workspace_bytes, const struct rept_tuning* tuning, void* stream);
+
+/*
+ * Algorithm 2's combined estimators (host, FP64; Section III-B, c > m with c2 = c mod m != 0,
+ * c1 = floor(c / m)): with S1 the sum of tau^(i) over the first c1 m processors, S2 over the
+ * last c2, and eta the sum of eta^(i) over all c, in this order of binary64 operations
+ *   t1 = (S1 m) / c1,  t2 = (S2 m^2) / c2,  eh = (eta m^3) / c,
+ *   v1 = (t1 (m - 1)) / c1,  v2 = (t1 (m^2 - c2) + (2 eh)(m - c2)) / c2,
+ *   tau_hat = (v2 t1 + v1 t2) / (v1 + v2), or t1 where v1 + v2 = 0.
+ * The local estimators are the same expressions at each node, from its local rows (those of the
+ * first c1 groups, or processors, in S1_v; the last group's in S2_v) and eta_v[v].
+ *   global: host int64[c]; local: host int64[rows][n] or NULL; eta_v: host int64[n] or NULL;
+ *   tau_v_hat: host double[n] or NULL (written only when local and eta_v are given).
+ * Errors: EINVAL (null pointers, or c <= m or m | c: rept_estimate covers those); ERANGE if a
+ * sum is negative or >= 2^53.
+ */
+rept_status rept_estimate_combined(uint32_t n, const rept_params* params, const int64_t* global,
+                                   const int64_t* local, int64_t eta, const int64_t* eta_v,
+                                   double* tau_hat, double* tau_v_hat);
 
 /*
  * The reduction of the local estimator's sums on the device (Sections III-A, III-B: S_v sums

@@ -67,7 +67,7 @@ bool valid_graph(const rept_graph* g) { return g && g->magic == REPT_MAGIC; }
 // Fill the launch shape for jobs of at most G_max groups, at most c_max processors and at most
 // max_out entries in an apex list.
 rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t max_out, uint64_t zero_words,
-                        bool any_zero, const rept_tuning* tu, BatchHeader* h) {
+                        bool any_zero, const rept_tuning* tu, BatchHeader* h, bool eta = false) {
     memset(h, 0, sizeof(*h));
     const uint32_t cus = rept_num_cus() ? rept_num_cus() : 256;
     uint32_t fit = 64;
@@ -94,23 +94,23 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     // past the budget, the sparser tables go first, then the default chunk sizes shrink
     // (a shape the caller chose is never changed: it is refused if it does not fit)
     uint32_t light_table = 4;
-    uint32_t lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table);
+    uint32_t lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table, eta);
     // default chunks keep two workgroups per CU where they can (down to 128 lists, 1024 entries)
     while (lds > 80 * 1024 - 256 && ((!own_b_chunk && b_chunk > 128) || (!own_block_cap && block_cap > 1024))) {
         if (!own_b_chunk && b_chunk > 128) b_chunk >>= 1;
         else block_cap >>= 1;
-        lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table);
+        lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table, eta);
     }
     while (lds > 160 * 1024 - 256) {  // static LDS takes a few bytes more
         if (light_table == 4) light_table = 2;
         else if (!own_b_chunk && b_chunk > 128) b_chunk >>= 1;
         else if (!own_block_cap && block_cap > 64) block_cap >>= 1;
         else return REPT_EINVAL;
-        lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table);
+        lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table, eta);
     }
     uint32_t blocks = tu ? tu->blocks : 0;
     if (!blocks) {
-        uint32_t per_cu = rept_count_blocks_per_cu(threads, lds);
+        uint32_t per_cu = rept_count_blocks_per_cu(threads, lds, eta);
         if (per_cu == 0) per_cu = 1;
         if (per_cu > 4) per_cu = 4;
         blocks = per_cu * cus;
@@ -127,6 +127,7 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     h->lds_bytes = lds;
     h->light_table = light_table;
     h->any_zero = any_zero ? 1u : 0u;
+    h->any_eta = eta ? 1u : 0u;
     h->zero_words = zero_words;
     return REPT_OK;
 }
@@ -440,6 +441,121 @@ rept_status rept_reduce_local(const int64_t* local, uint32_t rows, uint32_t n, i
     if (!local || !sums || rows == 0 || n == 0) return REPT_EINVAL;
     if (((uintptr_t)local | (uintptr_t)sums) & 7u) return REPT_EINVAL;
     if (rept_launch_reduce(local, rows, n, sums, (hipStream_t)stream) != hipSuccess) return REPT_EDEVICE;
+    return REPT_OK;
+}
+
+rept_status rept_count_eta_workspace_size(const rept_graph* graph, const rept_params* params, size_t* bytes) {
+    if (!valid_graph(graph) || !params_ok(params) || !bytes) return REPT_EINVAL;
+    const uint32_t G = groups_of(params);
+    if (G > REPT_GMAX) return REPT_ENOTSUP;
+    const size_t pairs = (size_t)8 * G * graph->E;
+    *bytes = table_bytes(graph, G) + ((pairs + 255) & ~(size_t)255);
+    return REPT_OK;
+}
+
+rept_status rept_count_eta(const rept_graph* graph, const rept_params* params, int64_t* global, int64_t* local,
+                           int64_t* eta, int64_t* eta_v, void* workspace, size_t workspace_bytes,
+                           const rept_tuning* tuning, void* stream) {
+    if (!valid_graph(graph) || !params_ok(params) || !global || !local || !eta) return REPT_EINVAL;
+    if (((uintptr_t)eta | (uintptr_t)eta_v) & 7u) return REPT_EINVAL;
+    const uint32_t G = groups_of(params);
+    if (G > REPT_GMAX || params->m > 65536) return REPT_ENOTSUP;
+    size_t need = 0;
+    rept_status st = rept_count_eta_workspace_size(graph, params, &need);
+    if (st != REPT_OK) return st;
+    if (!workspace || ((uintptr_t)workspace & 255u)) return REPT_EINVAL;
+    if (workspace_bytes < need) return REPT_ENOMEM;
+    rept_job jb;
+    memset(&jb, 0, sizeof(jb));
+    jb.graph = graph;
+    jb.params = *params;
+    jb.global = global;
+    jb.local = local;
+    jb.t0 = 0;
+    jb.t1 = graph->E;
+    jb.unit0 = 0;
+    jb.unit1 = UINT32_MAX;
+    jb.workspace = workspace;
+    jb.workspace_bytes = table_bytes(graph, G);
+    JobDev d;
+    uint64_t zw = 0;
+    st = make_job(jb, &d, &zw);
+    if (st != REPT_OK) return st;
+    d.es = (uint32_t)graph->E;
+    d.pairs = (uint32_t*)((uint8_t*)workspace + table_bytes(graph, G));
+    BatchHeader h;
+    st = make_header(1, d.G, d.c, graph->max_out, zw, true, tuning, &h, true);
+    if (st != REPT_OK) return st;
+    h.any_fill = 1;
+    h.fill_edges = graph->E > UINT32_MAX ? UINT32_MAX : (uint32_t)graph->E;
+    hipStream_t s = (hipStream_t)stream;
+    if (rept_launch_zero(d.pairs, (uint64_t)8 * G * graph->E, s) != hipSuccess) return REPT_EDEVICE;
+    if (rept_launch_zero(eta, (uint64_t)16 * params->c, s) != hipSuccess) return REPT_EDEVICE;
+    if (eta_v && rept_launch_zero(eta_v, (uint64_t)16 * graph->n, s) != hipSuccess) return REPT_EDEVICE;
+    if (rept_launch_single(graph->ctrl, h, d, s) != hipSuccess) return REPT_EDEVICE;
+    if (rept_launch_eta(graph, d, eta, eta_v, s) != hipSuccess) return REPT_EDEVICE;
+    return REPT_OK;
+}
+
+namespace {
+// Algorithm 2's combination of the two estimates (Section III-B), one value: S1, S2 the sums
+// over the first c1 groups and over the last group, eta the pair count; binary64 operations in
+// the stated order, t1 when both variances are zero
+double combine(int64_t S1, int64_t S2, int64_t eta, uint32_t m, uint32_t c) {
+    const uint32_t c1 = c / m, c2 = c % m;
+    const double dm = (double)m, dm2 = (double)((uint64_t)m * m), dm3 = (double)((uint64_t)m * m * m);
+    const double dc1 = (double)c1, dc2 = (double)c2, dc = (double)c;
+    const double a2 = (double)((uint64_t)m * m - c2), b2 = (double)(m - c2), dm1 = (double)(m - 1);
+    const double t1 = ((double)S1 * dm) / dc1, t2 = ((double)S2 * dm2) / dc2;
+    const double eh = ((double)eta * dm3) / dc;
+    const double v1 = (t1 * dm1) / dc1, v2 = (t1 * a2 + (2.0 * eh) * b2) / dc2;
+    return (v1 + v2 == 0.0) ? t1 : (v2 * t1 + v1 * t2) / (v1 + v2);
+}
+}  // namespace
+
+rept_status rept_estimate_combined(uint32_t n, const rept_params* params, const int64_t* global,
+                                   const int64_t* local, int64_t eta, const int64_t* eta_v, double* tau_hat,
+                                   double* tau_v_hat) {
+    if (!params_ok(params) || n == 0 || !global || !tau_hat) return REPT_EINVAL;
+    const uint32_t m = params->m, c = params->c;
+    if (c <= m || c % m == 0) return REPT_EINVAL;  // rept_estimate covers these
+    const int64_t lim = (int64_t)1 << 53;
+    const uint32_t c1 = c / m;
+    int64_t S1 = 0, S2 = 0;
+    for (uint32_t i = 0; i < c; ++i) {
+        int64_t* S = i < c1 * m ? &S1 : &S2;
+        if (global[i] < 0 || global[i] >= lim - *S) return REPT_ERANGE;
+        *S += global[i];
+    }
+    if (eta < 0 || eta >= lim) return REPT_ERANGE;
+    if (tau_v_hat && local && eta_v) {
+        const bool per_proc = (params->flags & REPT_LOCAL_PER_PROC) != 0;
+        const uint32_t rows = rept_local_rows(params), split = per_proc ? c1 * m : c1;
+        std::atomic<bool> bad{false};
+        constexpr uint32_t kPart = 32768;
+        const uint32_t parts = (uint32_t)(((uint64_t)n + kPart - 1) / kPart);
+        const std::function<void(uint32_t)> part = [&](uint32_t k) {
+            const uint32_t v0 = k * kPart, v1 = std::min<uint64_t>((uint64_t)v0 + kPart, n);
+            for (uint32_t v = v0; v < v1; ++v) {
+                int64_t A = 0, B = 0;
+                bool ok = eta_v[v] >= 0 && eta_v[v] < lim;
+                for (uint32_t r = 0; r < rows; ++r) {
+                    const int64_t x = local[(uint64_t)r * n + v];
+                    int64_t* S = r < split ? &A : &B;
+                    ok &= x >= 0 && x < lim - *S;
+                    *S += ok ? x : 0;
+                }
+                if (!ok) {
+                    bad = true;
+                    return;
+                }
+                tau_v_hat[v] = combine(A, B, eta_v[v], m, c);
+            }
+        };
+        HostPool::get().run(parts, part);
+        if (bad) return REPT_ERANGE;
+    }
+    *tau_hat = combine(S1, S2, eta, m, c);
     return REPT_OK;
 }
 

@@ -74,7 +74,8 @@ struct JobDev {
     uint32_t gs;                 // slots per stored edge in the slot table (G padded: 1, 2, 4, 8)
     uint16_t* tab;               // slot table [E][gs]: h_k of the edge stored at each position
     uint32_t fill;               // 1: the launch (re)writes the slot table first
-    uint32_t pad[3];
+    uint32_t es;                 // stored edges (rows of the pair counters)
+    uint32_t* pairs;             // Algorithm 2 pair counters [G][es][2] (s, L), or null
 };
 
 // Work queues of the counting kernel: each phase's tiles are split over kQueues interleaved
@@ -104,6 +105,7 @@ struct alignas(128) BatchHeader {
     uint64_t zero_words;   // max words to clear over jobs
     uint32_t any_fill;     // some job's slot table is written by this launch
     uint32_t fill_edges;   // largest stream length over those jobs (bounds their stored edges)
+    uint32_t any_eta;      // some job counts Algorithm 2's pair counters (the kernel's second form)
     uint32_t queues[kQueues * kQueueStride];  // sub-queue counters, reset by setup
 };
 
@@ -125,12 +127,14 @@ hipError_t rept_launch_single(uint8_t* ctrl, const BatchHeader& hdr, const JobDe
                               hipStream_t stream);
 // slots per stored edge in a slot table for G groups (1, 2, 4 or 8)
 inline uint32_t rept_slot_stride(uint32_t G) { return G <= 1 ? 1u : (G <= 2 ? 2u : (G <= 4 ? 4u : 8u)); }
+hipError_t rept_launch_zero(void* p, uint64_t bytes, hipStream_t stream);
+hipError_t rept_launch_eta(const rept_graph* g, const JobDev& d, int64_t* eta, int64_t* eta_v, hipStream_t stream);
 hipError_t rept_launch_reduce(const int64_t* local, uint32_t rows, uint32_t n, int64_t* sums, hipStream_t stream);
 hipError_t rept_launch_slots(const uint64_t* hp, uint32_t G, uint32_t m, const uint32_t* edges,
                              uint64_t E, uint32_t* slots, hipStream_t stream);
-// LDS bytes of the counting kernel for a launch shape
+// LDS bytes of the counting kernel for a launch shape (eta: the form with Algorithm 2's counters)
 uint32_t rept_count_lds(uint32_t threads, uint32_t wave_cap, uint32_t block_cap, uint32_t b_chunk, uint32_t G,
-                        uint32_t hist_c, uint32_t light_table);
+                        uint32_t hist_c, uint32_t light_table, bool eta);
 // resident workgroups per CU of the counting kernel for a launch shape (0 if unknown)
-uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes);
+uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes, bool eta);
 uint32_t rept_num_cus();

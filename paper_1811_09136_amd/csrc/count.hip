@@ -88,11 +88,12 @@ __host__ __device__ inline uint32_t slot_width(uint32_t G) { return G <= 1 ? 1u 
 // wavefronts' light team areas (the heavy phase finishes before the light phase starts).
 struct Area {  // one team's staging area: W side (hash table of a's list) + B side (b lists)
     uint32_t hkey, hidx, ew, et, wslot, cntw;
-    uint32_t eb, etb, bslot, cntb, bpos;
+    uint32_t eb, etb, bslot, cntb, bpos, epos;
     uint32_t red;  // 64 words of team scratch (scans, reductions, broadcast)
     uint32_t bytes;
 };
-__host__ __device__ inline Area area_layout(uint32_t DW, uint32_t DB, uint32_t G, uint32_t tf) {
+// eta: the B side also keeps each staged pair's adjacency position (Algorithm 2's counters)
+__host__ __device__ inline Area area_layout(uint32_t DW, uint32_t DB, uint32_t G, uint32_t tf, bool eta) {
     Area A;
     const uint32_t H = pow2_at_least(tf * DW);
     uint32_t p = 0;
@@ -107,6 +108,7 @@ __host__ __device__ inline Area area_layout(uint32_t DW, uint32_t DB, uint32_t G
     A.bslot = p; p = up16(p + 2 * slot_width(G) * DB);
     A.cntb = p; p = up16(p + 4 * G * DB);
     A.bpos = p; p = up16(p + 8 * (DB + 1));  // (list offset, first item) per staged list
+    A.epos = p; p = eta ? up16(p + 4 * DB) : p;  // position of the pair {a, b} in the adjacency
     A.red = p; p = up16(p + 4 * 64);
     A.bytes = p;
     return A;
@@ -130,11 +132,11 @@ struct Layout {
     uint32_t union_off, total;
 };
 __host__ __device__ inline Layout count_layout(uint32_t nwaves, uint32_t DL, uint32_t DW, uint32_t DB,
-                                               uint32_t G, uint32_t HC, uint32_t LT) {
+                                               uint32_t G, uint32_t HC, uint32_t LT, bool eta) {
     Layout L;
     L.misc = misc_layout(HC);
-    L.heavy = area_layout(DW, DB, G, kHeavyTable);
-    L.light = area_layout(DL, DL, G, LT);
+    L.heavy = area_layout(DW, DB, G, kHeavyTable, eta);
+    L.light = area_layout(DL, DL, G, LT, eta);
     L.union_off = nwaves * L.misc.bytes;
     const uint32_t u = L.heavy.bytes > nwaves * L.light.bytes ? L.heavy.bytes : nwaves * L.light.bytes;
     L.total = L.union_off + u;
@@ -154,6 +156,7 @@ struct TeamView {
     uint16_t* bslot;  // [DB][gs] slot rows of the B entries
     uint32_t* cntb;
     uint2* bpos;  // .x: offset of b's list, .y: index of its first item in the chunk's walk
+    uint32_t* epos;  // adjacency position of each staged pair {a, b}
     uint32_t* red;
     uint32_t DW, DB;
     uint32_t tf;  // hash slots per key, at least
@@ -172,6 +175,7 @@ __device__ inline TeamView team_view(uint8_t* base, const Area& A, uint32_t DW, 
     T.bslot = (uint16_t*)(base + A.bslot);
     T.cntb = (uint32_t*)(base + A.cntb);
     T.bpos = (uint2*)(base + A.bpos);
+    T.epos = (uint32_t*)(base + A.epos);
     T.red = (uint32_t*)(base + A.red);
     T.DW = DW;
     T.DB = DB;
@@ -204,7 +208,8 @@ struct JobRegs {
     int64_t* global;
     int64_t* local;
     const uint16_t* tab;  // slot table of the stored edges, gs slots per edge
-    uint32_t n, m, c, G, gs, per_proc, t0, t1, last_ck, use_hist;
+    uint32_t* pairs;      // Algorithm 2 pair counters [G][es][2], or null
+    uint32_t n, m, c, G, gs, per_proc, t0, t1, last_ck, use_hist, es;
 };
 
 __device__ inline void load_job(const JobDev* __restrict__ j, uint32_t HC, JobRegs& r) {
@@ -218,6 +223,8 @@ __device__ inline void load_job(const JobDev* __restrict__ j, uint32_t HC, JobRe
     r.global = j->global;
     r.local = j->local;
     r.tab = j->tab;
+    r.pairs = j->pairs;
+    r.es = j->es;
     r.gs = j->gs;
     r.n = j->n;
     r.m = j->m;
@@ -431,8 +438,9 @@ __device__ __forceinline__ uint32_t team_sum(uint32_t v, uint32_t* red) {
 // entry k, list position p): the triangle (a, b = eb[ib], w = ew[k]) with times t_ab = etb[ib],
 // t_aw = et[k], t_bw = tim[p].  Its first two edges by time decide the processor per group:
 // edges at a have their slots staged; the slots of {b, w} come from the slot table.
-template <uint32_t GS>
-__device__ void drain_hits_t(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a, uint32_t qn) {
+template <uint32_t GS, bool ETA>
+__device__ void drain_hits_t(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a, uint32_t wbase,
+                             uint32_t qn) {
     const uint32_t lane = lane_id();
     for (uint32_t q0 = 0; q0 < qn; q0 += 64) {
         const uint32_t q = q0 + lane;
@@ -487,6 +495,21 @@ __device__ void drain_hits_t(const JobRegs& J, const TeamView& T, const WaveView
                             atomicAdd(&T.cntb[g * T.DB + ib], 1u);
                             atomicAdd(&T.cntw[g * T.DW + k], 1u);
                         }
+                        if (ETA && J.pairs) {
+                            // Algorithm 2's per-edge counts (Section III-B): the first two edges
+                            // gain a non-last occurrence; the last edge a last-edge occurrence
+                            // when the same processor stores it
+                            const uint32_t pab = T.epos[ib], paw = wbase + k;
+                            const uint32_t pf1 = last == 0 ? paw : pab, pf2 = last == 2 ? paw : p;
+                            const uint32_t pl = last == 0 ? pab : (last == 1 ? paw : p);
+                            uint32_t* cg = J.pairs + 2 * (uint64_t)g * J.es;
+                            atomicAdd(cg + 2 * (uint64_t)pf1, 1u);
+                            atomicAdd(cg + 2 * (uint64_t)pf2, 1u);
+                            const uint64_t llo = last == 0 ? alo : (last == 1 ? wlo : blo);
+                            const uint64_t lhi = last == 0 ? ahi : (last == 1 ? whi : bhi);
+                            const uint32_t sl = (uint32_t)((g < 4 ? llo >> (16 * g) : lhi >> (16 * (g - 4))) & 0xffffu);
+                            if (sl == s1) atomicAdd(cg + 2 * (uint64_t)pl + 1, 1u);
+                        }
                     }
                 }
             }
@@ -496,12 +519,13 @@ __device__ void drain_hits_t(const JobRegs& J, const TeamView& T, const WaveView
 }
 
 // the drain for the job's slot-row width (uniform over the wavefront)
+template <bool ETA>
 __device__ __forceinline__ void drain_hits(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a,
-                                           uint32_t qn) {
-    if (J.gs == 1) drain_hits_t<1>(J, T, V, a, qn);
-    else if (J.gs == 2) drain_hits_t<2>(J, T, V, a, qn);
-    else if (J.gs == 4) drain_hits_t<4>(J, T, V, a, qn);
-    else drain_hits_t<8>(J, T, V, a, qn);
+                                           uint32_t wbase, uint32_t qn) {
+    if (J.gs == 1) drain_hits_t<1, ETA>(J, T, V, a, wbase, qn);
+    else if (J.gs == 2) drain_hits_t<2, ETA>(J, T, V, a, wbase, qn);
+    else if (J.gs == 4) drain_hits_t<4, ETA>(J, T, V, a, wbase, qn);
+    else drain_hits_t<8, ETA>(J, T, V, a, wbase, qn);
 }
 
 // popcount of the bits of `m` below this lane
@@ -516,8 +540,9 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 // starts after the round's first item and at or before its own.  The owners, the neighbour
 // loads and the first hash probes of all windows of a round are issued together.
 // A hit is queued as (owner | hash slot << 16, list position).
-__device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a, uint32_t kbits,
-                           uint32_t bn, uint32_t it_begin, uint32_t it_end) {
+template <bool ETA>
+__device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a, uint32_t wbase,
+                           uint32_t kbits, uint32_t bn, uint32_t it_begin, uint32_t it_end) {
     constexpr uint32_t R = 64 * kWalk;
     const uint32_t lane = lane_id();
     const uint32_t bmask = (1u << kbits) - 1u;
@@ -566,7 +591,7 @@ __device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& 
         if (qn >= 64) {
             wave_sync();
             const uint32_t full = qn & ~63u, rem = qn - full;
-            drain_hits(J, T, V, a, full);
+            drain_hits<ETA>(J, T, V, a, wbase, full);
             if (rem) {
                 uint32_t v = 0, pp = 0;
                 if (lane < rem) {
@@ -632,7 +657,7 @@ __device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& 
     }
     if (qn) {
         wave_sync();
-        drain_hits(J, T, V, a, qn);
+        drain_hits<ETA>(J, T, V, a, wbase, qn);
     }
 }
 
@@ -640,7 +665,7 @@ __device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& 
 // this wavefront.  a's list is hashed into LDS in chunks of DW entries (W side); for each W
 // chunk the lists of all of a's out-neighbours are walked in chunks of DB entries (B side).
 // (s, d): offset and length of a's list; (r0, rn): offset and length of a's reverse list.
-template <bool BLOCK>
+template <bool BLOCK, bool ETA>
 __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a, uint32_t s,
                            uint32_t d, uint32_t r0, uint32_t rn) {
     const uint32_t nt = BLOCK ? blockDim.x : 64;
@@ -708,6 +733,7 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                     T.eb[pos] = b;
                     T.etb[pos] = tb;
                     T.bpos[pos] = make_uint2(bo, sc);
+                    if (ETA) T.epos[pos] = pab;
                     // an own pair {a, b} is also a W entry when it falls in the current W chunk
                     const bool staged = e >= ws && e < ws + wn;
                     uint64_t lo = 0, hi = 0;
@@ -727,7 +753,7 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                 const uint32_t per = (nwin + nw - 1) / nw;
                 const uint32_t w0 = wid * per, w1 = (w0 + per) < nwin ? (w0 + per) : nwin;
                 const uint32_t ib = w0 * 64, ie = (w1 * 64) < items ? (w1 * 64) : items;
-                if (w0 < w1) walk_items(J, T, V, a, kbits, nb, ib, ie);
+                if (w0 < w1) walk_items<ETA>(J, T, V, a, s + ws, kbits, nb, ib, ie);
             }
             team_sync<BLOCK>();
             if (!J.per_proc) {
@@ -909,6 +935,82 @@ __global__ void __launch_bounds__(256) k_fill(const JobDev* __restrict__ jobs) {
     }
 }
 
+// Algorithm 2's triangle-pair counts from the per-edge counters (Section III-B).  For a stored
+// edge g of processor i (group k, slot h_k(g)): s = semi-triangles of i with g as a non-last
+// edge, L = those with g as the last edge.  The definition of eta^(i) counts C(s, 2) pairs at
+// g; Algorithm 2 as printed, whose counter starts at |N| when g is inserted, counts
+// s L + C(s, 2).  Both go to eta[0][i], eta[1][i]; each edge's share also goes to both of its
+// endpoints in eta_v[0][.], eta_v[1][.] (summed over processors).  Work split as in k_fill.
+constexpr uint32_t ETA_LDS_PROCS = 512;  // processors accumulated in LDS per workgroup
+__global__ void __launch_bounds__(256) k_eta(const uint32_t* __restrict__ off, const uint32_t* __restrict__ nbr,
+                                             uint32_t n, const uint16_t* __restrict__ tab, uint32_t gs, uint32_t G,
+                                             uint32_t m, uint32_t c, const uint32_t* __restrict__ pairs, uint32_t es,
+                                             int64_t* __restrict__ eta, int64_t* __restrict__ eta_v) {
+    __shared__ uint32_t so[FILL_NODES + 1];
+    __shared__ unsigned long long acc[2][ETA_LDS_PROCS];
+    const bool in_lds = c <= ETA_LDS_PROCS;
+    for (uint32_t i = threadIdx.x; i < ETA_LDS_PROCS; i += 256u) acc[0][i] = acc[1][i] = 0ull;
+    const uint32_t Es = ldg(off + n);
+    for (uint64_t c0 = (uint64_t)blockIdx.x * FILL_CHUNK; c0 < Es; c0 += (uint64_t)gridDim.x * FILL_CHUNK) {
+        const uint32_t p0 = (uint32_t)c0, p1 = (c0 + FILL_CHUNK) < Es ? (uint32_t)(c0 + FILL_CHUNK) : Es;
+        const uint32_t bf = fill_owner(off, n, p0), bl = fill_owner(off, n, p1 - 1u);
+        for (uint32_t w0 = bf; w0 <= bl; w0 += FILL_NODES) {
+            const uint32_t cnt = (bl + 1u - w0) < FILL_NODES ? (bl + 1u - w0) : FILL_NODES;
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i <= cnt; i += 256u) so[i] = ldg(off + w0 + i);
+            __syncthreads();
+            const uint32_t q0 = so[0] > p0 ? so[0] : p0, q1 = so[cnt] < p1 ? so[cnt] : p1;
+            for (uint32_t p = q0 + threadIdx.x; p < q1; p += 256u) {
+                unsigned long long fd = 0, fl = 0;
+                for (uint32_t k = 0; k < G; ++k) {
+                    const uint64_t w2 = ldg((const uint64_t*)pairs + (uint64_t)k * es + p);  // (s, L)
+                    const uint32_t sx = (uint32_t)w2, ly = (uint32_t)(w2 >> 32);
+                    const uint32_t slot = ldg(tab + (uint64_t)p * gs + k);
+                    // an edge counts only for an active processor (inactive slots stay at zero)
+                    if (sx == 0 || k * m + slot >= c) continue;
+                    const unsigned long long d = (unsigned long long)sx * (sx - 1u) / 2u;
+                    const unsigned long long l = d + (unsigned long long)sx * ly;
+                    const uint32_t proc = k * m + slot;
+                    if (in_lds) {
+                        atomicAdd(&acc[0][proc], d);
+                        atomicAdd(&acc[1][proc], l);
+                    } else {
+                        atomicAdd((unsigned long long*)eta + proc, d);
+                        atomicAdd((unsigned long long*)eta + c + proc, l);
+                    }
+                    fd += d;
+                    fl += l;
+                }
+                if (eta_v && (fd | fl)) {
+                    uint32_t lo = 0, hi = cnt;  // so[lo] <= p < so[hi]
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (so[mid] <= p) lo = mid; else hi = mid;
+                    }
+                    const uint32_t a = w0 + lo, b = ldg(nbr + p);
+                    atomicAdd((unsigned long long*)eta_v + a, fd);
+                    atomicAdd((unsigned long long*)eta_v + b, fd);
+                    atomicAdd((unsigned long long*)eta_v + n + a, fl);
+                    atomicAdd((unsigned long long*)eta_v + n + b, fl);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (in_lds) {
+        for (uint32_t i = threadIdx.x; i < c; i += 256u) {
+            if (acc[0][i]) atomicAdd((unsigned long long*)eta + i, acc[0][i]);
+            if (acc[1][i]) atomicAdd((unsigned long long*)eta + c + i, acc[1][i]);
+        }
+    }
+}
+
+// zero n 32-bit words (a kernel rather than a memset, so the sequence stays capture-safe)
+__global__ void k_zero_u32(uint32_t* p, uint64_t words) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 // ======================================================================= count kernel ====
 
 // Claim the next tile of a phase's queue (counters at ctr[q * kQueueStride]).  The caller starts
@@ -927,13 +1029,16 @@ __device__ uint32_t claim_tile(uint32_t* ctr, uint32_t total, uint32_t& q, uint3
     return total;
 }
 
+// ETA: the form that also counts Algorithm 2's per-edge pair counters for jobs that ask for
+// them (a separate instance, so the plain kernel's registers are not spent on them)
+template <bool ETA>
 __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* __restrict__ jobs) {
     extern __shared__ __align__(16) uint8_t lds[];
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const uint32_t DL = hdr->wave_cap, DW = hdr->block_cap, DB = hdr->b_chunk;
     const uint32_t GM = hdr->G_max, HC = hdr->hist_c, njobs = hdr->njobs;
     const uint32_t LT = hdr->light_table;
-    const Layout L = count_layout(nw, DL, DW, DB, GM, HC, LT);
+    const Layout L = count_layout(nw, DL, DW, DB, GM, HC, LT, ETA);
     const WaveView V = wave_view(lds + wid * L.misc.bytes, L.misc);
     uint8_t* uni = lds + L.union_off;
     __shared__ uint32_t s_tile;
@@ -962,7 +1067,7 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
             __syncthreads();
             const uint32_t a = J.apex[jobs[j].unit0 + (tile - jobs[j].heavy_prefix)];
             const uint32_t s0 = J.off[a], r0 = J.roff[a];
-            count_apex<true>(J, T, V, a, s0, J.off[a + 1] - s0, r0, J.roff[a + 1] - r0);
+            count_apex<true, ETA>(J, T, V, a, s0, J.off[a + 1] - s0, r0, J.roff[a + 1] - r0);
         }
     }
     __syncthreads();  // the union area changes owners
@@ -997,7 +1102,7 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
                 trn = ldg(J.roff + ta + 1) - tr;
             }
             for (uint32_t u = 0; u < ue - ub; ++u)
-                count_apex<false>(J, T, V, __shfl(ta, u, 64), __shfl(ts, u, 64), __shfl(td, u, 64), __shfl(tr, u, 64),
+                count_apex<false, ETA>(J, T, V, __shfl(ta, u, 64), __shfl(ts, u, 64), __shfl(td, u, 64), __shfl(tr, u, 64),
                                   __shfl(trn, u, 64));
         }
     }
@@ -1039,9 +1144,11 @@ hipError_t report(hipError_t e, const char* what) {
 hipError_t set_attrs() {
     if (g_attr_set) return hipSuccess;
     // the kernel's static LDS (a few bytes) and the dynamic part share the CU's 160 KB
-    hipError_t e = hipFuncSetAttribute((const void*)k_count, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void*)k_count<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        160 * 1024 - 256);
     if (e != hipSuccess) return report(e, "hipFuncSetAttribute(k_count)");
+    e = hipFuncSetAttribute((const void*)k_count<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
+    if (e != hipSuccess) return report(e, "hipFuncSetAttribute(k_count, pair counters)");
     g_attr_set = true;
     return hipSuccess;
 }
@@ -1065,22 +1172,23 @@ hipError_t launch_common(uint8_t* ws, const BatchHeader& h, hipStream_t s) {
         if (blocks < 1) blocks = 1;
         hipLaunchKernelGGL(k_fill, dim3((uint32_t)blocks, h.njobs), dim3(256), 0, s, jobs);
     }
-    hipLaunchKernelGGL(k_count, dim3(h.blocks), dim3(h.threads), h.lds_bytes, s, hdr, jobs);
+    if (h.any_eta) hipLaunchKernelGGL(k_count<true>, dim3(h.blocks), dim3(h.threads), h.lds_bytes, s, hdr, jobs);
+    else hipLaunchKernelGGL(k_count<false>, dim3(h.blocks), dim3(h.threads), h.lds_bytes, s, hdr, jobs);
     return report(hipGetLastError(), "counting kernel launch");
 }
 
 }  // namespace
 
 uint32_t rept_count_lds(uint32_t threads, uint32_t wave_cap, uint32_t block_cap, uint32_t b_chunk, uint32_t G,
-                        uint32_t hist_c, uint32_t light_table) {
-    return count_layout(threads / 64, wave_cap, block_cap, b_chunk, G, hist_c, light_table).total;
+                        uint32_t hist_c, uint32_t light_table, bool eta) {
+    return count_layout(threads / 64, wave_cap, block_cap, b_chunk, G, hist_c, light_table, eta).total;
 }
 
-uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes) {
+uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes, bool eta) {
     if (set_attrs() != hipSuccess) return 0;
     int nb = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_count, (int)threads,
-                                                                (size_t)lds_bytes);
+    const void* fn = eta ? (const void*)k_count<true> : (const void*)k_count<false>;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, (int)threads, (size_t)lds_bytes);
     if (e != hipSuccess) {
         (void)report(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor(k_count)");
         (void)hipGetLastError();
@@ -1103,6 +1211,26 @@ hipError_t rept_launch_reduce(const int64_t* local, uint32_t rows, uint32_t n, i
     uint32_t blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_reduce_rows, dim3(blocks), dim3(256), 0, s, local, rows, n, sums);
+    return hipGetLastError();
+}
+
+hipError_t rept_launch_zero(void* p, uint64_t bytes, hipStream_t s) {
+    (void)hipGetLastError();
+    const uint64_t words = bytes / 4;
+    uint64_t blocks = (words + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_zero_u32, dim3((uint32_t)blocks), dim3(256), 0, s, (uint32_t*)p, words);
+    return hipGetLastError();
+}
+
+hipError_t rept_launch_eta(const rept_graph* g, const JobDev& d, int64_t* eta, int64_t* eta_v, hipStream_t s) {
+    (void)hipGetLastError();
+    uint64_t blocks = (g->E + FILL_CHUNK - 1) / FILL_CHUNK;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_eta, dim3((uint32_t)blocks), dim3(256), 0, s, g->off, g->nbr, g->n, (const uint16_t*)d.tab,
+                       d.gs, d.G, d.m, d.c, (const uint32_t*)d.pairs, d.es, eta, eta_v);
     return hipGetLastError();
 }
 

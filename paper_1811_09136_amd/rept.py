@@ -81,6 +81,9 @@ def lib() -> ctypes.CDLL:
             "rept_count_range": ([vp, P(rept_params), u64, u64, vp, vp, vp, sz, vp], i32),
             "rept_estimate": ([u32, P(rept_params), vp, vp, vp, vp], i32),
             "rept_estimate_sums": ([u32, P(rept_params), vp, vp, vp, vp], i32),
+            "rept_count_eta_workspace_size": ([vp, P(rept_params), P(sz)], i32),
+            "rept_count_eta": ([vp, P(rept_params), vp, vp, vp, vp, vp, sz, P(rept_tuning), vp], i32),
+            "rept_estimate_combined": ([u32, P(rept_params), vp, vp, ctypes.c_int64, vp, vp, vp], i32),
             "rept_reduce_local": ([vp, u32, u32, vp, vp], i32),
             "rept_hash_slots": ([P(rept_params), vp, u64, vp, vp], i32),
             "rept_batch_workspace_size": ([u32, P(sz)], i32),
@@ -101,7 +104,8 @@ def lib() -> ctypes.CDLL:
 
 EXPORTED = ["rept_local_rows", "rept_query_sizes", "rept_build", "rept_build_host", "rept_graph_get_info",
             "rept_count_workspace_size", "rept_count",
-            "rept_count_range", "rept_estimate", "rept_estimate_sums", "rept_reduce_local", "rept_hash_slots", "rept_batch_workspace_size",
+            "rept_count_range", "rept_estimate", "rept_estimate_sums", "rept_count_eta_workspace_size",
+            "rept_count_eta", "rept_estimate_combined", "rept_reduce_local", "rept_hash_slots", "rept_batch_workspace_size",
             "rept_batch_prepare", "rept_batch_launch", "rept_batch_count", "rept_destroy", "rept_status_str",
             "rept_device_cus"]
 
@@ -247,6 +251,41 @@ def rept_estimate_sums(n: int, params: Params, glob: np.ndarray, sums: np.ndarra
     return th.value, tv
 
 
+def rept_count_eta_workspace_size(handle: int, params: Params) -> int:
+    p = params.c_struct()
+    b = ctypes.c_size_t(0)
+    _check(lib().rept_count_eta_workspace_size(handle, ctypes.byref(p), ctypes.byref(b)),
+           "rept_count_eta_workspace_size")
+    return b.value
+
+
+def rept_count_eta(handle: int, params: Params, global_ptr: int, local_ptr: int, eta_ptr: int, eta_v_ptr: int | None,
+                   ws_ptr: int, ws_bytes: int, tuning: rept_tuning | None, stream_ptr: int | None):
+    p = params.c_struct()
+    _check(lib().rept_count_eta(handle, ctypes.byref(p), global_ptr, local_ptr, eta_ptr, eta_v_ptr, ws_ptr, ws_bytes,
+                                None if tuning is None else ctypes.byref(tuning), stream_ptr), "rept_count_eta")
+
+
+def rept_estimate_combined(n: int, params: Params, glob: np.ndarray, loc: np.ndarray | None, eta: int,
+                           eta_v: np.ndarray | None):
+    """Algorithm 2's combined FP64 estimators (c > m, m not dividing c); returns
+    (tau_hat, tau_v_hat or None).  eta: sum of the definition counters; eta_v: int64[n]."""
+    p = params.c_struct()
+    g = np.ascontiguousarray(glob, dtype=np.int64)
+    th = ctypes.c_double(0.0)
+    tv = lp = ep = None
+    if loc is not None and eta_v is not None:
+        lo = np.ascontiguousarray(loc, dtype=np.int64)
+        ev = np.ascontiguousarray(eta_v, dtype=np.int64)
+        if ev.shape != (n,):
+            raise ValueError("eta_v must hold n values")
+        tv = np.empty(n, dtype=np.float64)
+        lp, ep = lo.ctypes.data, ev.ctypes.data
+    _check(lib().rept_estimate_combined(n, ctypes.byref(p), g.ctypes.data, lp, int(eta), ep, ctypes.addressof(th),
+                                        None if tv is None else tv.ctypes.data), "rept_estimate_combined")
+    return th.value, tv
+
+
 def rept_reduce_local(local_ptr: int, rows: int, n: int, sums_ptr: int, stream_ptr: int | None):
     """sums[v] = sum of the rows of local at v, on the device (exact int64)."""
     _check(lib().rept_reduce_local(local_ptr, rows, n, sums_ptr, stream_ptr), "rept_reduce_local")
@@ -357,6 +396,21 @@ class Graph:
         rept_count_range(self.handle, params, t0, t1, g.data_ptr(), l.data_ptr(), ws.data_ptr(), ws.numel(),
                          _stream_ptr(stream))
         return g, l
+
+    def count_eta(self, params: Params, stream=None, with_nodes: bool = True, tuning: rept_tuning | None = None):
+        """Counts with Algorithm 2's pair counters: (global[c], local[rows][n], eta[2][c],
+        eta_v[2][n] or None); row 0 of eta / eta_v is the definition counter, row 1 the
+        counter as printed in Algorithm 2."""
+        torch = self._torch
+        g, l = self.outputs(params)
+        eta = torch.empty((2, params.c), dtype=torch.int64, device=self.device)
+        eta_v = torch.empty((2, self.n), dtype=torch.int64, device=self.device) if with_nodes else None
+        ws = _alloc(rept_count_eta_workspace_size(self.handle, params), self.device)
+        rept_count_eta(self.handle, params, g.data_ptr(), l.data_ptr(), eta.data_ptr(),
+                       None if eta_v is None else eta_v.data_ptr(), ws.data_ptr(), ws.numel(), tuning,
+                       _stream_ptr(stream))
+        self._eta_ws = ws  # kept until the next call: the work on `stream` may still read it
+        return g, l, eta, eta_v
 
     def close(self):
         if getattr(self, "handle", None):

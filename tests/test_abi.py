@@ -158,3 +158,45 @@ def test_estimators_from_concurrent_host_threads():
     for t in ts:
         t.join()
     assert not errors
+
+
+@pytest.mark.parametrize("m,c,per_proc", [(10, 15, False), (2, 3, False), (3, 7, True), (100, 250, False),
+                                          (7, 50, True)])
+def test_estimate_combined_zero_ulp_against_oracle(m, c, per_proc):
+    """Algorithm 2's combined estimators (Section III-B) from the library equal the oracle's bit
+    for bit, global and local, over group rows or processor rows, at a size split over the host
+    pool; sums at 2^53 or below 0 are ERANGE; c <= m or m | c is EINVAL."""
+    from paper_1811_09136_amd import rept
+    rng = np.random.default_rng(13 * m + c)
+    n = 70_001
+    rows = c if per_proc else -(-c // m)
+    glob = rng.integers(0, 2**36, size=c)
+    loc = rng.integers(0, 2**38, size=(rows, n))
+    eta = int(rng.integers(0, 2**45))
+    eta_v = rng.integers(0, 2**40, size=n)
+    loc[:, 5] = 0  # a node with no counts at all: both variances zero
+    eta_v[5] = 0
+    P = rept.Params(m, c, 0, per_proc=per_proc)
+    th, tv = rept.rept_estimate_combined(n, P, glob, loc, eta, eta_v)
+    oth, otv = oracle.estimate2(n, m, c, glob, loc, eta, eta_v, per_proc=per_proc)
+    assert th == oth and np.array_equal(tv.view(np.uint64), otv.view(np.uint64))
+    assert tv[5] == 0.0
+    th0, tv0 = rept.rept_estimate_combined(n, P, glob, None, eta, None)
+    assert th0 == oth and tv0 is None
+    for what, bad in [("eta", None), ("eta_v", n - 1), ("loc", n // 2)]:
+        g2, l2, e2, v2 = glob, loc, eta, eta_v
+        if what == "eta":
+            e2 = 2**53
+        elif what == "eta_v":
+            v2 = eta_v.copy()
+            v2[bad] = -1
+        else:
+            l2 = loc.copy()
+            l2[-1, bad] = 2**53
+        with pytest.raises(rept.ReptError) as ei:
+            rept.rept_estimate_combined(n, P, g2, l2, e2, v2)
+        assert ei.value.code == rept.REPT_ERANGE
+    for mm, cc in [(10, 10), (10, 40), (10, 7)]:
+        with pytest.raises(rept.ReptError) as ei:
+            rept.rept_estimate_combined(n, rept.Params(mm, cc, 0), np.zeros(cc, np.int64), None, 0, None)
+        assert ei.value.code == rept.REPT_EINVAL
