@@ -78,6 +78,10 @@ def _load():
         L.oracle_rept2_eta.restype = i32
         L.oracle_estimate2.argtypes = [u32, u32, u32, u32, i32, vp, vp, ctypes.c_int64, vp, vp, vp]
         L.oracle_estimate2.restype = i32
+        L.oracle_mascot.argtypes = [u32, u32, u32, u64, vp, u64, vp, vp]
+        L.oracle_mascot.restype = i32
+        L.oracle_estimate_mascot.argtypes = [u32, u32, u32, vp, vp, vp, vp]
+        L.oracle_estimate_mascot.restype = i32
         _lib = L
     return _lib
 
@@ -240,4 +244,35 @@ def estimate2(n: int, m: int, c: int, glob, loc=None, eta: int = 0, eta_v=None, 
                                   ctypes.addressof(th), None if tv is None else tv.ctypes.data)
     if rc != OK:
         raise OracleError(rc, "oracle_estimate2")
+    return th.value, tv
+
+
+def mascot(edges, n: int, m: int, c: int, seed: int):
+    """Parallel MASCOT (Section III-C): c processors, each keeping every edge independently with
+    probability 1/m (processor i keeps e iff h_i(e) = 0, h_i the hash of group i); returns
+    (global[c], local[c][n]) of the per-processor counters of Algorithm 1's counting step."""
+    e = _edges(edges)
+    glob = np.zeros(c, dtype=np.int64)
+    loc = np.zeros((c, n), dtype=np.int64)
+    rc = _load().oracle_mascot(n, m, c, seed & (2**64 - 1), e.ctypes.data, len(e), glob.ctypes.data,
+                               loc.ctypes.data)
+    if rc != OK:
+        raise OracleError(rc, "oracle_mascot")
+    return glob, loc
+
+
+def estimate_mascot(n: int, m: int, c: int, glob, loc=None):
+    """Parallel MASCOT's estimators (the mean of the processors' m^2 tau^(i)): (tau_hat,
+    tau_v_hat[n] or None)."""
+    g = np.ascontiguousarray(np.asarray(glob, dtype=np.int64))
+    th = ctypes.c_double(0.0)
+    tv = lp = None
+    if loc is not None:
+        lo = np.ascontiguousarray(np.asarray(loc, dtype=np.int64))
+        tv = np.zeros(n, dtype=np.float64)
+        lp = lo.ctypes.data
+    rc = _load().oracle_estimate_mascot(n, m, c, g.ctypes.data, lp, ctypes.addressof(th),
+                                        None if tv is None else tv.ctypes.data)
+    if rc != OK:
+        raise OracleError(rc, "oracle_estimate_mascot")
     return th.value, tv

@@ -607,3 +607,114 @@ int oracle_estimate2(uint32_t n, uint32_t m, uint32_t c, uint32_t local_rows, in
     }
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------ parallel MASCOT ------ */
+
+/*
+ * Parallel MASCOT (Section III-C; MASCOT by Lim and Kang, KDD 2015): c processors, each
+ * running MASCOT with edge sampling probability p = 1/m independently of the others.  For
+ * every stream edge (u, v) at time t, processor i counts N = N_u^(i) intersect N_v^(i) over its
+ * own sampled edges that arrived before t, adds |N| to its counter tau^(i) and to tau_u^(i),
+ * tau_v^(i), and 1 to tau_w^(i) for each w in N; then it keeps (u, v) with probability p.
+ * The counting step is Algorithm 1's; only the sampling differs from REPT: the processors'
+ * samples overlap instead of partitioning the stream.
+ *
+ * The independent coin of processor i is drawn from the same hash family as REPT's groups:
+ * processor i keeps edge e iff h_i(e) == 0, where h_i : E -> [0, m) has the coefficients of
+ * group i (SplitMix64 outputs 4i..4i+3 of `seed`).  So P(keep) = 1/m, and different processors
+ * use independent hash functions (one group each).
+ * Outputs (overwritten): global[i] = tau^(i) (c entries); local[i*n + v] = tau_v^(i).
+ */
+int oracle_mascot(uint32_t n, uint32_t m, uint32_t c, uint64_t seed, const uint32_t *edges, uint64_t E,
+                  int64_t *global, int64_t *local) {
+    if (n == 0 || m == 0 || c == 0 || !edges || !global || !local) return OR_EINVAL;
+    int rc = oracle_validate(n, edges, E);
+    if (rc) return rc;
+    uint64_t *params = (uint64_t *)malloc(sizeof(uint64_t) * 4 * c);
+    adjlist *adj = (adjlist *)calloc(n, sizeof(adjlist));
+    uint8_t *keep = (uint8_t *)malloc(E ? E : 1);
+    if (!params || !adj || !keep) {
+        rc = OR_ENOMEM;
+        goto done;
+    }
+    memset(global, 0, sizeof(int64_t) * c);
+    memset(local, 0, sizeof(int64_t) * (uint64_t)c * n);
+    oracle_hash_params(seed, c, params);
+    for (uint32_t i = 0; i < c && rc == OR_OK; ++i) {
+        uint64_t kept = 0;
+        for (uint64_t t = 0; t < E; ++t) {
+            keep[t] = oracle_slot(params + 4 * i, m, edges[2 * t], edges[2 * t + 1]) == 0;
+            kept += keep[t];
+        }
+        edgeset Si; /* the sample of processor i */
+        if (es_init(&Si, kept)) {
+            rc = OR_ENOMEM;
+            break;
+        }
+        int64_t *loc = local + (uint64_t)i * n;
+        for (uint32_t x = 0; x < n; ++x) adj[x].len = 0;
+        for (uint64_t t = 0; t < E; ++t) {
+            const uint32_t u = edges[2 * t], v = edges[2 * t + 1];
+            const adjlist *small = adj[u].len <= adj[v].len ? &adj[u] : &adj[v];
+            const uint32_t other = adj[u].len <= adj[v].len ? v : u;
+            int64_t cnt = 0;
+            for (uint32_t q = 0; q < small->len; ++q) {
+                const uint32_t w = small->nbr[q];
+                if (es_get(&Si, pairkey(other, w), NULL)) {
+                    ++cnt;
+                    loc[w] += 1;
+                }
+            }
+            global[i] += cnt;
+            loc[u] += cnt;
+            loc[v] += cnt;
+            if (keep[t]) {
+                es_put(&Si, pairkey(u, v), t);
+                if (adj_push(&adj[u], v) || adj_push(&adj[v], u)) {
+                    rc = OR_ENOMEM;
+                    break;
+                }
+            }
+        }
+        es_free(&Si);
+    }
+done:
+    if (adj)
+        for (uint32_t x = 0; x < n; ++x) free(adj[x].nbr);
+    free(adj);
+    free(keep);
+    free(params);
+    return rc;
+}
+
+/*
+ * Parallel MASCOT's estimators: each processor's estimate is m^2 tau^(i) (MASCOT scales a
+ * counted triangle by 1/p^2), and the parallel estimate is their mean,
+ *   tau_hat = ((double)S * (double)(m*m)) / (double)c,   S = sum_i tau^(i),
+ * and per node with S_v = sum_i tau_v^(i) (local: c rows of n); binary64, one rounding for
+ * the product and one for the quotient; a sum below 0 or at or above 2^53 is ERANGE.
+ */
+int oracle_estimate_mascot(uint32_t n, uint32_t m, uint32_t c, const int64_t *global, const int64_t *local,
+                           double *tau_hat, double *tau_v_hat) {
+    if (n == 0 || m == 0 || c == 0 || !global || !tau_hat) return OR_EINVAL;
+    const int64_t lim = (int64_t)1 << 53;
+    const double num = (double)((uint64_t)m * m), den = (double)c;
+    int64_t S = 0;
+    for (uint32_t i = 0; i < c; ++i) {
+        if (global[i] < 0 || global[i] >= lim - S) return OR_ERANGE;
+        S += global[i];
+    }
+    if (tau_v_hat && local) {
+        for (uint32_t v = 0; v < n; ++v) {
+            int64_t Sv = 0;
+            for (uint32_t i = 0; i < c; ++i) {
+                const int64_t x = local[(uint64_t)i * n + v];
+                if (x < 0 || x >= lim - Sv) return OR_ERANGE;
+                Sv += x;
+            }
+            tau_v_hat[v] = ((double)Sv * num) / den;
+        }
+    }
+    *tau_hat = ((double)S * num) / den;
+    return OR_OK;
+}

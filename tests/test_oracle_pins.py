@@ -481,3 +481,72 @@ def test_alg2_estimator_unbiased_over_seeds():
         est.append(oracle.estimate2(60, m, c, g, None, eta, None)[0])
     se = np.std(est) / np.sqrt(len(est))
     assert tau > 0 and abs(np.mean(est) - tau) < 5 * se
+
+
+# ------------------------------------------------------------------ parallel MASCOT -------
+
+def test_mascot_one_is_exact():
+    """m = 1 (p = 1): every processor keeps every edge, so each processor's counters are the
+    exact triangle counts (the adjacency-matrix identity, not an enumeration)."""
+    e = synth.er(40, 300, 51, 52)
+    tau, tau_v = brute.exact_counts(e, 40)
+    g, l = oracle.mascot(e, 40, 1, 3, 9)
+    assert tau > 0 and g.tolist() == [tau] * 3
+    for i in range(3):
+        assert np.array_equal(l[i], tau_v)
+
+
+@pytest.mark.parametrize("m,c,seed", [(2, 3, 1), (3, 5, 2), (4, 2, 3)])
+def test_mascot_counts_semi_triangles_of_independent_samples(m, c, seed):
+    """Processor i counts exactly the triangles whose first two edges it sampled (h_i = 0),
+    found by enumerating the graph's triangles and testing the hash (a different route from
+    the stream replay); its locals add the triangle to its three nodes."""
+    e = synth.er(40, 260, 60 + seed, 61 + seed)
+    g, l = oracle.mascot(e, 40, m, c, seed)
+    sl = oracle.slots(e, m, c, seed)  # group i's hash = processor i's coin
+    want_g = np.zeros(c, np.int64)
+    want_l = np.zeros((c, 40), np.int64)
+    for tri, ts in brute.triangles(e, 40):
+        t1, t2 = sorted(ts)[:2]
+        for i in range(c):
+            if sl[i, t1] == 0 and sl[i, t2] == 0:
+                want_g[i] += 1
+                for x in tri:
+                    want_l[i, x] += 1
+    assert np.array_equal(g, want_g) and np.array_equal(l, want_l) and want_g.sum() > 0
+    # processors are independent samplers: processor 0 equals REPT with one processor
+    g1, l1 = oracle.rept(e, 40, m, 1, seed)
+    assert g[0] == g1[0] and np.array_equal(l[0], l1[0])
+
+
+def test_mascot_estimator_unbiased_with_paper_variance():
+    """Section III-C: the mean of c independent MASCOT estimates is unbiased with variance
+    (tau (m^2 - 1) + 2 eta (m - 1)) / c, checked over hash seeds; on this graph it is several
+    times REPT's tau (m - 1) / c1 at c = m (the comparison the paper draws)."""
+    n = 30
+    e = synth.shuffled(synth.er(n, 160, 41, 42), 43)
+    tau, _ = brute.exact_counts(e, n)
+    eta = brute.eta(e, n)
+    m, c, R = 3, 3, 1500
+    var = (tau * (m * m - 1) + 2 * eta * (m - 1)) / c
+    seeds = synth.u64(8, 31, R)
+    est = np.empty(R)
+    for r in range(R):
+        g, _ = oracle.mascot(e, n, m, c, int(seeds[r]))
+        est[r] = oracle.estimate_mascot(n, m, c, g)[0]
+    assert abs(est.mean() - tau) < 4.0 * math.sqrt(var / R)
+    ratio = est.var(ddof=1) / var
+    assert 0.8 < ratio < 1.25, (ratio, tau, eta)
+    assert var > 2 * tau * (m - 1)
+
+
+def test_mascot_estimator_values():
+    """(S m^2) / c with one rounding each: hand values, exact cases, and ERANGE."""
+    th, tv = oracle.estimate_mascot(2, 3, 4, [1, 2, 3, 4], [[1, 0], [0, 0], [2, 0], [0, 1]])
+    assert th == 22.5 and tv.tolist() == [6.75, 2.25]
+    th, _ = oracle.estimate_mascot(1, 10, 7, [3] * 7)
+    assert th == (21.0 * 100.0) / 7.0
+    with pytest.raises(oracle.OracleError):
+        oracle.estimate_mascot(1, 2, 2, [2**52, 2**52])
+    with pytest.raises(oracle.OracleError):
+        oracle.estimate_mascot(1, 2, 1, [1], [[-1]])
