@@ -58,13 +58,20 @@ typedef enum rept_status {
 
 /* rept_params.flags */
 #define REPT_LOCAL_PER_PROC 1u /* local counters per processor [c][n] instead of per group [G][n] */
+/* Parallel MASCOT (Section III-C): each of the c processors keeps every edge independently with
+ * probability 1/m (processor i keeps e iff h_i(e) = 0, h_i the hash of group i), so the samples
+ * overlap instead of partitioning the stream; the counting step is Algorithm 1's.  Processors
+ * are their own groups (c <= 8 per call; independent seeds give further processors), the local
+ * output has c rows, and the estimator is the mean of the processors' m^2 tau^(i), that is
+ * (m^2 / c) sum_i tau^(i) for any c.  Not with rept_count_eta / rept_estimate_combined. */
+#define REPT_MASCOT 2u
 
 /* REPT sampling parameters (Table I: p = 1/m, c processors; plus the hash seed). */
 typedef struct rept_params {
     uint32_t m;     /* 1/p, 1 <= m <= 65536 (m = 1 counts every triangle once per group) */
-    uint32_t c;     /* processors, 1 <= c <= 8*m (at most 8 hash groups) */
+    uint32_t c;     /* processors, 1 <= c <= 8*m (at most 8 hash groups); c <= 8 with REPT_MASCOT */
     uint64_t seed;  /* seed of the hash parameters */
-    uint32_t flags; /* REPT_LOCAL_PER_PROC or 0 */
+    uint32_t flags; /* REPT_LOCAL_PER_PROC, REPT_MASCOT, both, or 0 */
     uint32_t reserved; /* must be 0 */
 } rept_params;
 
@@ -83,7 +90,8 @@ typedef struct rept_graph_info {
     uint64_t num_reverse;   /* pairs in the reverse lists (counted from the longer list's side) */
 } rept_graph_info;
 
-/* Number of local-counter rows for `params`: G = ceil(c/m), or c with REPT_LOCAL_PER_PROC.
+/* Number of local-counter rows for `params`: G = ceil(c/m), or c with REPT_LOCAL_PER_PROC or
+ * REPT_MASCOT.
  * The local output of every count call is int64[rows][n], row-major.  Returns 0 on bad
  * params. */
 uint32_t rept_local_rows(const rept_params* params);
@@ -177,7 +185,9 @@ rept_status rept_count_range(const rept_graph* graph, const rept_params* params,
  *     tau_v_hat = ((double)S_v * (double)(m*m)) / (double)c,   S_v = sum of the local rows at v
  * with the sums exact in int64 and one rounding each for the product and the quotient.
  *   global: host int64[c]; local: host int64[rows][n] or NULL; tau_v_hat: host double[n] or NULL.
- * Errors: EINVAL; ENOTSUP for c > m with c % m != 0 (rept_estimate_combined covers it);
+ * With REPT_MASCOT the same expressions hold for every c (the mean of the processors' MASCOT
+ * estimates m^2 tau^(i), Section III-C).
+ * Errors: EINVAL; ENOTSUP for REPT with c > m and c % m != 0 (rept_estimate_combined covers it);
  *         ERANGE if a sum is negative or >= 2^53.
  */
 rept_status rept_estimate(uint32_t n, const rept_params* params, const int64_t* global,

@@ -44,11 +44,14 @@ void group_params(uint64_t seed, uint32_t G, uint64_t* hp) {
 
 bool params_ok(const rept_params* p) {
     if (!p || p->m == 0 || p->c == 0 || p->reserved != 0) return false;
-    if (p->flags & ~REPT_LOCAL_PER_PROC) return false;
+    if (p->flags & ~(REPT_LOCAL_PER_PROC | REPT_MASCOT)) return false;
     return true;
 }
 
-uint32_t groups_of(const rept_params* p) { return (p->c + p->m - 1) / p->m; }
+bool is_mascot(const rept_params* p) { return (p->flags & REPT_MASCOT) != 0; }
+
+// hash groups: ceil(c/m) for REPT; one per processor for parallel MASCOT
+uint32_t groups_of(const rept_params* p) { return is_mascot(p) ? p->c : (p->c + p->m - 1) / p->m; }
 
 // bytes of the slot table of a graph's stored edges for G groups
 size_t table_bytes(const rept_graph* g, uint32_t G) {
@@ -155,6 +158,15 @@ rept_status make_job(const rept_job& jb, JobDev* d, uint64_t* zero_words) {
     d->m = jb.params.m;
     d->c = jb.params.c;
     d->G = G;
+    // processor of slot j of group k: k * pstride + j for the slots j < ck (last group: last_ck)
+    if (is_mascot(&jb.params)) {
+        d->ck = d->last_ck = 1;  // processor k keeps the edges with h_k(e) = 0
+        d->pstride = 1;
+    } else {
+        d->ck = jb.params.m;
+        d->last_ck = jb.params.c - (G - 1) * jb.params.m;
+        d->pstride = jb.params.m;
+    }
     d->per_proc = (jb.params.flags & REPT_LOCAL_PER_PROC) ? 1u : 0u;
     d->rows = d->per_proc ? jb.params.c : G;
     d->accumulate = (jb.flags & REPT_JOB_ACCUMULATE) ? 1u : 0u;
@@ -225,7 +237,7 @@ extern "C" {
 
 uint32_t rept_local_rows(const rept_params* p) {
     if (!params_ok(p)) return 0;
-    return (p->flags & REPT_LOCAL_PER_PROC) ? p->c : groups_of(p);
+    return ((p->flags & REPT_LOCAL_PER_PROC) || is_mascot(p)) ? p->c : groups_of(p);
 }
 
 rept_status rept_query_sizes(uint32_t n, uint64_t num_edges, size_t* persistent_bytes, size_t* scratch_bytes) {
@@ -371,7 +383,7 @@ rept_status estimate_core(uint32_t n, const rept_params* params, const int64_t* 
                           uint32_t rows, double* tau_hat, double* tau_v_hat) {
     if (!params_ok(params) || n == 0 || !global || !tau_hat) return REPT_EINVAL;
     const uint32_t m = params->m, c = params->c;
-    if (c > m && c % m != 0) return REPT_ENOTSUP;
+    if (c > m && c % m != 0 && !is_mascot(params)) return REPT_ENOTSUP;
     const int64_t limit = (int64_t)1 << 53;
     const double num = (double)((uint64_t)m * (uint64_t)m);
     const double den = (double)c;
@@ -458,6 +470,7 @@ rept_status rept_count_eta(const rept_graph* graph, const rept_params* params, i
                            const rept_tuning* tuning, void* stream) {
     if (!valid_graph(graph) || !params_ok(params) || !global || !local || !eta) return REPT_EINVAL;
     if (((uintptr_t)eta | (uintptr_t)eta_v) & 7u) return REPT_EINVAL;
+    if (is_mascot(params)) return REPT_ENOTSUP;
     const uint32_t G = groups_of(params);
     if (G > REPT_GMAX || params->m > 65536) return REPT_ENOTSUP;
     size_t need = 0;
@@ -516,7 +529,7 @@ double combine(int64_t S1, int64_t S2, int64_t eta, uint32_t m, uint32_t c) {
 rept_status rept_estimate_combined(uint32_t n, const rept_params* params, const int64_t* global,
                                    const int64_t* local, int64_t eta, const int64_t* eta_v, double* tau_hat,
                                    double* tau_v_hat) {
-    if (!params_ok(params) || n == 0 || !global || !tau_hat) return REPT_EINVAL;
+    if (!params_ok(params) || n == 0 || !global || !tau_hat || is_mascot(params)) return REPT_EINVAL;
     const uint32_t m = params->m, c = params->c;
     if (c <= m || c % m == 0) return REPT_EINVAL;  // rept_estimate covers these
     const int64_t lim = (int64_t)1 << 53;

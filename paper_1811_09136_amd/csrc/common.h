@@ -76,6 +76,8 @@ struct JobDev {
     uint32_t fill;               // 1: the launch (re)writes the slot table first
     uint32_t es;                 // stored edges (rows of the pair counters)
     uint32_t* pairs;             // Algorithm 2 pair counters [G][es][2] (s, L), or null
+    uint32_t ck, last_ck;        // active slots of a full group and of the last group
+    uint32_t pstride;            // processor of slot j of group k: k * pstride + j
 };
 
 // Work queues of the counting kernel: each phase's tiles are split over kQueues interleaved

@@ -209,7 +209,7 @@ struct JobRegs {
     int64_t* local;
     const uint16_t* tab;  // slot table of the stored edges, gs slots per edge
     uint32_t* pairs;      // Algorithm 2 pair counters [G][es][2], or null
-    uint32_t n, m, c, G, gs, per_proc, t0, t1, last_ck, use_hist, es;
+    uint32_t n, m, c, G, gs, per_proc, t0, t1, ck, last_ck, pstride, use_hist, es;
 };
 
 __device__ inline void load_job(const JobDev* __restrict__ j, uint32_t HC, JobRegs& r) {
@@ -233,7 +233,9 @@ __device__ inline void load_job(const JobDev* __restrict__ j, uint32_t HC, JobRe
     r.per_proc = j->per_proc;
     r.t0 = j->t0;
     r.t1 = j->t1;
-    r.last_ck = j->c - (j->G - 1) * j->m;
+    r.ck = j->ck;
+    r.last_ck = j->last_ck;
+    r.pstride = j->pstride;
     r.use_hist = (HC != 0 && j->c <= HC) ? 1u : 0u;
 }
 
@@ -481,9 +483,9 @@ __device__ void drain_hits_t(const JobRegs& J, const TeamView& T, const WaveView
                         s1 = (uint32_t)(xhi >> (bit - 15)) & 0xffffu;
                         mhi &= mhi - 1;
                     }
-                    const uint32_t ck = (g + 1 < J.G) ? J.m : J.last_ck;
+                    const uint32_t ck = (g + 1 < J.G) ? J.ck : J.last_ck;
                     if (s1 < ck) {
-                        const uint32_t proc = g * J.m + s1;
+                        const uint32_t proc = g * J.pstride + s1;
                         if (J.use_hist) atomicAdd(&V.hist[proc], 1u);
                         else add64(J.global + proc, 1);
                         if (J.per_proc) {

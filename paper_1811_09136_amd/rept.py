@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "librept.so")
 REPT_OK, REPT_EINVAL, REPT_ERANGE, REPT_ESELFLOOP, REPT_EDUP, REPT_ENOMEM, REPT_EDEVICE, REPT_ENOTSUP = \
     0, -1, -2, -3, -4, -5, -6, -7
 REPT_LOCAL_PER_PROC = 1
+REPT_MASCOT = 2
 REPT_JOB_ACCUMULATE = 1
 REPT_JOB_TABLE_READY = 2
 UINT64_MAX = 2**64 - 1
@@ -128,17 +129,19 @@ class Params:
     c: int
     seed: int
     per_proc: bool = False
+    mascot: bool = False  # parallel MASCOT: independent Bernoulli(1/m) samples (Section III-C)
 
     def c_struct(self) -> rept_params:
-        return rept_params(self.m, self.c, self.seed & UINT64_MAX, REPT_LOCAL_PER_PROC if self.per_proc else 0, 0)
+        flags = (REPT_LOCAL_PER_PROC if self.per_proc else 0) | (REPT_MASCOT if self.mascot else 0)
+        return rept_params(self.m, self.c, self.seed & UINT64_MAX, flags, 0)
 
     @property
     def groups(self) -> int:
-        return -(-self.c // self.m)
+        return self.c if self.mascot else -(-self.c // self.m)
 
     @property
     def rows(self) -> int:
-        return self.c if self.per_proc else self.groups
+        return self.c if (self.per_proc or self.mascot) else self.groups
 
 
 # ------------------------------------------------------------------ same-name wrappers -----

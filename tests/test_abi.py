@@ -200,3 +200,27 @@ def test_estimate_combined_zero_ulp_against_oracle(m, c, per_proc):
         with pytest.raises(rept.ReptError) as ei:
             rept.rept_estimate_combined(n, rept.Params(mm, cc, 0), np.zeros(cc, np.int64), None, 0, None)
         assert ei.value.code == rept.REPT_EINVAL
+
+
+def test_mascot_params_and_estimator():
+    """Parallel MASCOT: one hash group and one local row per processor, at most 8 per call;
+    its estimator is (m^2 / c) S for every c, 0 ulp against the oracle's."""
+    from paper_1811_09136_amd import rept
+    P = rept.Params(10, 7, 0, mascot=True)
+    assert rept.rept_local_rows(P) == 7 and P.rows == 7 and P.groups == 7
+    rng = np.random.default_rng(17)
+    for m, c in [(10, 7), (2, 5), (3, 3), (100, 8), (1, 1)]:
+        n = 5003
+        glob = rng.integers(0, 2**40, size=c)
+        loc = rng.integers(0, 2**40, size=(c, n))
+        th, tv = rept.rept_estimate(n, rept.Params(m, c, 0, mascot=True), glob, loc)
+        oth, otv = oracle.estimate_mascot(n, m, c, glob, loc)
+        assert th == oth and np.array_equal(tv.view(np.uint64), otv.view(np.uint64))
+        th2, tv2 = rept.rept_estimate_sums(n, rept.Params(m, c, 0, mascot=True), glob, loc.sum(axis=0))
+        assert th2 == oth and np.array_equal(tv2.view(np.uint64), otv.view(np.uint64))
+    with pytest.raises(rept.ReptError) as ei:
+        rept.rept_estimate_combined(3, rept.Params(2, 5, 0, mascot=True), np.zeros(5, np.int64), None, 0, None)
+    assert ei.value.code == rept.REPT_EINVAL
+    lib = rept.lib()
+    bad = rept.rept_params(2, 3, 0, 4, 0)  # an unknown flag
+    assert lib.rept_local_rows(ctypes.byref(bad)) == 0

@@ -1,0 +1,128 @@
+"""Parallel MASCOT (Section III-C) on the counting kernels against the CPU oracle: every
+processor's counters bit for bit, the estimators at 0 ulp, and MASCOT jobs batched with REPT
+jobs.
+
+Inputs are seeded synthetic streams (module ``synth``).  Each case prints its name and shape
+before touching the GPU so that a failing run names its case.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _count(cuda, edges, n, params, tune=None):
+    import torch
+    from paper_1811_09136_amd import rept
+    g = rept.Graph(rept.to_device_edges(edges, cuda), n)
+    if tune is None:
+        glob, loc = g.count(params)
+    else:
+        out = g.outputs(params)
+        job = rept.make_job(g, params, out, g.new_workspace(params))
+        ws = torch.empty(rept.rept_batch_workspace_size(1), dtype=torch.uint8, device=cuda)
+        rept.rept_batch_count([job], tune, ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
+        glob, loc = out
+    torch.cuda.synchronize()
+    res = glob.cpu().numpy(), loc.cpu().numpy(), g.info
+    g.close()
+    return res
+
+
+@pytest.mark.parametrize("m,c,per_proc", [(2, 3, False), (3, 5, True), (10, 8, False), (1, 2, False),
+                                          (5, 1, False), (4, 7, True)])
+def test_mascot_random_graphs(cuda, m, c, per_proc):
+    from paper_1811_09136_amd import rept
+    e = synth.er(300, 3000, 31 + m, 32 + c)
+    _say(f"mascot ER n=300 E=3000 m={m} c={c} per_proc={per_proc}")
+    got = _count(cuda, e, 300, rept.Params(m, c, 55 + m * c, per_proc, mascot=True))
+    og, ol = oracle.mascot(e, 300, m, c, 55 + m * c)
+    assert np.array_equal(got[0], og), (got[0], og)
+    assert np.array_equal(got[1], ol)
+    assert ol.sum() == 3 * og.sum()
+
+
+def test_mascot_degenerate(cuda):
+    from paper_1811_09136_amd import rept
+    cases = [(np.zeros((0, 2), np.uint32), 4), (np.array([[0, 1], [1, 2], [0, 2]], np.uint32), 3),
+             (synth.shuffled(synth.complete(16), 9, 10), 16)]
+    for e, n in cases:
+        for m, c in [(1, 3), (2, 8)]:
+            _say(f"mascot degenerate E={len(e)} n={n} m={m} c={c}")
+            got = _count(cuda, e, n, rept.Params(m, c, 6, mascot=True))
+            og, ol = oracle.mascot(e, n, m, c, 6)
+            assert np.array_equal(got[0], og) and np.array_equal(got[1], ol)
+
+
+@pytest.mark.parametrize("tune", [None, dict(wave_cap=16, block_cap=64, b_chunk=16, threads=256),
+                                  dict(wave_cap=8, block_cap=64, b_chunk=1024, threads=64, blocks=3)])
+def test_mascot_launch_shapes(cuda, tune):
+    from paper_1811_09136_amd import rept
+    e, n = synth.scaled_chung_lu(120_000, 33)
+    _say(f"mascot Chung-Lu n={n} E={len(e)} m=3 c=6 tune={tune}")
+    got = _count(cuda, e, n, rept.Params(3, 6, 21, mascot=True), None if tune is None else rept.tuning(**tune))
+    assert got[2].max_out_degree > 64
+    og, ol = oracle.mascot(e, n, 3, 6, 21)
+    assert np.array_equal(got[0], og) and np.array_equal(got[1], ol)
+
+
+def test_mascot_million_edges_and_estimate(cuda):
+    """A 1M-edge power-law stream, m = 10, eight processors: counters exact, estimators 0 ulp."""
+    from paper_1811_09136_amd import rept
+    e, n = synth.scaled_chung_lu(1_000_000, 43)
+    _say(f"mascot Chung-Lu n={n} E={len(e)} m=10 c=8")
+    P = rept.Params(10, 8, 77, mascot=True)
+    glob, loc, _ = _count(cuda, e, n, P)
+    og, ol = oracle.mascot(e, n, 10, 8, 77)
+    assert np.array_equal(glob, og) and np.array_equal(loc, ol)
+    th, tv = rept.rept_estimate(n, P, glob, loc)
+    oth, otv = oracle.estimate_mascot(n, 10, 8, og, ol)
+    assert th == oth and np.array_equal(tv.view(np.uint64), otv.view(np.uint64))
+
+
+def test_mascot_and_rept_jobs_in_one_batch(cuda):
+    """MASCOT and REPT jobs (different group counts and processor maps) in one persistent
+    launch: each job's outputs equal its oracle's."""
+    import torch
+    from paper_1811_09136_amd import rept
+    from paper_1811_09136_amd.batch import Batch, Job
+    e1 = synth.er(400, 4000, 5, 6)
+    e2, n2 = synth.scaled_chung_lu(60_000, 7)
+    g1 = rept.Graph(rept.to_device_edges(e1, cuda), 400)
+    g2 = rept.Graph(rept.to_device_edges(e2, cuda), n2)
+    specs = [(g1, e1, 400, rept.Params(3, 5, 1, mascot=True)), (g1, e1, 400, rept.Params(3, 5, 1)),
+             (g2, e2, n2, rept.Params(10, 8, 2, mascot=True)), (g2, e2, n2, rept.Params(10, 40, 2)),
+             (g2, e2, n2, rept.Params(2, 3, 3, per_proc=True, mascot=True))]
+    _say(f"mascot + rept batch of {len(specs)} jobs")
+    jobs = [Job(g, p) for g, _, _, p in specs]
+    Batch(jobs).launch()
+    torch.cuda.synchronize()
+    for j, (_, e, n, p) in zip(jobs, specs):
+        got_g, got_l = j.out[0].cpu().numpy(), j.out[1].cpu().numpy()
+        if p.mascot:
+            og, ol = oracle.mascot(e, n, p.m, p.c, p.seed)
+        else:
+            og, ol = oracle.rept(e, n, p.m, p.c, p.seed, per_proc=p.per_proc)
+        assert np.array_equal(got_g, og) and np.array_equal(got_l, ol), p
+    g1.close()
+    g2.close()
+
+
+def test_mascot_limits(cuda):
+    from paper_1811_09136_amd import rept
+    e = synth.er(50, 200, 1, 2)
+    g = rept.Graph(rept.to_device_edges(e, cuda), 50)
+    with pytest.raises(rept.ReptError) as ei:
+        g.count(rept.Params(10, 9, 1, mascot=True))  # nine independent hashes in one call
+    assert ei.value.code == rept.REPT_ENOTSUP
+    with pytest.raises(rept.ReptError) as ei:
+        g.count_eta(rept.Params(2, 3, 1, mascot=True))
+    assert ei.value.code == rept.REPT_ENOTSUP
+    g.close()
