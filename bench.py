@@ -10,10 +10,12 @@ Default workload: Chung-Lu power-law stream, 1,000,000 nodes, 20,000,000 edges, 
 random order, m = 10 (p = 0.1), c = 40 (four hash groups).  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-batched] [--no-served]
-                  [--workload NAME]
+                  [--no-alg2] [--no-mascot] [--workload NAME]
 
 The line also carries "batched" (512 jobs: plain one-by-one vs one graph-captured batched launch)
-and "served" (Poisson requests: continuous batching vs a FIFO plain loop) comparisons.
+and "served" (Poisson requests: continuous batching vs a FIFO plain loop) comparisons, "alg2"
+(Algorithm 2's pass, c mod m != 0, against the plain count) and "mascot" (parallel MASCOT
+against REPT with the same m and c).
 """
 from __future__ import annotations
 
@@ -54,6 +56,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--no-served", action="store_true", help="skip the served-vs-plain comparison")
+    ap.add_argument("--no-alg2", action="store_true", help="skip the Algorithm 2 (c mod m != 0) pass")
+    ap.add_argument("--no-mascot", action="store_true", help="skip the parallel MASCOT pass")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 1 GiB (reference for FETCH_SIZE/WRITE_SIZE scaling)")
     return ap.parse_args()
@@ -142,6 +146,83 @@ def cpu_single_core(edges, n, m, c):
     return {"value": len(edges) / (dt * c), "unit": "stream edges/s", "cores": 1, "kind": "oracle",
             "sample": f"Algorithm 1 replay of processor 0 of {c} over all {len(edges)} stream edges on core {core} "
                       f"(pinned) took {dt:.2f} s; whole job = {c} x that"}
+
+
+def bench_alg2(dev, edges, n: int, m: int, c: int, reps: int = 3):
+    """Algorithm 2 on the same stream (c > m, c mod m != 0): rept_count_eta (slot table, counts
+    with the per-edge pair counters, k_eta) against rept_count under the same parameters, then the
+    combined estimators on the host.  The counts of both calls must agree."""
+    import numpy as np
+    import torch
+    from paper_1811_09136_amd import rept
+    params = rept.Params(m, c, HASH_SEED)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    g = rept.Graph(rept.to_device_edges(edges, dev), n)
+    glob, loc = g.outputs(params)
+    eta = torch.empty((2, c), dtype=torch.int64, device=dev)
+    eta_v = torch.empty((2, n), dtype=torch.int64, device=dev)
+    wsb = rept.rept_count_eta_workspace_size(g.handle, params)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    plain_ms, eta_ms = [], []
+    for r in range(reps + 1):
+        for kind in ("plain", "eta"):
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            if kind == "plain":
+                rept.rept_count(g.handle, params, glob.data_ptr(), loc.data_ptr(), ws.data_ptr(), wsb, sp)
+            else:
+                rept.rept_count_eta(g.handle, params, glob.data_ptr(), loc.data_ptr(), eta.data_ptr(),
+                                    eta_v.data_ptr(), ws.data_ptr(), wsb, None, sp)
+            ev1.record(stream)
+            stream.synchronize()
+            if kind == "plain":
+                ref = glob.cpu().numpy()
+            elif not np.array_equal(glob.cpu().numpy(), ref):
+                raise RuntimeError("rept_count_eta and rept_count disagree")
+            if r:
+                (plain_ms if kind == "plain" else eta_ms).append(ev0.elapsed_time(ev1))
+    h_glob, h_loc = glob.cpu().numpy(), loc.cpu().numpy()
+    h_eta, h_eta_v = eta.cpu().numpy(), eta_v.cpu().numpy()
+    t0 = time.perf_counter()
+    tau_hat, _ = rept.rept_estimate_combined(n, params, h_glob, h_loc, int(h_eta[0].sum()), h_eta_v[0])
+    est_ms = 1e3 * (time.perf_counter() - t0)
+    g.close()
+    cm, em = float(np.median(plain_ms)), float(np.median(eta_ms))
+    return {"m": m, "c": c, "count_ms": cm, "count_eta_ms": em, "eta_overhead": em / cm,
+            "count_eta_edges_per_s": len(edges) / (em * 1e-3), "combined_estimate_ms": est_ms,
+            "tau_hat": tau_hat, "eta_def_sum": int(h_eta[0].sum()), "eta_printed_sum": int(h_eta[1].sum()),
+            "semi_triangles": int(h_glob.sum())}
+
+
+def bench_mascot(dev, edges, n: int, m: int, c: int = 8, reps: int = 3):
+    """Parallel MASCOT (Section III-C) on the same stream with c independent samplers, against
+    REPT with the same m and c (the paper expects the same computational cost)."""
+    import numpy as np
+    import torch
+    from paper_1811_09136_amd import rept
+    stream = torch.cuda.current_stream()
+    g = rept.Graph(rept.to_device_edges(edges, dev), n)
+    res = {"m": m, "c": c}
+    for name, p in (("rept", rept.Params(m, c, HASH_SEED)), ("mascot", rept.Params(m, c, HASH_SEED, mascot=True))):
+        out = g.outputs(p)
+        ws = g.new_workspace(p)
+        ms = []
+        for r in range(reps + 1):
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            g.count(p, out=out, workspace=ws)
+            ev1.record(stream)
+            stream.synchronize()
+            if r:
+                ms.append(ev0.elapsed_time(ev1))
+        glob, loc = out[0].cpu().numpy(), out[1].cpu().numpy()
+        tau_hat, _ = rept.rept_estimate(n, p, glob, None)
+        res[name] = {"count_ms": float(np.median(ms)), "edges_per_s": len(edges) / (float(np.median(ms)) * 1e-3),
+                     "semi_triangles": int(glob.sum()), "tau_hat": tau_hat}
+    g.close()
+    res["mascot_over_rept_time"] = res["mascot"]["count_ms"] / res["rept"]["count_ms"]
+    return res
 
 
 def bench_batched(dev, reps: int = 3):
@@ -417,6 +498,12 @@ def main():
                    "source_digest": count_kernel_source_digest()},
         "tau_hat": tau_hat,
     }
+    if not args.no_alg2 and c > m:
+        say("algorithm 2 pass")
+        out["alg2"] = bench_alg2(dev, edges, n, m, c - m // 2)
+    if not args.no_mascot and m > 1:
+        say("parallel MASCOT pass")
+        out["mascot"] = bench_mascot(dev, edges, n, m, min(c, 8))
     if not args.no_batched:
         say("batched workload")
         out["batched"] = bench_batched(dev)
