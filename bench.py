@@ -10,12 +10,12 @@ Default workload: Chung-Lu power-law stream, 1,000,000 nodes, 20,000,000 edges, 
 random order, m = 10 (p = 0.1), c = 40 (four hash groups).  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-batched] [--no-served]
-                  [--no-alg2] [--no-mascot] [--workload NAME]
+                  [--no-alg2] [--no-mascot] [--no-incremental] [--workload NAME]
 
 The line also carries "batched" (512 jobs: plain one-by-one vs one graph-captured batched launch)
 and "served" (Poisson requests: continuous batching vs a FIFO plain loop) comparisons, "alg2"
-(Algorithm 2's pass, c mod m != 0, against the plain count) and "mascot" (parallel MASCOT
-against REPT with the same m and c).
+(Algorithm 2's pass, c mod m != 0, against the plain count), "mascot" (parallel MASCOT
+against REPT with the same m and c) and "incremental" (the stream appended in ten chunks).
 """
 from __future__ import annotations
 
@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--no-served", action="store_true", help="skip the served-vs-plain comparison")
     ap.add_argument("--no-alg2", action="store_true", help="skip the Algorithm 2 (c mod m != 0) pass")
     ap.add_argument("--no-mascot", action="store_true", help="skip the parallel MASCOT pass")
+    ap.add_argument("--no-incremental", action="store_true", help="skip the incremental-stream pass")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 1 GiB (reference for FETCH_SIZE/WRITE_SIZE scaling)")
     return ap.parse_args()
@@ -222,6 +223,39 @@ def bench_mascot(dev, edges, n: int, m: int, c: int = 8, reps: int = 3):
                      "semi_triangles": int(glob.sum()), "tau_hat": tau_hat}
     g.close()
     res["mascot_over_rept_time"] = res["mascot"]["count_ms"] / res["rept"]["count_ms"]
+    return res
+
+
+def bench_incremental(dev, edges, n: int, m: int, c: int, ref_glob, chunks: int = 10):
+    """The same stream appended in `chunks` equal chunks (rept_stream_append: validate, merge,
+    count each chunk's edges against the earlier ones); per-append latency and whole-stream
+    throughput, and the final counters must equal the one-shot count's."""
+    import numpy as np
+    import torch
+    from paper_1811_09136_amd import rept
+    E = len(edges)
+    step = -(-E // chunks)
+    d_edges = rept.to_device_edges(edges, dev)
+    params = rept.Params(m, c, HASH_SEED)
+    res = {"chunks": chunks, "chunk_edges": step}
+    for rep in range(2):  # the first pass warms the code objects
+        inc = rept.IncrementalStream(n, E, step, params, dev)
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for a in range(0, E, step):
+            ta = time.perf_counter()
+            inc.append(d_edges[a:a + step])
+            torch.cuda.synchronize()
+            lat.append(1e3 * (time.perf_counter() - ta))
+        total = time.perf_counter() - t0
+        same = bool(np.array_equal(inc.counts[0].cpu().numpy(), ref_glob))
+        inc.close()
+        del inc
+    if not same:
+        raise RuntimeError("incremental counters disagree with the one-shot count")
+    res.update({"total_ms": 1e3 * total, "edges_per_s": E / total, "append_ms_first": lat[0],
+                "append_ms_last": lat[-1], "append_ms_median": float(np.median(lat)), "equal_to_one_shot": same})
     return res
 
 
@@ -504,6 +538,9 @@ def main():
     if not args.no_mascot and m > 1:
         say("parallel MASCOT pass")
         out["mascot"] = bench_mascot(dev, edges, n, m, min(c, 8))
+    if not args.no_incremental:
+        say("incremental stream")
+        out["incremental"] = bench_incremental(dev, edges, n, m, c, h_glob.numpy())
     if not args.no_batched:
         say("batched workload")
         out["batched"] = bench_batched(dev)

@@ -275,6 +275,61 @@ rept_status rept_reduce_local(const int64_t* local, uint32_t rows, uint32_t n, i
 rept_status rept_hash_slots(const rept_params* params, const uint32_t* edges, uint64_t num_edges,
                             uint32_t* slots, void* stream);
 
+/*
+ * Incremental streams (Section II: the stream is processed as it arrives; Section III-A builds
+ * the processors' edge sets on the fly).  The stream is appended in chunks; after each append
+ * the caller's counters hold every per-edge update of Algorithm 1 (for all c processors, REPT
+ * or parallel MASCOT) of all edges appended so far, so estimates can be formed after every
+ * chunk (the per-interval use the paper names).  The counters are exactly those of rept_count
+ * on the stream appended so far.
+ *
+ * The device keeps the whole adjacency of the edges seen so far (both directions, sorted by
+ * neighbour, arrival time beside each entry).  An append sorts and validates the chunk, merges
+ * it into the adjacency in one pass, and counts each chunk edge against the edges that arrived
+ * before it (one work item per entry of its endpoints' shorter list).  The cost of an append is
+ * linear in the edges so far plus the chunk's intersection work.
+ */
+typedef struct rept_stream rept_stream; /* opaque host-side handle */
+
+/* Device bytes for a stream of up to `capacity` edges over n nodes, appended in chunks of at
+ * most `max_chunk` edges: 48 bytes per edge of capacity, 64 per edge of chunk, 8 per node, and
+ * the sort's temporary storage, whose size depends on the device (queried from the current
+ * device; no device work).  EINVAL if n == 0, n > 2^29, capacity == 0, capacity >= 2^31,
+ * max_chunk == 0 or max_chunk > capacity; EDEVICE if the device cannot be queried. */
+rept_status rept_stream_query_sizes(uint32_t n, uint64_t capacity, uint64_t max_chunk, size_t* bytes);
+
+/*
+ * Create an empty stream.
+ *   params:  as for rept_count (REPT or REPT_MASCOT; at most 8 hash groups).
+ *   buffer:  device, >= rept_stream_query_sizes bytes, 256-byte aligned; owned by the caller,
+ *            must stay allocated while the handle is used.
+ *   global:  device int64[c]; local: device int64[rows][n] (rows = rept_local_rows(params)),
+ *            8-byte aligned: zeroed here (on `stream`), then accumulated by every append.
+ * Errors: EINVAL, ENOTSUP (more than 8 groups, m > 65536), ENOMEM (buffer too small), EDEVICE.
+ */
+rept_status rept_stream_create(uint32_t n, uint64_t capacity, uint64_t max_chunk, const rept_params* params,
+                               void* buffer, size_t bytes, int64_t* global, int64_t* local, void* stream,
+                               rept_stream** out);
+
+/*
+ * Append the next num_edges stream edges (device uint32[num_edges][2], 8-byte aligned; the edge
+ * in row i arrives at time T + i, T = edges appended before).  The chunk is validated against
+ * itself and everything appended before (ids < n, no self-loop, no unordered pair twice); the
+ * call synchronises `stream` once to read that result.  On an error nothing changes: the
+ * adjacency, the counters and T are as before, and later appends continue from there.  On
+ * success the merge and the count are enqueued on `stream` (asynchronous); the chunk's memory
+ * may be reused once that work has completed.
+ * Errors: EINVAL (bad handle or pointer), ENOMEM (num_edges > max_chunk, or the capacity would
+ * be exceeded), ERANGE, ESELFLOOP, EDUP (in that order of precedence), EDEVICE.
+ */
+rept_status rept_stream_append(rept_stream* s, const uint32_t* edges, uint64_t num_edges, void* stream);
+
+/* Edges appended so far (host only). */
+rept_status rept_stream_num_edges(const rept_stream* s, uint64_t* num_edges);
+
+/* Release the handle (not the caller's buffers). */
+void rept_stream_destroy(rept_stream* s);
+
 /* ------------------------------------------------------------------ batched counting ------ */
 
 /* rept_job.flags */

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librept.so")
-SOURCES = ["api.hip", "build.hip", "count.hip"]
+SOURCES = ["api.hip", "build.hip", "count.hip", "stream.hip"]
 ARCH = os.environ.get("REPT_OFFLOAD_ARCH", "gfx950")
 
 

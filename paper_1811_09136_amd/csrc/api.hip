@@ -67,6 +67,46 @@ std::unordered_map<void*, Shape> g_shapes;  // prepared batch workspaces -> laun
 
 bool valid_graph(const rept_graph* g) { return g && g->magic == REPT_MAGIC; }
 
+// ---- incremental streams: host handle and the layout of the caller's buffer ---------------
+constexpr uint32_t REPT_STREAM_MAGIC = 0x52535452u;
+}  // namespace
+struct rept_stream {
+    uint32_t magic;
+    rept_params params;
+    uint64_t capacity, max_chunk;
+    IncState st;
+    IncCount base;  // parameters of the per-edge count (pointers filled per append)
+};
+namespace {
+bool valid_stream(const rept_stream* s) { return s && s->magic == REPT_STREAM_MAGIC; }
+
+struct IncLayout {
+    size_t key[2], tim[2], off, coff, ckey_a, ckey_b, ctim_a, ctim_b, end, flags, temp, total, temp_bytes;
+};
+size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+IncLayout inc_layout(uint32_t n, uint64_t cap, uint64_t maxc) {
+    IncLayout L;
+    const size_t E2 = 2 * cap, C2 = 2 * maxc;
+    size_t p = 0;
+    for (int i = 0; i < 2; ++i) {
+        L.key[i] = p; p = up256(p + 8 * E2);
+        L.tim[i] = p; p = up256(p + 4 * E2);
+    }
+    L.off = p; p = up256(p + 4 * ((size_t)n + 1));
+    L.coff = p; p = up256(p + 4 * ((size_t)n + 1));
+    L.ckey_a = p; p = up256(p + 8 * C2);
+    L.ckey_b = p; p = up256(p + 8 * C2);
+    L.ctim_a = p; p = up256(p + 4 * C2);
+    L.ctim_b = p; p = up256(p + 4 * C2);
+    L.end = p; p = up256(p + 8 * C2);
+    L.flags = p; p = up256(p + 8);
+    L.temp_bytes = rept_inc_sort_temp_bytes(C2, 64);
+    L.temp = p; p = up256(p + L.temp_bytes);
+    L.total = p;
+    return L;
+}
+uint32_t bit_length(uint32_t x) { return x ? 32u - (uint32_t)__builtin_clz(x) : 0u; }
+
 // Fill the launch shape for jobs of at most G_max groups, at most c_max processors and at most
 // max_out entries in an apex list.
 rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t max_out, uint64_t zero_words,
@@ -660,6 +700,121 @@ rept_status rept_batch_count(const rept_job* jobs, uint32_t njobs, const rept_tu
     rept_status st = rept_batch_prepare(jobs, njobs, tuning, workspace, workspace_bytes, stream);
     if (st != REPT_OK) return st;
     return rept_batch_launch(workspace, stream);
+}
+
+rept_status rept_stream_query_sizes(uint32_t n, uint64_t capacity, uint64_t max_chunk, size_t* bytes) {
+    if (n == 0 || n > (1u << 29) || capacity == 0 || capacity >= (1ull << 31) || max_chunk == 0 ||
+        max_chunk > capacity || !bytes)
+        return REPT_EINVAL;
+    const IncLayout L = inc_layout(n, capacity, max_chunk);
+    if (L.temp_bytes == 0) return REPT_EDEVICE;
+    *bytes = L.total;
+    return REPT_OK;
+}
+
+rept_status rept_stream_create(uint32_t n, uint64_t capacity, uint64_t max_chunk, const rept_params* params,
+                               void* buffer, size_t bytes, int64_t* global, int64_t* local, void* stream,
+                               rept_stream** out) {
+    if (!out || !params_ok(params) || !buffer || !global || !local) return REPT_EINVAL;
+    if (((uintptr_t)buffer & 255u) || (((uintptr_t)global | (uintptr_t)local) & 7u)) return REPT_EINVAL;
+    size_t need = 0;
+    rept_status st = rept_stream_query_sizes(n, capacity, max_chunk, &need);
+    if (st != REPT_OK) return st;
+    const uint32_t G = groups_of(params);
+    if (G > REPT_GMAX || params->m > 65536) return REPT_ENOTSUP;
+    if (bytes < need) return REPT_ENOMEM;
+    const IncLayout L = inc_layout(n, capacity, max_chunk);
+    uint8_t* B = (uint8_t*)buffer;
+    rept_stream* h = (rept_stream*)calloc(1, sizeof(rept_stream));
+    if (!h) return REPT_ENOMEM;
+    h->params = *params;
+    h->capacity = capacity;
+    h->max_chunk = max_chunk;
+    IncState& S = h->st;
+    S.n = n;
+    S.end_bit = 32 + (bit_length(n - 1) ? bit_length(n - 1) : 1);
+    S.T = 0;
+    S.cur = 0;
+    for (int i = 0; i < 2; ++i) {
+        S.key[i] = (uint64_t*)(B + L.key[i]);
+        S.tim[i] = (uint32_t*)(B + L.tim[i]);
+    }
+    S.off = (uint32_t*)(B + L.off);
+    S.coff = (uint32_t*)(B + L.coff);
+    S.ckey_a = (uint64_t*)(B + L.ckey_a);
+    S.ckey_b = (uint64_t*)(B + L.ckey_b);
+    S.ctim_a = (uint32_t*)(B + L.ctim_a);
+    S.ctim_b = (uint32_t*)(B + L.ctim_b);
+    S.end = (uint64_t*)(B + L.end);
+    S.flags = (uint32_t*)(B + L.flags);
+    S.temp = B + L.temp;
+    S.temp_bytes = L.temp_bytes;
+    const uint32_t cus = rept_num_cus() ? rept_num_cus() : 256;
+    S.count_blocks = 8 * cus;
+    IncCount& a = h->base;
+    memset(&a, 0, sizeof(a));
+    a.global = global;
+    a.local = local;
+    a.n = n;
+    a.m = params->m;
+    a.c = params->c;
+    a.G = G;
+    if (is_mascot(params)) {
+        a.ck_full = a.last_ck = 1;
+        a.pstride = 1;
+    } else {
+        a.ck_full = params->m;
+        a.last_ck = params->c - (G - 1) * params->m;
+        a.pstride = params->m;
+    }
+    a.per_proc = (params->flags & REPT_LOCAL_PER_PROC) ? 1u : 0u;
+    group_params(params->seed, G, a.hp);
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t rows = rept_local_rows(params);
+    if (rept_launch_zero(S.off, 4 * ((uint64_t)n + 1), s) != hipSuccess ||
+        rept_inc_zero64(global, params->c, s) != hipSuccess ||
+        rept_inc_zero64(local, rows * n, s) != hipSuccess) {
+        free(h);
+        return REPT_EDEVICE;
+    }
+    h->magic = REPT_STREAM_MAGIC;
+    *out = h;
+    return REPT_OK;
+}
+
+rept_status rept_stream_append(rept_stream* h, const uint32_t* edges, uint64_t num_edges, void* stream) {
+    if (!valid_stream(h)) return REPT_EINVAL;
+    if (num_edges == 0) return REPT_OK;
+    if (!edges || ((uintptr_t)edges & 7u)) return REPT_EINVAL;
+    if (num_edges > h->max_chunk || h->st.T + num_edges > h->capacity) return REPT_ENOMEM;
+    const size_t temp = rept_inc_sort_temp_bytes(2 * num_edges, h->st.end_bit);
+    if (temp == 0) return REPT_EDEVICE;
+    if (temp > h->st.temp_bytes) return REPT_ENOMEM;  // not expected: sized for the largest chunk
+    hipStream_t s = (hipStream_t)stream;
+    if (rept_inc_prepare(h->st, edges, num_edges, s) != hipSuccess) return REPT_EDEVICE;
+    uint32_t flags = 0;
+    if (hipMemcpyAsync(&flags, h->st.flags, sizeof(flags), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return REPT_EDEVICE;
+    // the stream's own order of precedence: ids, then self-loops, then repeated pairs
+    if (flags & RF_RANGE) return REPT_ERANGE;
+    if (flags & RF_SELFLOOP) return REPT_ESELFLOOP;
+    if (flags & RF_DUP) return REPT_EDUP;
+    if (rept_inc_commit(h->st, num_edges, h->base, s) != hipSuccess) return REPT_EDEVICE;
+    return REPT_OK;
+}
+
+rept_status rept_stream_num_edges(const rept_stream* h, uint64_t* num_edges) {
+    if (!valid_stream(h) || !num_edges) return REPT_EINVAL;
+    *num_edges = h->st.T;
+    return REPT_OK;
+}
+
+void rept_stream_destroy(rept_stream* h) {
+    if (valid_stream(h)) {
+        h->magic = 0;
+        free(h);
+    }
 }
 
 void rept_destroy(rept_graph* graph) {

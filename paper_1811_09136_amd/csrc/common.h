@@ -140,3 +140,48 @@ uint32_t rept_count_lds(uint32_t threads, uint32_t wave_cap, uint32_t block_cap,
 // resident workgroups per CU of the counting kernel for a launch shape (0 if unknown)
 uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes, bool eta);
 uint32_t rept_num_cus();
+
+// ---- incremental streaming (stream.hip) ------------------------------------------------------
+// Device state of an incrementally built stream: the adjacency of the edges seen so far, both
+// directions, keys (x << 32 | y) sorted ascending with arrival times beside them (double
+// buffered: the merge writes the other copy), node offsets, and the chunk work space.
+struct IncState {
+    uint32_t n;
+    uint32_t end_bit;  // radix-sort bits of a key: 32 + bit length of n - 1
+    uint64_t T;        // edges appended so far
+    int cur;           // the current adjacency copy
+    uint64_t* key[2];
+    uint32_t* tim[2];
+    uint32_t* off;   // [n + 1] offsets into the current copy
+    uint32_t* coff;  // [n + 1] first position of each node's run in the sorted chunk
+    uint64_t *ckey_a, *ckey_b;  // chunk keys before / after the sort (a: item lengths later)
+    uint32_t *ctim_a, *ctim_b;
+    uint64_t* end;      // inclusive scan of the item lengths
+    uint32_t* flags;    // validation word (RF_*)
+    void* temp;         // rocPRIM temporary storage
+    size_t temp_bytes;
+    uint32_t count_blocks;
+};
+// Arguments of the per-edge counting kernel
+struct IncCount {
+    const uint64_t* key;
+    const uint32_t* tim;
+    const uint32_t* off;
+    const uint64_t* ck;  // sorted chunk keys
+    const uint32_t* ct;  // their times
+    const uint64_t* end;
+    uint64_t N2;
+    int64_t* global;
+    int64_t* local;
+    uint32_t n, m, c, G;
+    uint32_t ck_full, last_ck, pstride, per_proc;  // processor map as in JobDev
+    uint64_t hp[4 * REPT_GMAX];
+};
+// rocPRIM temporary bytes for sorting `entries` keys of end_bit bits and scanning as many lengths
+// (queries the current device; 0 on failure)
+size_t rept_inc_sort_temp_bytes(uint64_t entries, uint32_t end_bit);
+hipError_t rept_inc_zero64(void* p, uint64_t words, hipStream_t stream);
+// steps 1-3 of an append (keys, sort, validation, chunk runs); the state is not changed
+hipError_t rept_inc_prepare(const IncState& st, const uint32_t* edges, uint64_t W, hipStream_t stream);
+// steps 4-5 (merge, count); advances st.cur and st.T
+hipError_t rept_inc_commit(IncState& st, uint64_t W, const IncCount& base, hipStream_t stream);

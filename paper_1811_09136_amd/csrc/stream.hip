@@ -1,0 +1,286 @@
+// Incremental streaming (Section II: the stream arrives over time; REPT's sets are built on the
+// fly): the stream is taken in chunks, and after every chunk the counters hold Algorithm 1's
+// updates of every edge seen so far.
+//
+// State on the device: the whole adjacency of the edges seen so far, both directions, as one
+// array of keys (x << 32 | y) sorted by (x, y) with the arrival time of each edge beside it,
+// and the node offsets into it.  An append:
+//   1. turns the chunk into keys (both directions, times T .. T+W-1) and checks ids and
+//      self-loops;
+//   2. sorts the chunk's keys (rocPRIM radix sort);
+//   3. checks for an unordered pair twice in the chunk or already in the adjacency (binary
+//      search in the node's sorted list), and finds each node's run in the sorted chunk;
+//   4. after the host has read the validation word (the one synchronisation), merges the chunk
+//      into the adjacency: every old and every new entry computes its merged position by one
+//      binary search in the other side's run of the same node, so the merge is one pass;
+//   5. counts the chunk's edges: for the edge (u, v) at time t, the entries w of the shorter of
+//      the two lists that arrived before t are searched in the other list (arrived before t as
+//      well); each common neighbour is a triangle whose last edge is (u, v), and every group
+//      whose hash puts {u, w} and {v, w} in the same active slot adds it to that processor's
+//      counters (Algorithm 1's UpdateTriangleCNT).  The work is one item per (edge, entry of
+//      its shorter list), spread evenly over the grid through an inclusive scan of the lengths.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include "common.h"
+#include "edge_hash.h"
+
+namespace {
+
+constexpr uint32_t kThreads = 256;
+constexpr uint32_t kHist = 1024;  // processors aggregated in LDS by the counting kernel
+
+__device__ __forceinline__ uint32_t hi32(uint64_t k) { return (uint32_t)(k >> 32); }
+__device__ __forceinline__ uint32_t lo32(uint64_t k) { return (uint32_t)k; }
+
+// first index in [lo, hi) with key >= x (keys sorted ascending)
+__device__ __forceinline__ uint64_t lower_bound64(const uint64_t* __restrict__ k, uint64_t lo, uint64_t hi,
+                                                  uint64_t x) {
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (k[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// 1. chunk edges -> keys of both directions, times; invalid ids are flagged and replaced by
+// node 0 so that every later index stays in range (the append is refused anyway)
+__global__ void __launch_bounds__(kThreads) k_inc_keys(const uint2* __restrict__ edges, uint64_t W, uint32_t n,
+                                                       uint32_t T, uint64_t* __restrict__ key,
+                                                       uint32_t* __restrict__ tim, uint32_t* __restrict__ flags) {
+    uint32_t f = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < W; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint2 e = edges[i];
+        if (e.x >= n || e.y >= n) {
+            f |= RF_RANGE;
+            e = make_uint2(0u, 0u);
+        } else if (e.x == e.y) {
+            f |= RF_SELFLOOP;
+        }
+        key[2 * i] = ((uint64_t)e.x << 32) | e.y;
+        key[2 * i + 1] = ((uint64_t)e.y << 32) | e.x;
+        tim[2 * i] = tim[2 * i + 1] = T + (uint32_t)i;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+// 3a. a pair twice in the sorted chunk, or already in the adjacency
+__global__ void __launch_bounds__(kThreads) k_inc_check(const uint64_t* __restrict__ ck, uint64_t N2,
+                                                        const uint64_t* __restrict__ akey,
+                                                        const uint32_t* __restrict__ off,
+                                                        uint32_t* __restrict__ flags) {
+    uint32_t f = 0;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N2; p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = ck[p];
+        if (p && ck[p - 1] == k) f |= RF_DUP;
+        const uint32_t x = hi32(k);
+        const uint64_t s = off[x], e = off[x + 1];
+        const uint64_t j = lower_bound64(akey, s, e, k);
+        if (j < e && akey[j] == k) f |= RF_DUP;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+// 3b. coff[x] = first chunk position with node >= x, for x in [0, n]
+__global__ void __launch_bounds__(kThreads) k_inc_coff(const uint64_t* __restrict__ ck, uint64_t N2, uint32_t n,
+                                                       uint32_t* __restrict__ coff) {
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= n; x += (uint64_t)gridDim.x * blockDim.x)
+        coff[x] = (uint32_t)lower_bound64(ck, 0, N2, x << 32);
+}
+
+// 4a. old entries move up by the number of chunk entries of their node with a smaller key
+__global__ void __launch_bounds__(kThreads) k_inc_merge_old(const uint64_t* __restrict__ akey,
+                                                            const uint32_t* __restrict__ atim, uint64_t N,
+                                                            const uint32_t* __restrict__ off,
+                                                            const uint32_t* __restrict__ coff,
+                                                            const uint64_t* __restrict__ ck,
+                                                            uint64_t* __restrict__ okey, uint32_t* __restrict__ otim) {
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = akey[p];
+        const uint32_t x = hi32(k);
+        const uint64_t r = lower_bound64(ck, coff[x], coff[x + 1], k) - coff[x];
+        const uint64_t q = p + coff[x] + r;  // off[x] + coff[x] + (p - off[x]) + r
+        okey[q] = k;
+        otim[q] = atim[p];
+    }
+}
+
+// 4b. chunk entries land after the old entries of their node with a smaller key
+__global__ void __launch_bounds__(kThreads) k_inc_merge_new(const uint64_t* __restrict__ ck,
+                                                            const uint32_t* __restrict__ ct, uint64_t N2,
+                                                            const uint32_t* __restrict__ off,
+                                                            const uint64_t* __restrict__ akey,
+                                                            uint64_t* __restrict__ okey, uint32_t* __restrict__ otim) {
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N2; p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = ck[p];
+        const uint32_t x = hi32(k);
+        const uint64_t r = lower_bound64(akey, off[x], off[x + 1], k) - off[x];
+        const uint64_t q = off[x] + p + r;  // off[x] + coff[x] + (p - coff[x]) + r
+        okey[q] = k;
+        otim[q] = ct[p];
+    }
+}
+
+// 4c. merged offsets: off[x] += coff[x]
+__global__ void __launch_bounds__(kThreads) k_inc_off(uint32_t* __restrict__ off, const uint32_t* __restrict__ coff,
+                                                      uint32_t n) {
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= n; x += (uint64_t)gridDim.x * blockDim.x)
+        off[x] += coff[x];
+}
+
+// 5a. items per chunk entry: the shorter list's length for the entry (u, v) with u < v (each
+// chunk edge once), 0 for the other direction
+__global__ void __launch_bounds__(kThreads) k_inc_lens(const uint64_t* __restrict__ ck, uint64_t N2,
+                                                       const uint32_t* __restrict__ off, uint64_t* __restrict__ len) {
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N2; p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = ck[p];
+        const uint32_t u = hi32(k), v = lo32(k);
+        uint64_t l = 0;
+        if (u < v) {
+            const uint32_t du = off[u + 1] - off[u], dv = off[v + 1] - off[v];
+            l = du < dv ? du : dv;
+        }
+        len[p] = l;
+    }
+}
+
+// 5b. the count: item i belongs to the chunk entry p with end[p - 1] <= i < end[p]
+__global__ void __launch_bounds__(kThreads) k_inc_count(IncCount a) {
+    __shared__ unsigned int hist[kHist];
+    const bool use_hist = a.c <= kHist;
+    for (uint32_t i = threadIdx.x; i < kHist; i += blockDim.x) hist[i] = 0u;
+    __syncthreads();
+    const uint64_t total = a.N2 ? a.end[a.N2 - 1] : 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        // the entry: first p with end[p] > i
+        uint64_t lo = 0, hi = a.N2;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (a.end[mid] <= i) lo = mid + 1;
+            else hi = mid;
+        }
+        const uint64_t p = lo;
+        const uint64_t k = a.ck[p];
+        const uint32_t t = a.ct[p];
+        const uint32_t u = hi32(k), v = lo32(k);
+        const uint32_t su = a.off[u], du = a.off[u + 1] - su, sv = a.off[v], dv = a.off[v + 1] - sv;
+        const uint64_t j = i - (p ? a.end[p - 1] : 0);
+        // A: the shorter list (ties: u's), B: the other
+        const bool au = du <= dv;
+        const uint32_t sa = au ? su : sv;
+        const uint32_t sb = au ? sv : su, db = au ? dv : du, b = au ? v : u;
+        const uint32_t ta = a.tim[sa + j];
+        if (ta >= t) continue;  // {x, w} arrived at or after (u, v): not yet in any set
+        const uint32_t w = lo32(a.key[sa + j]);
+        const uint64_t want = ((uint64_t)b << 32) | w;
+        const uint64_t q = lower_bound64(a.key, sb, (uint64_t)sb + db, want);
+        if (q >= (uint64_t)sb + db || a.key[q] != want || a.tim[q] >= t) continue;
+        // triangle {u, v, w} with last edge (u, v): per group, the processor that stored both
+        // {u, w} and {v, w}, if one did
+        for (uint32_t g = 0; g < a.G; ++g) {
+            const uint64_t* c4 = a.hp + 4 * g;
+            const uint32_t s1 = rept_hash::slot_of(c4, a.m, u, w);
+            const uint32_t s2 = rept_hash::slot_of(c4, a.m, v, w);
+            const uint32_t active = (g + 1 < a.G) ? a.ck_full : a.last_ck;
+            if (s1 != s2 || s1 >= active) continue;
+            const uint32_t proc = g * a.pstride + s1;
+            if (use_hist) atomicAdd(&hist[proc], 1u);
+            else atomicAdd((unsigned long long*)a.global + proc, 1ull);
+            int64_t* row = a.local + (uint64_t)(a.per_proc ? proc : g) * a.n;
+            atomicAdd((unsigned long long*)row + u, 1ull);
+            atomicAdd((unsigned long long*)row + v, 1ull);
+            atomicAdd((unsigned long long*)row + w, 1ull);
+        }
+    }
+    if (use_hist) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < a.c; i += blockDim.x)
+            if (hist[i]) atomicAdd((unsigned long long*)a.global + i, (unsigned long long)hist[i]);
+    }
+}
+
+__global__ void k_inc_zero64(uint64_t* p, uint64_t words) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+uint32_t grid_of(uint64_t items, uint32_t cap) {
+    uint64_t b = (items + kThreads - 1) / kThreads;
+    if (b > cap) b = cap;
+    return b ? (uint32_t)b : 1u;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------- launchers ----
+
+size_t rept_inc_sort_temp_bytes(uint64_t entries, uint32_t end_bit) {
+    size_t a = 0, b = 0;
+    uint64_t* kp = nullptr;
+    uint32_t* vp = nullptr;
+    uint64_t* lp = nullptr;
+    if (rocprim::radix_sort_pairs(nullptr, a, kp, kp, vp, vp, (size_t)entries, 0, end_bit) != hipSuccess) return 0;
+    if (rocprim::inclusive_scan(nullptr, b, lp, lp, (size_t)entries, rocprim::plus<uint64_t>()) != hipSuccess) return 0;
+    const size_t m = a > b ? a : b;
+    return m ? m : 1;
+}
+
+hipError_t rept_inc_zero64(void* p, uint64_t words, hipStream_t s) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_inc_zero64, dim3(grid_of(words, 4096)), dim3(kThreads), 0, s, (uint64_t*)p, words);
+    return hipGetLastError();
+}
+
+hipError_t rept_inc_prepare(const IncState& st, const uint32_t* edges, uint64_t W, hipStream_t s) {
+    (void)hipGetLastError();
+    const uint64_t N2 = 2 * W;
+    hipLaunchKernelGGL(k_inc_zero64, dim3(1), dim3(64), 0, s, (uint64_t*)st.flags, (uint64_t)1);
+    hipLaunchKernelGGL(k_inc_keys, dim3(grid_of(W, 8192)), dim3(kThreads), 0, s, (const uint2*)edges, W, st.n,
+                       (uint32_t)st.T, st.ckey_a, st.ctim_a, st.flags);
+    size_t tb = st.temp_bytes;
+    hipError_t e = rocprim::radix_sort_pairs(st.temp, tb, st.ckey_a, st.ckey_b, st.ctim_a, st.ctim_b, (size_t)N2, 0,
+                                             st.end_bit, s);
+    if (e != hipSuccess) return e;
+    const uint64_t* akey = st.key[st.cur];
+    hipLaunchKernelGGL(k_inc_check, dim3(grid_of(N2, 8192)), dim3(kThreads), 0, s, st.ckey_b, N2, akey, st.off,
+                       st.flags);
+    hipLaunchKernelGGL(k_inc_coff, dim3(grid_of((uint64_t)st.n + 1, 8192)), dim3(kThreads), 0, s, st.ckey_b, N2,
+                       st.n, st.coff);
+    return hipGetLastError();
+}
+
+hipError_t rept_inc_commit(IncState& st, uint64_t W, const IncCount& base, hipStream_t s) {
+    (void)hipGetLastError();
+    const uint64_t N2 = 2 * W, N = 2 * st.T;
+    const int nxt = st.cur ^ 1;
+    hipLaunchKernelGGL(k_inc_merge_old, dim3(grid_of(N, 8192)), dim3(kThreads), 0, s, st.key[st.cur], st.tim[st.cur],
+                       N, st.off, st.coff, st.ckey_b, st.key[nxt], st.tim[nxt]);
+    hipLaunchKernelGGL(k_inc_merge_new, dim3(grid_of(N2, 8192)), dim3(kThreads), 0, s, st.ckey_b, st.ctim_b, N2,
+                       st.off, st.key[st.cur], st.key[nxt], st.tim[nxt]);
+    hipLaunchKernelGGL(k_inc_off, dim3(grid_of((uint64_t)st.n + 1, 8192)), dim3(kThreads), 0, s, st.off, st.coff,
+                       st.n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    st.cur = nxt;
+    st.T += W;
+    // the count of the chunk's edges against the merged adjacency
+    uint64_t* len = st.ckey_a;  // free after the sort
+    hipLaunchKernelGGL(k_inc_lens, dim3(grid_of(N2, 8192)), dim3(kThreads), 0, s, st.ckey_b, N2, st.off, len);
+    size_t tb = st.temp_bytes;
+    e = rocprim::inclusive_scan(st.temp, tb, len, st.end, (size_t)N2, rocprim::plus<uint64_t>(), s);
+    if (e != hipSuccess) return e;
+    IncCount a = base;
+    a.key = st.key[st.cur];
+    a.tim = st.tim[st.cur];
+    a.off = st.off;
+    a.ck = st.ckey_b;
+    a.ct = st.ctim_b;
+    a.end = st.end;
+    a.N2 = N2;
+    hipLaunchKernelGGL(k_inc_count, dim3(st.count_blocks), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}

@@ -85,6 +85,11 @@ def lib() -> ctypes.CDLL:
             "rept_count_eta_workspace_size": ([vp, P(rept_params), P(sz)], i32),
             "rept_count_eta": ([vp, P(rept_params), vp, vp, vp, vp, vp, sz, P(rept_tuning), vp], i32),
             "rept_estimate_combined": ([u32, P(rept_params), vp, vp, ctypes.c_int64, vp, vp, vp], i32),
+            "rept_stream_query_sizes": ([u32, u64, u64, P(sz)], i32),
+            "rept_stream_create": ([u32, u64, u64, P(rept_params), vp, sz, vp, vp, vp, P(vp)], i32),
+            "rept_stream_append": ([vp, vp, u64, vp], i32),
+            "rept_stream_num_edges": ([vp, P(u64)], i32),
+            "rept_stream_destroy": ([vp], None),
             "rept_reduce_local": ([vp, u32, u32, vp, vp], i32),
             "rept_hash_slots": ([P(rept_params), vp, u64, vp, vp], i32),
             "rept_batch_workspace_size": ([u32, P(sz)], i32),
@@ -106,7 +111,8 @@ def lib() -> ctypes.CDLL:
 EXPORTED = ["rept_local_rows", "rept_query_sizes", "rept_build", "rept_build_host", "rept_graph_get_info",
             "rept_count_workspace_size", "rept_count",
             "rept_count_range", "rept_estimate", "rept_estimate_sums", "rept_count_eta_workspace_size",
-            "rept_count_eta", "rept_estimate_combined", "rept_reduce_local", "rept_hash_slots", "rept_batch_workspace_size",
+            "rept_count_eta", "rept_estimate_combined", "rept_stream_query_sizes", "rept_stream_create",
+            "rept_stream_append", "rept_stream_num_edges", "rept_stream_destroy", "rept_reduce_local", "rept_hash_slots", "rept_batch_workspace_size",
             "rept_batch_prepare", "rept_batch_launch", "rept_batch_count", "rept_destroy", "rept_status_str",
             "rept_device_cus"]
 
@@ -289,6 +295,35 @@ def rept_estimate_combined(n: int, params: Params, glob: np.ndarray, loc: np.nda
     return th.value, tv
 
 
+def rept_stream_query_sizes(n: int, capacity: int, max_chunk: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().rept_stream_query_sizes(n, capacity, max_chunk, ctypes.byref(b)), "rept_stream_query_sizes")
+    return b.value
+
+
+def rept_stream_create(n: int, capacity: int, max_chunk: int, params: Params, buf_ptr: int, buf_bytes: int,
+                       global_ptr: int, local_ptr: int, stream_ptr: int | None) -> int:
+    p = params.c_struct()
+    h = ctypes.c_void_p(0)
+    _check(lib().rept_stream_create(n, capacity, max_chunk, ctypes.byref(p), buf_ptr, buf_bytes, global_ptr,
+                                    local_ptr, stream_ptr, ctypes.byref(h)), "rept_stream_create")
+    return h.value
+
+
+def rept_stream_append(handle: int, edges_ptr: int, num_edges: int, stream_ptr: int | None):
+    _check(lib().rept_stream_append(handle, edges_ptr, num_edges, stream_ptr), "rept_stream_append")
+
+
+def rept_stream_num_edges(handle: int) -> int:
+    v = ctypes.c_uint64(0)
+    _check(lib().rept_stream_num_edges(handle, ctypes.byref(v)), "rept_stream_num_edges")
+    return v.value
+
+
+def rept_stream_destroy(handle: int):
+    lib().rept_stream_destroy(handle)
+
+
 def rept_reduce_local(local_ptr: int, rows: int, n: int, sums_ptr: int, stream_ptr: int | None):
     """sums[v] = sum of the rows of local at v, on the device (exact int64)."""
     _check(lib().rept_reduce_local(local_ptr, rows, n, sums_ptr, stream_ptr), "rept_reduce_local")
@@ -421,6 +456,54 @@ class Graph:
             self.handle = None
             self.persistent = None
             self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class IncrementalStream:
+    """A stream appended chunk by chunk on the device; `counts` (global int64[c], local
+    int64[rows][n]) always hold Algorithm 1's updates of every edge appended so far."""
+
+    def __init__(self, n: int, capacity: int, max_chunk: int, params: Params, device="cuda", stream=None):
+        import torch
+        self.n, self.params, self.device = int(n), params, torch.device(device)
+        nbytes = rept_stream_query_sizes(self.n, capacity, max_chunk)
+        self.buffer = _alloc(nbytes, self.device)
+        self.counts = (torch.empty(params.c, dtype=torch.int64, device=self.device),
+                       torch.empty((params.rows, self.n), dtype=torch.int64, device=self.device))
+        self.handle = rept_stream_create(self.n, capacity, max_chunk, params, self.buffer.data_ptr(), nbytes,
+                                         self.counts[0].data_ptr(), self.counts[1].data_ptr(), _stream_ptr(stream))
+
+    def append(self, edges_dev, stream=None):
+        """Append a device [W, 2] chunk (int32 bits of uint32 ids).  Raises ReptError (state
+        unchanged) if the chunk is invalid."""
+        W = int(edges_dev.shape[0])
+        if W:
+            if not edges_dev.is_contiguous():
+                raise ValueError("edges must be contiguous")
+            rept_stream_append(self.handle, edges_dev.data_ptr(), W, _stream_ptr(stream))
+        self._last = edges_dev  # the chunk stays referenced until the next append
+
+    @property
+    def num_edges(self) -> int:
+        return rept_stream_num_edges(self.handle)
+
+    def estimate(self):
+        """(tau_hat, tau_v_hat) of the stream so far (synchronises)."""
+        import torch
+        torch.cuda.synchronize(self.device)
+        g, l = self.counts[0].cpu().numpy(), self.counts[1].cpu().numpy()
+        return rept_estimate(self.n, self.params, g, l)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            rept_stream_destroy(self.handle)
+            self.handle = None
+            self.buffer = None
 
     def __del__(self):
         try:

@@ -1,0 +1,112 @@
+"""Incremental streams on the device: after every appended chunk the counters equal the
+oracle's replay of the stream so far (bit for bit), for REPT (all group layouts) and parallel
+MASCOT; invalid chunks are refused and leave the state unchanged.
+
+Each case prints its name and shape before touching the GPU."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _oracle(edges, n, p):
+    if p.mascot:
+        return oracle.mascot(edges, n, p.m, p.c, p.seed)
+    return oracle.rept(edges, n, p.m, p.c, p.seed, per_proc=p.per_proc)
+
+
+def _check(inc, edges_so_far, n, p):
+    import torch
+    torch.cuda.synchronize()
+    og, ol = _oracle(edges_so_far, n, p)
+    assert np.array_equal(inc.counts[0].cpu().numpy(), og)
+    assert np.array_equal(inc.counts[1].cpu().numpy(), ol)
+    assert inc.num_edges == len(edges_so_far)
+
+
+@pytest.mark.parametrize("m,c,per_proc,mascot", [(3, 7, False, False), (1, 1, False, False), (10, 40, False, False),
+                                                 (4, 4, True, False), (2, 5, False, True), (5, 3, False, False)])
+def test_chunks_equal_oracle_prefixes(cuda, m, c, per_proc, mascot):
+    from paper_1811_09136_amd import rept
+    e = synth.er(300, 3000, 7 + m, 8 + c)
+    p = rept.Params(m, c, 40 + m * c, per_proc, mascot)
+    _say(f"stream ER n=300 E=3000 m={m} c={c} per_proc={per_proc} mascot={mascot}")
+    inc = rept.IncrementalStream(300, 3000, 1200, p, cuda)
+    cuts = [0, 1, 8, 9, 1000, 1700, 2900, 3000]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        inc.append(rept.to_device_edges(e[a:b], cuda))
+        _check(inc, e[:b], 300, p)
+    inc.close()
+
+
+def test_hub_stream_and_estimates(cuda):
+    """A power-law stream with hub lists in uneven chunks; the estimates after each chunk
+    equal the oracle's estimates of the prefix (0 ulp)."""
+    from paper_1811_09136_amd import rept
+    e, n = synth.scaled_chung_lu(200_000, 19)
+    p = rept.Params(10, 40, 3)
+    _say(f"stream Chung-Lu n={n} E={len(e)} m=10 c=40")
+    inc = rept.IncrementalStream(n, len(e), 90_000, p, cuda)
+    for a, b in [(0, 50_000), (50_000, 50_001), (50_001, 140_000), (140_000, 200_000)]:
+        inc.append(rept.to_device_edges(e[a:b], cuda))
+        og, ol = oracle.rept(e[:b], n, 10, 40, 3)
+        th, tv = inc.estimate()
+        oth, otv = oracle.estimate(n, 10, 40, og, ol)
+        assert th == oth and np.array_equal(tv.view(np.uint64), otv.view(np.uint64))
+    inc.close()
+
+
+def test_equals_count_on_the_whole_stream(cuda):
+    """The final counters equal rept_count on the stream built at once."""
+    import torch
+    from paper_1811_09136_amd import rept
+    e, n = synth.scaled_chung_lu(300_000, 23)
+    p = rept.Params(10, 15, 8)
+    _say(f"stream vs rept_count Chung-Lu n={n} E={len(e)} m=10 c=15")
+    inc = rept.IncrementalStream(n, len(e), 100_000, p, cuda)
+    for a in range(0, len(e), 100_000):
+        inc.append(rept.to_device_edges(e[a:a + 100_000], cuda))
+    g = rept.Graph(rept.to_device_edges(e, cuda), n)
+    glob, loc = g.count(p)
+    torch.cuda.synchronize()
+    assert torch.equal(inc.counts[0], glob) and torch.equal(inc.counts[1], loc)
+    g.close()
+    inc.close()
+
+
+def test_invalid_chunks_leave_state_unchanged(cuda):
+    from paper_1811_09136_amd import rept
+    e = synth.er(100, 800, 3, 4)
+    p = rept.Params(2, 3, 5)
+    _say("stream invalid chunks")
+    inc = rept.IncrementalStream(100, 750, 400, p, cuda)
+    inc.append(rept.to_device_edges(e[:300], cuda))
+    bad = [(np.array([[5, 5]], np.uint32), rept.REPT_ESELFLOOP),
+           (np.array([[1, 100]], np.uint32), rept.REPT_ERANGE),
+           (np.vstack([e[300:310], e[300:301][:, ::-1]]).astype(np.uint32), rept.REPT_EDUP),  # twice in a chunk
+           (np.vstack([e[300:305], e[10:11]]).astype(np.uint32), rept.REPT_EDUP),  # already appended
+           (np.vstack([e[300:305], [[7, 7]], [[1, 1000]]]).astype(np.uint32), rept.REPT_ERANGE),
+           (e[300:701], rept.REPT_ENOMEM)]  # longer than max_chunk
+    for chunk, code in bad:
+        with pytest.raises(rept.ReptError) as ei:
+            inc.append(rept.to_device_edges(chunk, cuda))
+        assert ei.value.code == code
+        _check(inc, e[:300], 100, p)
+    inc.append(rept.to_device_edges(e[300:700], cuda))
+    _check(inc, e[:700], 100, p)
+    with pytest.raises(rept.ReptError) as ei:
+        inc.append(rept.to_device_edges(e[700:800], cuda))  # 800 edges > capacity 750
+    assert ei.value.code == rept.REPT_ENOMEM
+    _check(inc, e[:700], 100, p)
+    inc.append(rept.to_device_edges(e[700:750], cuda))
+    _check(inc, e[:750], 100, p)
+    inc.append(rept.to_device_edges(e[750:750], cuda))  # an empty chunk changes nothing
+    _check(inc, e[:750], 100, p)
+    inc.close()
