@@ -370,7 +370,13 @@ typedef struct rept_tuning {
     uint32_t blocks;     /* persistent workgroups (default: as many as fit, up to 4 per CU) */
     uint32_t threads;    /* 64..1024, a multiple of 64 (default 256) */
     uint32_t light_tile; /* 1..64: apexes taken per queue pop by a wavefront (default 8) */
-    uint32_t reserved[2];
+    uint32_t phase_launches; /* 1: both phases in one launch; 2: the light phase (apexes of at most
+                                wave_cap entries, one per wavefront) runs as a launch of its own
+                                after the heavy one, its workgroups holding no heavy team area in
+                                LDS, so more wavefronts are resident; 0 or 3: that launch on a
+                                second stream of the library's, forked from and joined back to
+                                `stream`, so it runs beside the heavy launch (default) */
+    uint32_t reserved;       /* must be 0 */
 } rept_tuning;
 
 /* Device workspace bytes for a batch of njobs jobs. */

@@ -172,6 +172,19 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     h->any_zero = any_zero ? 1u : 0u;
     h->any_eta = eta ? 1u : 0u;
     h->zero_words = zero_words;
+    // the light phase in a launch of its own: the same workgroup size, no heavy team area
+    const uint32_t pl = tu ? tu->phase_launches : 0u;
+    if (pl > 3 || (tu && tu->reserved)) return REPT_EINVAL;
+    h->split = pl != 1 ? 1u : 0u;
+    h->split_streams = (pl == 0 || pl == 3) ? 1u : 0u;
+    if (h->split) {
+        h->light_threads = threads;
+        h->light_lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table, eta, false);
+        uint32_t per_cu = rept_count_blocks_per_cu(threads, h->light_lds, eta);
+        if (per_cu == 0) per_cu = 1;
+        if (per_cu > 8) per_cu = 8;
+        h->light_blocks = (tu && tu->blocks) ? tu->blocks : per_cu * cus;
+    }
     return REPT_OK;
 }
 

@@ -108,6 +108,12 @@ struct alignas(128) BatchHeader {
     uint32_t any_fill;     // some job's slot table is written by this launch
     uint32_t fill_edges;   // largest stream length over those jobs (bounds their stored edges)
     uint32_t any_eta;      // some job counts Algorithm 2's pair counters (the kernel's second form)
+    uint32_t split;          // 1: the light phase is a launch of its own (shape below)
+    uint32_t light_threads;  // its workgroup size
+    uint32_t light_blocks;   // its grid
+    uint32_t light_lds;      // its dynamic LDS bytes (no heavy team area)
+    uint32_t split_streams;  // 1: that launch runs on a second stream, beside the heavy one
+    uint32_t pad_[2];
     uint32_t queues[kQueues * kQueueStride];  // sub-queue counters, reset by setup
 };
 
@@ -134,9 +140,10 @@ hipError_t rept_launch_eta(const rept_graph* g, const JobDev& d, int64_t* eta, i
 hipError_t rept_launch_reduce(const int64_t* local, uint32_t rows, uint32_t n, int64_t* sums, hipStream_t stream);
 hipError_t rept_launch_slots(const uint64_t* hp, uint32_t G, uint32_t m, const uint32_t* edges,
                              uint64_t E, uint32_t* slots, hipStream_t stream);
-// LDS bytes of the counting kernel for a launch shape (eta: the form with Algorithm 2's counters)
+// LDS bytes of the counting kernel for a launch shape (eta: the form with Algorithm 2's counters;
+// heavy: the launch runs the heavy phase, whose team area shares the LDS with the light areas)
 uint32_t rept_count_lds(uint32_t threads, uint32_t wave_cap, uint32_t block_cap, uint32_t b_chunk, uint32_t G,
-                        uint32_t hist_c, uint32_t light_table, bool eta);
+                        uint32_t hist_c, uint32_t light_table, bool eta, bool heavy = true);
 // resident workgroups per CU of the counting kernel for a launch shape (0 if unknown)
 uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes, bool eta);
 uint32_t rept_num_cus();

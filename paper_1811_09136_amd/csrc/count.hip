@@ -28,6 +28,8 @@
 #include <stdint.h>
 #include <stdio.h>
 
+#include <mutex>
+
 #include "common.h"
 #include "edge_hash.h"
 
@@ -132,13 +134,14 @@ struct Layout {
     uint32_t union_off, total;
 };
 __host__ __device__ inline Layout count_layout(uint32_t nwaves, uint32_t DL, uint32_t DW, uint32_t DB,
-                                               uint32_t G, uint32_t HC, uint32_t LT, bool eta) {
+                                               uint32_t G, uint32_t HC, uint32_t LT, bool eta, bool heavy) {
     Layout L;
     L.misc = misc_layout(HC);
     L.heavy = area_layout(DW, DB, G, kHeavyTable, eta);
     L.light = area_layout(DL, DL, G, LT, eta);
     L.union_off = nwaves * L.misc.bytes;
-    const uint32_t u = L.heavy.bytes > nwaves * L.light.bytes ? L.heavy.bytes : nwaves * L.light.bytes;
+    const uint32_t hb = heavy ? L.heavy.bytes : 0u;  // a light-only launch has no heavy team area
+    const uint32_t u = hb > nwaves * L.light.bytes ? hb : nwaves * L.light.bytes;
     L.total = L.union_off + u;
     return L;
 }
@@ -1009,14 +1012,15 @@ __device__ uint32_t claim_tile(uint32_t* ctr, uint32_t total, uint32_t& q, uint3
 
 // ETA: the form that also counts Algorithm 2's per-edge pair counters for jobs that ask for
 // them (a separate instance, so the plain kernel's registers are not spent on them)
+// phases: 1 the heavy phase, 2 the light phase, 3 both (one launch)
 template <bool ETA>
-__global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* __restrict__ jobs) {
+__global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* __restrict__ jobs, uint32_t phases) {
     extern __shared__ __align__(16) uint8_t lds[];
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const uint32_t DL = hdr->wave_cap, DW = hdr->block_cap, DB = hdr->b_chunk;
     const uint32_t GM = hdr->G_max, HC = hdr->hist_c, njobs = hdr->njobs;
     const uint32_t LT = hdr->light_table;
-    const Layout L = count_layout(nw, DL, DW, DB, GM, HC, LT, ETA);
+    const Layout L = count_layout(nw, DL, DW, DB, GM, HC, LT, ETA, (phases & 1u) != 0);
     const WaveView V = wave_view(lds + wid * L.misc.bytes, L.misc);
     uint8_t* uni = lds + L.union_off;
     __shared__ uint32_t s_tile;
@@ -1026,7 +1030,7 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
     int cur = -1;
 
     // phase 1: long lists, one apex per workgroup
-    {
+    if (phases & 1u) {
         const TeamView T = team_view(uni, L.heavy, DW, DB, kHeavyTable);
         const uint32_t total = hdr->heavy_total;
         uint32_t q = blockIdx.x % kQueues, left = kQueues;  // used by thread 0
@@ -1051,7 +1055,7 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
     __syncthreads();  // the union area changes owners
 
     // phase 2: short lists, one apex per wavefront
-    {
+    if (phases & 2u) {
         const TeamView T = team_view(uni + wid * L.light.bytes, L.light, DL, DL, LT);
         const uint32_t total = hdr->light_total, tile_len = hdr->light_tile;
         uint32_t q = (blockIdx.x * nw + wid) % kQueues, left = kQueues;  // used by lane 0
@@ -1114,6 +1118,32 @@ __global__ void k_reduce_rows(const int64_t* local, uint32_t rows, uint32_t n, i
 
 bool g_attr_set = false;
 
+// Second stream of the current device for the light-phase launch, and the fork and join
+// events around it (created on first use, default priority, kept for the process).  One
+// enqueue sequence at a time: the events are re-recorded by every launch.
+struct AuxStream {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_aux_mu;
+AuxStream g_aux[16];
+hipError_t aux_for_current(AuxStream** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 16) return hipErrorInvalidDevice;
+    AuxStream& a = g_aux[dev];
+    if (a.device != dev) {
+        if ((e = hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&a.fork, hipEventDisableTiming)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&a.join, hipEventDisableTiming)) != hipSuccess) return e;
+        a.device = dev;
+    }
+    *out = &a;
+    return hipSuccess;
+}
+
 hipError_t report(hipError_t e, const char* what) {
     if (e != hipSuccess) fprintf(stderr, "rept: %s failed: %s\n", what, hipGetErrorString(e));
     return e;
@@ -1150,16 +1180,44 @@ hipError_t launch_common(uint8_t* ws, const BatchHeader& h, hipStream_t s) {
         if (blocks < 1) blocks = 1;
         hipLaunchKernelGGL(k_fill, dim3((uint32_t)blocks, h.njobs), dim3(256), 0, s, jobs);
     }
-    if (h.any_eta) hipLaunchKernelGGL(k_count<true>, dim3(h.blocks), dim3(h.threads), h.lds_bytes, s, hdr, jobs);
-    else hipLaunchKernelGGL(k_count<false>, dim3(h.blocks), dim3(h.threads), h.lds_bytes, s, hdr, jobs);
-    return report(hipGetLastError(), "counting kernel launch");
+    // heavy and light phases in one launch, or the light phase in a launch of its own (a
+    // light-only workgroup needs no heavy team area, so more wavefronts fit per CU)
+    // (split: the light launch on a second stream, forked after the setup kernels and joined
+    // back, so that it runs beside the heavy launch as workgroups free the CUs)
+    const uint32_t first = h.split ? 1u : 3u;
+    std::unique_lock<std::mutex> lk(g_aux_mu, std::defer_lock);
+    AuxStream* aux = nullptr;
+    hipStream_t ls = s;
+    if (h.split && h.split_streams) {
+        lk.lock();
+        if ((e = aux_for_current(&aux)) != hipSuccess) return report(e, "second stream");
+        if ((e = hipEventRecord(aux->fork, s)) != hipSuccess) return report(e, "fork event");
+        if ((e = hipStreamWaitEvent(aux->stream, aux->fork, 0)) != hipSuccess) return report(e, "fork wait");
+        ls = aux->stream;
+    }
+    if (h.any_eta) hipLaunchKernelGGL(k_count<true>, dim3(h.blocks), dim3(h.threads), h.lds_bytes, s, hdr, jobs, first);
+    else hipLaunchKernelGGL(k_count<false>, dim3(h.blocks), dim3(h.threads), h.lds_bytes, s, hdr, jobs, first);
+    if (h.split) {
+        if (h.any_eta)
+            hipLaunchKernelGGL(k_count<true>, dim3(h.light_blocks), dim3(h.light_threads), h.light_lds, ls, hdr, jobs,
+                               2u);
+        else
+            hipLaunchKernelGGL(k_count<false>, dim3(h.light_blocks), dim3(h.light_threads), h.light_lds, ls, hdr, jobs,
+                               2u);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return report(e, "counting kernel launch");
+    if (aux) {
+        if ((e = hipEventRecord(aux->join, aux->stream)) != hipSuccess) return report(e, "join event");
+        if ((e = hipStreamWaitEvent(s, aux->join, 0)) != hipSuccess) return report(e, "join wait");
+    }
+    return hipSuccess;
 }
 
 }  // namespace
 
 uint32_t rept_count_lds(uint32_t threads, uint32_t wave_cap, uint32_t block_cap, uint32_t b_chunk, uint32_t G,
-                        uint32_t hist_c, uint32_t light_table, bool eta) {
-    return count_layout(threads / 64, wave_cap, block_cap, b_chunk, G, hist_c, light_table, eta).total;
+                        uint32_t hist_c, uint32_t light_table, bool eta, bool heavy) {
+    return count_layout(threads / 64, wave_cap, block_cap, b_chunk, G, hist_c, light_table, eta, heavy).total;
 }
 
 uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes, bool eta) {

@@ -55,7 +55,7 @@ class rept_job(ctypes.Structure):
 class rept_tuning(ctypes.Structure):
     _fields_ = [("wave_cap", ctypes.c_uint32), ("block_cap", ctypes.c_uint32), ("b_chunk", ctypes.c_uint32),
                 ("blocks", ctypes.c_uint32), ("threads", ctypes.c_uint32), ("light_tile", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("phase_launches", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 _lib = None
@@ -533,6 +533,6 @@ def make_job(graph: Graph, params: Params, out, workspace, t0: int = 0, t1: int 
     return job
 
 
-def tuning(wave_cap=0, block_cap=0, b_chunk=0, blocks=0, threads=0, light_tile=0) -> rept_tuning:
+def tuning(wave_cap=0, block_cap=0, b_chunk=0, blocks=0, threads=0, light_tile=0, phase_launches=0) -> rept_tuning:
     """Launch shape of the counting kernel (zero = library default); see ``rept_tuning`` in rept.h."""
-    return rept_tuning(wave_cap, block_cap, b_chunk, blocks, threads, light_tile, (ctypes.c_uint32 * 2)())
+    return rept_tuning(wave_cap, block_cap, b_chunk, blocks, threads, light_tile, phase_launches, 0)
