@@ -90,7 +90,7 @@ __host__ __device__ inline uint32_t slot_width(uint32_t G) { return G <= 1 ? 1u 
 // wavefronts' light team areas (the heavy phase finishes before the light phase starts).
 struct Area {  // one team's staging area: W side (hash table of a's list) + B side (b lists)
     uint32_t hkey, hidx, ew, et, wslot, cntw;
-    uint32_t eb, etb, bslot, cntb, bpos, epos;
+    uint32_t eb, etb, bslot, cntb, bpos, epos, ewe, ebe;
     uint32_t red;  // 64 words of team scratch (scans, reductions, broadcast)
     uint32_t bytes;
 };
@@ -111,6 +111,9 @@ __host__ __device__ inline Area area_layout(uint32_t DW, uint32_t DB, uint32_t G
     A.cntb = p; p = up16(p + 4 * G * DB);
     A.bpos = p; p = up16(p + 8 * (DB + 1));  // (list offset, first item) per staged list
     A.epos = p; p = eta ? up16(p + 4 * DB) : p;  // position of the pair {a, b} in the adjacency
+    // Algorithm 2's per-edge counts of the W and B entries, (s, L) packed 16 + 16 bits per group
+    A.ewe = p; p = eta ? up16(p + 4 * G * DW) : p;
+    A.ebe = p; p = eta ? up16(p + 4 * G * DB) : p;
     A.red = p; p = up16(p + 4 * 64);
     A.bytes = p;
     return A;
@@ -160,6 +163,8 @@ struct TeamView {
     uint32_t* cntb;
     uint2* bpos;  // .x: offset of b's list, .y: index of its first item in the chunk's walk
     uint32_t* epos;  // adjacency position of each staged pair {a, b}
+    uint32_t* ewe;   // [G][DW] pair counts (s | L << 16) of the W entries since the last flush
+    uint32_t* ebe;   // [G][DB] the same for the B entries
     uint32_t* red;
     uint32_t DW, DB;
     uint32_t tf;  // hash slots per key, at least
@@ -179,6 +184,8 @@ __device__ inline TeamView team_view(uint8_t* base, const Area& A, uint32_t DW, 
     T.cntb = (uint32_t*)(base + A.cntb);
     T.bpos = (uint2*)(base + A.bpos);
     T.epos = (uint32_t*)(base + A.epos);
+    T.ewe = (uint32_t*)(base + A.ewe);
+    T.ebe = (uint32_t*)(base + A.ebe);
     T.red = (uint32_t*)(base + A.red);
     T.DW = DW;
     T.DB = DB;
@@ -478,18 +485,20 @@ __device__ void drain_hits_t(const JobRegs& J, const TeamView& T, const WaveView
                         }
                         if (ETA && J.pairs) {
                             // Algorithm 2's per-edge counts (Section III-B): the first two edges
-                            // gain a non-last occurrence; the last edge a last-edge occurrence
-                            // when the same processor stores it
-                            const uint32_t pab = T.epos[ib], paw = wbase + k;
-                            const uint32_t pf1 = last == 0 ? paw : pab, pf2 = last == 2 ? paw : p;
-                            const uint32_t pl = last == 0 ? pab : (last == 1 ? paw : p);
-                            uint32_t* cg = J.pairs + 2 * (uint64_t)g * J.es;
-                            atomicAdd(cg + 2 * (uint64_t)pf1, 1u);
-                            atomicAdd(cg + 2 * (uint64_t)pf2, 1u);
+                            // gain a non-last occurrence (s), the last edge a last-edge occurrence
+                            // (L) when the same processor stores it.  {a, w} and {a, b} are staged
+                            // entries, counted in LDS; {b, w} (list position p) in global memory.
                             const uint64_t llo = last == 0 ? alo : (last == 1 ? wlo : blo);
                             const uint64_t lhi = last == 0 ? ahi : (last == 1 ? whi : bhi);
                             const uint32_t sl = (uint32_t)((g < 4 ? llo >> (16 * g) : lhi >> (16 * (g - 4))) & 0xffffu);
-                            if (sl == s1) atomicAdd(cg + 2 * (uint64_t)pl + 1, 1u);
+                            const uint32_t lw = sl == s1 ? (1u << 16) : 0u;  // the last edge's L step
+                            const uint32_t we = last == 1 ? lw : 1u;  // {a, w}: last (L) or not (s)
+                            const uint32_t be = last == 0 ? lw : 1u;  // {a, b}
+                            if (we) atomicAdd(&T.ewe[g * T.DW + k], we);
+                            if (be) atomicAdd(&T.ebe[g * T.DB + ib], be);
+                            uint32_t* cp = J.pairs + 2 * ((uint64_t)g * J.es + p);
+                            if (last != 2) atomicAdd(cp, 1u);
+                            else if (lw) atomicAdd(cp + 1, 1u);
                         }
                     }
                 }
@@ -507,6 +516,13 @@ __device__ __forceinline__ void drain_hits(const JobRegs& J, const TeamView& T, 
     else if (J.gs == 2) drain_hits_t<2, ETA>(J, T, V, a, wbase, qn);
     else if (J.gs == 4) drain_hits_t<4, ETA>(J, T, V, a, wbase, qn);
     else drain_hits_t<8, ETA>(J, T, V, a, wbase, qn);
+}
+
+// add packed pair counts (s | L << 16) to the stored edge at adjacency position pos, group g
+__device__ __forceinline__ void flush_pair(const JobRegs& J, uint32_t g, uint32_t pos, uint32_t v) {
+    uint32_t* cp = J.pairs + 2 * ((uint64_t)g * J.es + pos);
+    if (v & 0xffffu) atomicAdd(cp, v & 0xffffu);
+    if (v >> 16) atomicAdd(cp + 1, v >> 16);
 }
 
 // popcount of the bits of `m` below this lane
@@ -669,6 +685,8 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
             load_slots(J.tab, J.gs, s + ws + i, lo, hi);
             store_row(T.wslot, J.gs, i, lo, hi);
             for (uint32_t g = 0; g < G; ++g) T.cntw[g * T.DW + i] = 0;
+            if (ETA)
+                for (uint32_t g = 0; g < G; ++g) T.ewe[g * T.DW + i] = 0;
             hash_insert(T.hkey, T.hidx, kbits, w, i);
         }
         team_sync<BLOCK>();
@@ -722,6 +740,8 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                     else load_slots(J.tab, J.gs, pab, lo, hi);
                     store_row(T.bslot, J.gs, pos, lo, hi);
                     for (uint32_t g = 0; g < G; ++g) T.cntb[g * T.DB + pos] = 0;
+                    if (ETA)
+                        for (uint32_t g = 0; g < G; ++g) T.ebe[g * T.DB + pos] = 0;
                 }
                 nb += tot_nb;
                 items += tot_items;
@@ -742,6 +762,23 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                     const uint32_t g = x / nb, i = x - g * nb;
                     const uint32_t v = T.cntb[g * T.DB + i];
                     if (v) add64(J.local + (uint64_t)g * J.n + T.eb[i], v);
+                }
+            }
+            if (ETA && J.pairs) {
+                // this B chunk's pair counts of the staged entries: at most one per W entry for a
+                // B entry and one per B list for a W entry, so 16 bits each cannot overflow
+                for (uint32_t x = tid; x < G * nb; x += nt) {
+                    const uint32_t g = x / nb, i = x - g * nb;
+                    const uint32_t v = T.ebe[g * T.DB + i];
+                    if (v) flush_pair(J, g, T.epos[i], v);
+                }
+                for (uint32_t x = tid; x < G * wn; x += nt) {
+                    const uint32_t g = x / wn, i = x - g * wn;
+                    const uint32_t v = T.ewe[g * T.DW + i];
+                    if (v) {
+                        flush_pair(J, g, s + ws + i, v);
+                        T.ewe[g * T.DW + i] = 0;
+                    }
                 }
             }
             team_sync<BLOCK>();
@@ -923,14 +960,23 @@ __global__ void __launch_bounds__(256) k_fill(const JobDev* __restrict__ jobs) {
 // s L + C(s, 2).  Both go to eta[0][i], eta[1][i]; each edge's share also goes to both of its
 // endpoints in eta_v[0][.], eta_v[1][.] (summed over processors).  Work split as in k_fill.
 constexpr uint32_t ETA_LDS_PROCS = 512;  // processors accumulated in LDS per workgroup
+constexpr uint32_t ETA_HASH = 1024;      // neighbour shares aggregated per workgroup (open addressing)
+constexpr uint32_t ETA_PROBES = 16;      // probes before a share goes to global memory directly
 __global__ void __launch_bounds__(256) k_eta(const uint32_t* __restrict__ off, const uint32_t* __restrict__ nbr,
                                              uint32_t n, const uint16_t* __restrict__ tab, uint32_t gs, uint32_t G,
                                              uint32_t m, uint32_t c, const uint32_t* __restrict__ pairs, uint32_t es,
                                              int64_t* __restrict__ eta, int64_t* __restrict__ eta_v) {
     __shared__ uint32_t so[FILL_NODES + 1];
     __shared__ unsigned long long acc[2][ETA_LDS_PROCS];
+    __shared__ unsigned long long own[2][FILL_NODES];  // shares of the owners in the node window
+    __shared__ uint32_t hkey[ETA_HASH];                 // neighbour id + 1, 0 = empty
+    __shared__ unsigned long long hval[2][ETA_HASH];
     const bool in_lds = c <= ETA_LDS_PROCS;
     for (uint32_t i = threadIdx.x; i < ETA_LDS_PROCS; i += 256u) acc[0][i] = acc[1][i] = 0ull;
+    for (uint32_t i = threadIdx.x; i < ETA_HASH; i += 256u) {
+        hkey[i] = 0u;
+        hval[0][i] = hval[1][i] = 0ull;
+    }
     const uint32_t Es = ldg(off + n);
     for (uint64_t c0 = (uint64_t)blockIdx.x * FILL_CHUNK; c0 < Es; c0 += (uint64_t)gridDim.x * FILL_CHUNK) {
         const uint32_t p0 = (uint32_t)c0, p1 = (c0 + FILL_CHUNK) < Es ? (uint32_t)(c0 + FILL_CHUNK) : Es;
@@ -939,6 +985,7 @@ __global__ void __launch_bounds__(256) k_eta(const uint32_t* __restrict__ off, c
             const uint32_t cnt = (bl + 1u - w0) < FILL_NODES ? (bl + 1u - w0) : FILL_NODES;
             __syncthreads();
             for (uint32_t i = threadIdx.x; i <= cnt; i += 256u) so[i] = ldg(off + w0 + i);
+            for (uint32_t i = threadIdx.x; i < cnt; i += 256u) own[0][i] = own[1][i] = 0ull;
             __syncthreads();
             const uint32_t q0 = so[0] > p0 ? so[0] : p0, q1 = so[cnt] < p1 ? so[cnt] : p1;
             for (uint32_t p = q0 + threadIdx.x; p < q1; p += 256u) {
@@ -968,11 +1015,45 @@ __global__ void __launch_bounds__(256) k_eta(const uint32_t* __restrict__ off, c
                         const uint32_t mid = (lo + hi) >> 1;
                         if (so[mid] <= p) lo = mid; else hi = mid;
                     }
-                    const uint32_t a = w0 + lo, b = ldg(nbr + p);
-                    atomicAdd((unsigned long long*)eta_v + a, fd);
-                    atomicAdd((unsigned long long*)eta_v + b, fd);
-                    atomicAdd((unsigned long long*)eta_v + n + a, fl);
-                    atomicAdd((unsigned long long*)eta_v + n + b, fl);
+                    atomicAdd(&own[0][lo], fd);  // the owner a = w0 + lo
+                    atomicAdd(&own[1][lo], fl);
+                    // the neighbour b: its slot in the workgroup's table, or global memory
+                    const uint32_t b = ldg(nbr + p), key = b + 1u;
+                    uint32_t h = (b * kHashMul) >> (32 - 10), probes = 0;
+                    bool done = false;
+                    for (; probes < ETA_PROBES; ++probes, h = (h + 1u) & (ETA_HASH - 1u)) {
+                        const uint32_t cur = hkey[h];
+                        if (cur == key || (cur == 0u && atomicCAS(&hkey[h], 0u, key) == 0u) || hkey[h] == key) {
+                            atomicAdd(&hval[0][h], fd);
+                            atomicAdd(&hval[1][h], fl);
+                            done = true;
+                            break;
+                        }
+                    }
+                    if (!done) {
+                        atomicAdd((unsigned long long*)eta_v + b, fd);
+                        atomicAdd((unsigned long long*)eta_v + n + b, fl);
+                    }
+                }
+            }
+            __syncthreads();
+            if (eta_v) {
+                for (uint32_t i = threadIdx.x; i < cnt; i += 256u) {
+                    if (own[0][i]) atomicAdd((unsigned long long*)eta_v + w0 + i, own[0][i]);
+                    if (own[1][i]) atomicAdd((unsigned long long*)eta_v + n + w0 + i, own[1][i]);
+                }
+            }
+        }
+        // the neighbour shares of this run of positions
+        __syncthreads();
+        if (eta_v) {
+            for (uint32_t i = threadIdx.x; i < ETA_HASH; i += 256u) {
+                const uint32_t key = hkey[i];
+                if (key) {
+                    if (hval[0][i]) atomicAdd((unsigned long long*)eta_v + (key - 1u), hval[0][i]);
+                    if (hval[1][i]) atomicAdd((unsigned long long*)eta_v + n + (key - 1u), hval[1][i]);
+                    hkey[i] = 0u;
+                    hval[0][i] = hval[1][i] = 0ull;
                 }
             }
         }
