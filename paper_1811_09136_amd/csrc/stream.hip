@@ -148,52 +148,87 @@ __global__ void __launch_bounds__(kThreads) k_inc_lens(const uint64_t* __restric
     }
 }
 
-// 5b. the count: item i belongs to the chunk entry p with end[p - 1] <= i < end[p]
+// first p in [lo, hi) with end[p] > i (end ascending)
+__device__ __forceinline__ uint64_t upper_item(const uint64_t* __restrict__ end, uint64_t lo, uint64_t hi, uint64_t i) {
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (end[mid] <= i) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// 5b. the count: item i belongs to the chunk entry p with end[p - 1] <= i < end[p].  A workgroup
+// takes kRun consecutive items; the slice of `end` they fall in is staged in LDS when it is
+// short enough (entries without items, the reverse direction of each edge, also sit in it),
+// so that each item finds its entry there.
+constexpr uint32_t kRun = 4096;    // items per workgroup run (16 per thread)
+constexpr uint32_t kStage = 4096;  // entries of `end` staged per run, at most
 __global__ void __launch_bounds__(kThreads) k_inc_count(IncCount a) {
     __shared__ unsigned int hist[kHist];
+    __shared__ uint64_t s_end[kStage];
+    __shared__ uint64_t s_lo, s_hi;
     const bool use_hist = a.c <= kHist;
     for (uint32_t i = threadIdx.x; i < kHist; i += blockDim.x) hist[i] = 0u;
-    __syncthreads();
     const uint64_t total = a.N2 ? a.end[a.N2 - 1] : 0;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
-        // the entry: first p with end[p] > i
-        uint64_t lo = 0, hi = a.N2;
-        while (lo < hi) {
-            const uint64_t mid = (lo + hi) >> 1;
-            if (a.end[mid] <= i) lo = mid + 1;
-            else hi = mid;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * kRun; i0 < total; i0 += (uint64_t)gridDim.x * kRun) {
+        const uint64_t i1 = (i0 + kRun) < total ? (i0 + kRun) : total;
+        __syncthreads();  // the previous run's readers of s_end are done
+        if (threadIdx.x == 0) {
+            s_lo = upper_item(a.end, 0, a.N2, i0);
+            s_hi = upper_item(a.end, s_lo, a.N2, i1 - 1) + 1;  // entries [lo, hi) hold the run
         }
-        const uint64_t p = lo;
-        const uint64_t k = a.ck[p];
-        const uint32_t t = a.ct[p];
-        const uint32_t u = hi32(k), v = lo32(k);
-        const uint32_t su = a.off[u], du = a.off[u + 1] - su, sv = a.off[v], dv = a.off[v + 1] - sv;
-        const uint64_t j = i - (p ? a.end[p - 1] : 0);
-        // A: the shorter list (ties: u's), B: the other
-        const bool au = du <= dv;
-        const uint32_t sa = au ? su : sv;
-        const uint32_t sb = au ? sv : su, db = au ? dv : du, b = au ? v : u;
-        const uint32_t ta = a.tim[sa + j];
-        if (ta >= t) continue;  // {x, w} arrived at or after (u, v): not yet in any set
-        const uint32_t w = lo32(a.key[sa + j]);
-        const uint64_t want = ((uint64_t)b << 32) | w;
-        const uint64_t q = lower_bound64(a.key, sb, (uint64_t)sb + db, want);
-        if (q >= (uint64_t)sb + db || a.key[q] != want || a.tim[q] >= t) continue;
-        // triangle {u, v, w} with last edge (u, v): per group, the processor that stored both
-        // {u, w} and {v, w}, if one did
-        for (uint32_t g = 0; g < a.G; ++g) {
-            const uint64_t* c4 = a.hp + 4 * g;
-            const uint32_t s1 = rept_hash::slot_of(c4, a.m, u, w);
-            const uint32_t s2 = rept_hash::slot_of(c4, a.m, v, w);
-            const uint32_t active = (g + 1 < a.G) ? a.ck_full : a.last_ck;
-            if (s1 != s2 || s1 >= active) continue;
-            const uint32_t proc = g * a.pstride + s1;
-            if (use_hist) atomicAdd(&hist[proc], 1u);
-            else atomicAdd((unsigned long long*)a.global + proc, 1ull);
-            int64_t* row = a.local + (uint64_t)(a.per_proc ? proc : g) * a.n;
-            atomicAdd((unsigned long long*)row + u, 1ull);
-            atomicAdd((unsigned long long*)row + v, 1ull);
-            atomicAdd((unsigned long long*)row + w, 1ull);
+        __syncthreads();
+        const uint64_t plo = s_lo, phi = s_hi;
+        const bool staged = phi - plo <= kStage;
+        if (staged)
+            for (uint64_t k = threadIdx.x; k < phi - plo; k += blockDim.x) s_end[k] = a.end[plo + k];
+        __syncthreads();
+        for (uint64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+            uint64_t p;
+            if (staged) {
+                uint32_t lo = 0, hi = (uint32_t)(phi - plo);
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (s_end[mid] <= i) lo = mid + 1;
+                    else hi = mid;
+                }
+                p = plo + lo;
+            } else {
+                p = upper_item(a.end, plo, phi, i);
+            }
+            const uint64_t k = a.ck[p];
+            const uint32_t t = a.ct[p];
+            const uint32_t u = hi32(k), v = lo32(k);
+            const uint32_t su = a.off[u], du = a.off[u + 1] - su, sv = a.off[v], dv = a.off[v + 1] - sv;
+            const uint64_t before = p ? (staged && p > plo ? s_end[p - 1 - plo] : a.end[p - 1]) : 0;
+            const uint64_t j = i - before;
+            // A: the shorter list (ties: u's), B: the other
+            const bool au = du <= dv;
+            const uint32_t sa = au ? su : sv;
+            const uint32_t sb = au ? sv : su, db = au ? dv : du, b = au ? v : u;
+            const uint32_t ta = a.tim[sa + j];
+            if (ta >= t) continue;  // {x, w} arrived at or after (u, v): not yet in any set
+            const uint32_t w = lo32(a.key[sa + j]);
+            const uint64_t want = ((uint64_t)b << 32) | w;
+            const uint64_t q = lower_bound64(a.key, sb, (uint64_t)sb + db, want);
+            if (q >= (uint64_t)sb + db || a.key[q] != want || a.tim[q] >= t) continue;
+            // triangle {u, v, w} with last edge (u, v): per group, the processor that stored both
+            // {u, w} and {v, w}, if one did
+            for (uint32_t g = 0; g < a.G; ++g) {
+                const uint64_t* c4 = a.hp + 4 * g;
+                const uint32_t s1 = rept_hash::slot_of(c4, a.m, u, w);
+                const uint32_t s2 = rept_hash::slot_of(c4, a.m, v, w);
+                const uint32_t active = (g + 1 < a.G) ? a.ck_full : a.last_ck;
+                if (s1 != s2 || s1 >= active) continue;
+                const uint32_t proc = g * a.pstride + s1;
+                if (use_hist) atomicAdd(&hist[proc], 1u);
+                else atomicAdd((unsigned long long*)a.global + proc, 1ull);
+                int64_t* row = a.local + (uint64_t)(a.per_proc ? proc : g) * a.n;
+                atomicAdd((unsigned long long*)row + u, 1ull);
+                atomicAdd((unsigned long long*)row + v, 1ull);
+                atomicAdd((unsigned long long*)row + w, 1ull);
+            }
         }
     }
     if (use_hist) {
