@@ -53,9 +53,13 @@ bool is_mascot(const rept_params* p) { return (p->flags & REPT_MASCOT) != 0; }
 // hash groups: ceil(c/m) for REPT; one per processor for parallel MASCOT
 uint32_t groups_of(const rept_params* p) { return is_mascot(p) ? p->c : (p->c + p->m - 1) / p->m; }
 
-// bytes of the slot table of a graph's stored edges for G groups
-size_t table_bytes(const rept_graph* g, uint32_t G) {
-    const size_t b = (size_t)g->E * rept_slot_stride(G) * sizeof(uint16_t);
+// 16-bit words per stored edge in the slot table: one slot per group (padded to 1, 2, 4, 8),
+// or for parallel MASCOT one keep mask (bit k: processor k keeps the edge)
+uint32_t table_stride(const rept_params* p) { return is_mascot(p) ? 1u : rept_slot_stride(groups_of(p)); }
+
+// bytes of the slot table of a graph's stored edges
+size_t table_bytes(const rept_graph* g, const rept_params* p) {
+    const size_t b = (size_t)g->E * table_stride(p) * sizeof(uint16_t);
     return b < 256 ? 256 : (b + 255) & ~(size_t)255;
 }
 
@@ -195,7 +199,7 @@ rept_status make_job(const rept_job& jb, JobDev* d, uint64_t* zero_words) {
     const uint32_t G = groups_of(&jb.params);
     if (G > REPT_GMAX || jb.params.m > 65536) return REPT_ENOTSUP;  // slots are staged as 16-bit
     if (!jb.workspace || ((uintptr_t)jb.workspace & 255u)) return REPT_EINVAL;
-    if (jb.workspace_bytes < table_bytes(g, G)) return REPT_ENOMEM;
+    if (jb.workspace_bytes < table_bytes(g, &jb.params)) return REPT_ENOMEM;
     memset(d, 0, sizeof(*d));
     d->off = g->off;
     d->nbr = g->nbr;
@@ -231,7 +235,8 @@ rept_status make_job(const rept_job& jb, JobDev* d, uint64_t* zero_words) {
     if (jb.unit0 > u1) return REPT_EINVAL;
     d->unit0 = jb.unit0;
     d->unit1 = u1;
-    d->gs = rept_slot_stride(G);
+    d->gs = table_stride(&jb.params);
+    d->mask = is_mascot(&jb.params) ? 1u : 0u;
     d->tab = (uint16_t*)jb.workspace;
     d->fill = (jb.flags & REPT_JOB_TABLE_READY) ? 0u : 1u;
     *zero_words = (uint64_t)d->c + (uint64_t)d->rows * d->n;
@@ -346,7 +351,7 @@ rept_status rept_count_workspace_size(const rept_graph* graph, const rept_params
     if (!valid_graph(graph) || !params_ok(params) || !bytes) return REPT_EINVAL;
     const uint32_t G = groups_of(params);
     if (G > REPT_GMAX || params->m > 65536) return REPT_ENOTSUP;
-    *bytes = table_bytes(graph, G);
+    *bytes = table_bytes(graph, params);
     return REPT_OK;
 }
 
@@ -514,7 +519,7 @@ rept_status rept_count_eta_workspace_size(const rept_graph* graph, const rept_pa
     const uint32_t G = groups_of(params);
     if (G > REPT_GMAX) return REPT_ENOTSUP;
     const size_t pairs = (size_t)8 * G * graph->E;
-    *bytes = table_bytes(graph, G) + ((pairs + 255) & ~(size_t)255);
+    *bytes = table_bytes(graph, params) + ((pairs + 255) & ~(size_t)255);
     return REPT_OK;
 }
 
@@ -542,13 +547,13 @@ rept_status rept_count_eta(const rept_graph* graph, const rept_params* params, i
     jb.unit0 = 0;
     jb.unit1 = UINT32_MAX;
     jb.workspace = workspace;
-    jb.workspace_bytes = table_bytes(graph, G);
+    jb.workspace_bytes = table_bytes(graph, params);
     JobDev d;
     uint64_t zw = 0;
     st = make_job(jb, &d, &zw);
     if (st != REPT_OK) return st;
     d.es = (uint32_t)graph->E;
-    d.pairs = (uint32_t*)((uint8_t*)workspace + table_bytes(graph, G));
+    d.pairs = (uint32_t*)((uint8_t*)workspace + table_bytes(graph, params));
     BatchHeader h;
     st = make_header(1, d.G, d.c, graph->max_out, zw, true, tuning, &h, true);
     if (st != REPT_OK) return st;

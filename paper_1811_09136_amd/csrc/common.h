@@ -78,6 +78,7 @@ struct JobDev {
     uint32_t* pairs;             // Algorithm 2 pair counters [G][es][2] (s, L), or null
     uint32_t ck, last_ck;        // active slots of a full group and of the last group
     uint32_t pstride;            // processor of slot j of group k: k * pstride + j
+    uint32_t mask;               // 1: the table holds keep masks (parallel MASCOT), gs = 1
 };
 
 // Work queues of the counting kernel: each phase's tiles are split over kQueues interleaved

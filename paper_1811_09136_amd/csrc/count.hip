@@ -219,7 +219,7 @@ struct JobRegs {
     int64_t* local;
     const uint16_t* tab;  // slot table of the stored edges, gs slots per edge
     uint32_t* pairs;      // Algorithm 2 pair counters [G][es][2], or null
-    uint32_t n, m, c, G, gs, per_proc, t0, t1, ck, last_ck, pstride, use_hist, es;
+    uint32_t n, m, c, G, gs, per_proc, t0, t1, ck, last_ck, pstride, use_hist, es, mask;
 };
 
 __device__ inline void load_job(const JobDev* __restrict__ j, uint32_t HC, JobRegs& r) {
@@ -246,6 +246,7 @@ __device__ inline void load_job(const JobDev* __restrict__ j, uint32_t HC, JobRe
     r.ck = j->ck;
     r.last_ck = j->last_ck;
     r.pstride = j->pstride;
+    r.mask = j->mask;
     r.use_hist = (HC != 0 && j->c <= HC) ? 1u : 0u;
 }
 
@@ -451,6 +452,27 @@ __device__ void drain_hits_t(const JobRegs& J, const TeamView& T, const WaveView
             // slot rows of the first two edges; the groups where their slots agree, all at once
             const uint64_t xlo = last == 0 ? wlo : alo, xhi = last == 0 ? whi : ahi;
             const uint64_t ylo = last == 2 ? wlo : blo, yhi = last == 2 ? whi : bhi;
+            if (GS == 1 && J.mask) {
+                // parallel MASCOT: the processors that kept both earlier edges
+                uint32_t mm = (uint32_t)(xlo & ylo) & ((1u << J.G) - 1u);
+                if (!(tl >= J.t0 && tl < J.t1)) mm = 0;
+                while (mm) {
+                    const uint32_t g = (uint32_t)__builtin_ctz(mm);  // processor g, its own group
+                    mm &= mm - 1u;
+                    if (J.use_hist) atomicAdd(&V.hist[g], 1u);
+                    else add64(J.global + g, 1);
+                    if (J.per_proc) {
+                        int64_t* row = J.local + (uint64_t)g * J.n;
+                        add64(row + a, 1);
+                        add64(row + b, 1);
+                        add64(row + w, 1);
+                    } else {
+                        atomicAdd(&T.cntb[g * T.DB + ib], 1u);
+                        atomicAdd(&T.cntw[g * T.DW + k], 1u);
+                    }
+                }
+                continue;
+            }
             uint64_t glo, ghi;
             group_masks(J.G, glo, ghi);
             if (!(tl >= J.t0 && tl < J.t1)) glo = ghi = 0;
@@ -941,9 +963,15 @@ __global__ void __launch_bounds__(256) k_fill(const JobDev* __restrict__ jobs) {
                 }
                 const uint32_t b = w0 + lo, w = ldg(nbr + p);
                 uint32_t wd[4] = {0u, 0u, 0u, 0u};
+                if (J.mask) {  // parallel MASCOT: bit g = processor g keeps the edge (h_g = 0)
 #pragma unroll
-                for (uint32_t g = 0; g < REPT_GMAX; ++g)
-                    if (g < G) wd[g >> 1] |= slot_of(cf + 4 * g, m, b, w) << (16 * (g & 1));
+                    for (uint32_t g = 0; g < REPT_GMAX; ++g)
+                        if (g < G) wd[0] |= (slot_of(cf + 4 * g, m, b, w) == 0u ? 1u : 0u) << g;
+                } else {
+#pragma unroll
+                    for (uint32_t g = 0; g < REPT_GMAX; ++g)
+                        if (g < G) wd[g >> 1] |= slot_of(cf + 4 * g, m, b, w) << (16 * (g & 1));
+                }
                 if (gs == 1) tab[p] = (uint16_t)wd[0];
                 else if (gs == 2) ((uint32_t*)tab)[p] = wd[0];
                 else if (gs == 4) ((uint2*)tab)[p] = make_uint2(wd[0], wd[1]);
