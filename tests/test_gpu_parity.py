@@ -62,7 +62,8 @@ def test_config1_parity(cuda):
 
 
 @pytest.mark.parametrize("m,c,per_proc", [(1, 1, False), (2, 2, False), (3, 7, False), (10, 40, False),
-                                          (4, 4, True), (5, 12, True), (2, 16, False)])
+                                          (4, 4, True), (5, 12, True), (2, 16, False), (20, 150, False),
+                                          (300, 1500, False), (17, 34, True), (257, 300, False)])
 def test_random_graphs(cuda, m, c, per_proc):
     e = synth.er(300, 3000, 11 + m, 12 + c)
     _say(f"ER n=300 E=3000 m={m} c={c} per_proc={per_proc}")
