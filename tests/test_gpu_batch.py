@@ -94,11 +94,18 @@ def test_graph_capture_replays(cuda):
     ref = [(j.out[0].clone(), j.out[1].clone()) for j in jobs]
     _say("capture + 3 replays")
     b.capture()
+    # an eager batch of the same graphs with other outputs, launched between the replays (it
+    # forks onto the library's second stream as the captured launch does)
+    import dataclasses
+    other = Batch([dataclasses.replace(j, out=None, workspace=None, table_ready=False) for j in jobs])
     for r in range(3):
         for j in jobs:  # eager work in between: scribble over the outputs
             j.out[0].fill_(-7)
             j.out[1].fill_(-7)
+        other.launch()
         torch.cuda.synchronize()
+        for o, (rg, rl) in zip(other.jobs, ref):
+            assert torch.equal(o.out[0], rg) and torch.equal(o.out[1], rl), f"eager batch {r}"
         b.replay()
         torch.cuda.synchronize()
         for j, (rg, rl) in zip(jobs, ref):
