@@ -61,15 +61,16 @@ typedef enum rept_status {
 /* Parallel MASCOT (Section III-C): each of the c processors keeps every edge independently with
  * probability 1/m (processor i keeps e iff h_i(e) = 0, h_i the hash of group i), so the samples
  * overlap instead of partitioning the stream; the counting step is Algorithm 1's.  Processors
- * are their own groups (c <= 8 per call; independent seeds give further processors), the local
- * output has c rows, and the estimator is the mean of the processors' m^2 tau^(i), that is
+ * are their own groups, the local output has c rows, and the estimator is the mean of the processors' m^2 tau^(i), that is
  * (m^2 / c) sum_i tau^(i) for any c.  Not with rept_count_eta / rept_estimate_combined. */
 #define REPT_MASCOT 2u
 
 /* REPT sampling parameters (Table I: p = 1/m, c processors; plus the hash seed). */
 typedef struct rept_params {
     uint32_t m;     /* 1/p, 1 <= m <= 65536 (m = 1 counts every triangle once per group) */
-    uint32_t c;     /* processors, 1 <= c <= 8*m (at most 8 hash groups); c <= 8 with REPT_MASCOT */
+    uint32_t c;     /* processors, c >= 1; G = ceil(c/m) hash groups (c with REPT_MASCOT).  rept_count and
+                       rept_count_range take any G; the batched, Algorithm 2 and incremental calls
+                       take G <= 8 */
     uint64_t seed;  /* seed of the hash parameters */
     uint32_t flags; /* REPT_LOCAL_PER_PROC, REPT_MASCOT, both, or 0 */
     uint32_t reserved; /* must be 0 */
@@ -147,8 +148,9 @@ rept_status rept_graph_get_info(const rept_graph* graph, rept_graph_info* info);
 /*
  * Device bytes of the workspace of one count of `graph` under `params`: the slot table of the
  * graph's stored edges, h_k(e) for every edge e and group k (Section III-A's hash, one per group
- * as in Section III-B), 16 bits per slot with the groups padded to 1, 2, 4 or 8 per edge,
- * rounded up to 256 bytes.  Host only.  Errors: EINVAL; ENOTSUP (more than 8 groups, m > 65536).
+ * as in Section III-B), 16 bits per slot with the groups padded to 1, 2, 4 or 8 per edge (more
+ * than 8 groups: the table of the 8 one launch counts), rounded up to 256 bytes.  Host only.
+ * Errors: EINVAL; ENOTSUP (m > 65536).
  */
 rept_status rept_count_workspace_size(const rept_graph* graph, const rept_params* params,
                                       size_t* bytes);
@@ -162,8 +164,11 @@ rept_status rept_count_workspace_size(const rept_graph* graph, const rept_params
  *   workspace: device, >= rept_count_workspace_size bytes, 256-byte aligned; the call rewrites it
  *              (the slot table) and reads it; it may be reused once the call's work on `stream`
  *              has completed.
- * Asynchronous on `stream`.  Errors: EINVAL, ENOMEM (workspace too small), ENOTSUP (more than 8
- * groups or m > 65536), EDEVICE.
+ * More than 8 groups run as successive launches of at most 8 groups on `stream` (groups are
+ * independent; each launch uses its groups' own hash coefficients of `seed` and writes its slice
+ * of the outputs), so the results equal a single pass over all groups.
+ * Asynchronous on `stream`.  Errors: EINVAL, ENOMEM (workspace too small), ENOTSUP (m > 65536),
+ * EDEVICE.
  */
 rept_status rept_count(const rept_graph* graph, const rept_params* params, int64_t* global,
                        int64_t* local, void* workspace, size_t workspace_bytes, void* stream);

@@ -33,9 +33,11 @@ struct SplitMix64 {
     }
 };
 
-void group_params(uint64_t seed, uint32_t G, uint64_t* hp) {
+// the coefficients of groups k0 .. k0 + G - 1: SplitMix64 outputs 4 k0 .. 4 (k0 + G) - 1
+void group_params(uint64_t seed, uint32_t G, uint64_t* hp, uint32_t k0 = 0) {
     const uint64_t p61 = (1ull << 61) - 1;
     SplitMix64 r{seed};
+    for (uint64_t q = 0; q < 4ull * k0; ++q) (void)r.next();
     for (uint32_t q = 0; q < 4 * G; ++q) {
         uint64_t v = r.next() >> 3;  // < 2^61 = p61 + 1
         hp[q] = v == p61 ? 0 : v;
@@ -243,35 +245,61 @@ rept_status make_job(const rept_job& jb, JobDev* d, uint64_t* zero_words) {
     return REPT_OK;
 }
 
+// One counting pass.  More than REPT_GMAX groups run as successive launches of at most that
+// many (groups are independent): launch q counts groups 8q .. 8q + 7 with their own hash
+// coefficients into its slice of the outputs, so the results equal one launch over all groups.
 rept_status count_one(const rept_graph* graph, const rept_params* params, uint64_t t0, uint64_t t1,
                       bool accumulate, int64_t* global, int64_t* local, void* workspace, size_t workspace_bytes,
                       void* stream) {
     if (!valid_graph(graph) || !params_ok(params) || !global || !local) return REPT_EINVAL;
     if (t0 > t1 || t1 > graph->E) return REPT_EINVAL;
-    if (groups_of(params) > REPT_GMAX || params->m > 65536) return REPT_ENOTSUP;
-    rept_job jb;
-    memset(&jb, 0, sizeof(jb));
-    jb.graph = graph;
-    jb.params = *params;
-    jb.global = global;
-    jb.local = local;
-    jb.t0 = t0;
-    jb.t1 = t1;
-    jb.unit0 = 0;
-    jb.unit1 = UINT32_MAX;
-    jb.flags = accumulate ? REPT_JOB_ACCUMULATE : 0u;
-    jb.workspace = workspace;
-    jb.workspace_bytes = workspace_bytes;
-    JobDev d;
-    uint64_t zw = 0;
-    rept_status st = make_job(jb, &d, &zw);
-    if (st != REPT_OK) return st;
-    BatchHeader h;
-    st = make_header(1, d.G, d.c, graph->max_out, zw, !accumulate, nullptr, &h);
-    if (st != REPT_OK) return st;
-    h.any_fill = 1;
-    h.fill_edges = graph->E > UINT32_MAX ? UINT32_MAX : (uint32_t)graph->E;
-    if (rept_launch_single(graph->ctrl, h, d, (hipStream_t)stream) != hipSuccess) return REPT_EDEVICE;
+    if (params->m > 65536) return REPT_ENOTSUP;
+    const uint32_t G = groups_of(params), m = params->m, n = graph->n;
+    const bool mascot = is_mascot(params), per_proc = (params->flags & REPT_LOCAL_PER_PROC) != 0;
+    // every pass's arguments are checked (check = 0) before the first launch (check = 1)
+    const uint32_t passes = (G + REPT_GMAX - 1) / REPT_GMAX;
+    for (uint32_t check = 0; check < 2; ++check) {
+        for (uint32_t q = 0; q < passes; ++q) {
+            const uint32_t k0 = q * REPT_GMAX, Gq = (G - k0) < REPT_GMAX ? (G - k0) : REPT_GMAX;
+            rept_params pp = *params;
+            uint64_t goff, loff;
+            if (mascot) {  // processors k0 .. k0 + Gq - 1, one group and one local row each
+                pp.c = Gq;
+                goff = k0;
+                loff = (uint64_t)k0 * n;
+            } else {  // the groups' processors k0 m .. ; the last group may be partial
+                const uint64_t left = (uint64_t)params->c - (uint64_t)k0 * m;
+                pp.c = (uint32_t)(left < (uint64_t)Gq * m ? left : (uint64_t)Gq * m);
+                goff = (uint64_t)k0 * m;
+                loff = per_proc ? (uint64_t)k0 * m * n : (uint64_t)k0 * n;
+            }
+            rept_job jb;
+            memset(&jb, 0, sizeof(jb));
+            jb.graph = graph;
+            jb.params = pp;
+            jb.global = global + goff;
+            jb.local = local + loff;
+            jb.t0 = t0;
+            jb.t1 = t1;
+            jb.unit0 = 0;
+            jb.unit1 = UINT32_MAX;
+            jb.flags = accumulate ? REPT_JOB_ACCUMULATE : 0u;
+            jb.workspace = workspace;
+            jb.workspace_bytes = workspace_bytes;
+            JobDev dq;
+            uint64_t zw = 0;
+            rept_status st = make_job(jb, &dq, &zw);
+            if (st != REPT_OK) return st;
+            group_params(params->seed, dq.G, dq.hp, k0);  // this pass's groups of the whole seed
+            BatchHeader h;
+            st = make_header(1, dq.G, dq.c, graph->max_out, zw, !accumulate, nullptr, &h);
+            if (st != REPT_OK) return st;
+            if (!check) continue;
+            h.any_fill = 1;
+            h.fill_edges = graph->E > UINT32_MAX ? UINT32_MAX : (uint32_t)graph->E;
+            if (rept_launch_single(graph->ctrl, h, dq, (hipStream_t)stream) != hipSuccess) return REPT_EDEVICE;
+        }
+    }
     return REPT_OK;
 }
 
@@ -349,8 +377,7 @@ rept_status rept_graph_get_info(const rept_graph* g, rept_graph_info* info) {
 
 rept_status rept_count_workspace_size(const rept_graph* graph, const rept_params* params, size_t* bytes) {
     if (!valid_graph(graph) || !params_ok(params) || !bytes) return REPT_EINVAL;
-    const uint32_t G = groups_of(params);
-    if (G > REPT_GMAX || params->m > 65536) return REPT_ENOTSUP;
+    if (params->m > 65536) return REPT_ENOTSUP;  // more than 8 groups: the table of one launch
     *bytes = table_bytes(graph, params);
     return REPT_OK;
 }

@@ -116,12 +116,16 @@ def test_mascot_and_rept_jobs_in_one_batch(cuda):
 
 
 def test_mascot_limits(cuda):
+    """More than 8 processors run as several launches in one call; the pair counters of
+    Algorithm 2 are not defined for MASCOT."""
     from paper_1811_09136_amd import rept
-    e = synth.er(50, 200, 1, 2)
-    g = rept.Graph(rept.to_device_edges(e, cuda), 50)
-    with pytest.raises(rept.ReptError) as ei:
-        g.count(rept.Params(10, 9, 1, mascot=True))  # nine independent hashes in one call
-    assert ei.value.code == rept.REPT_ENOTSUP
+    e = synth.er(300, 3000, 1, 2)
+    g = rept.Graph(rept.to_device_edges(e, cuda), 300)
+    for m, c in [(10, 9), (3, 20)]:
+        _say(f"mascot n=300 E=3000 m={m} c={c} (launches of 8 processors)")
+        glob, loc = g.count(rept.Params(m, c, 1, mascot=True))
+        og, ol = oracle.mascot(e, 300, m, c, 1)
+        assert np.array_equal(glob.cpu().numpy(), og) and np.array_equal(loc.cpu().numpy(), ol)
     with pytest.raises(rept.ReptError) as ei:
         g.count_eta(rept.Params(2, 3, 1, mascot=True))
     assert ei.value.code == rept.REPT_ENOTSUP

@@ -379,3 +379,30 @@ def test_build_from_host_stream(cuda):
     with pytest.raises(rept.ReptError) as ei:
         rept.rept_build_host(n, e, P.data_ptr(), pb - 256, S.data_ptr(), sb, sp)
     assert ei.value.code == rept.REPT_ENOMEM
+
+
+@pytest.mark.parametrize("m,c,per_proc", [(2, 40, False), (3, 29, False), (2, 33, True), (10, 320, False)])
+def test_more_than_eight_groups(cuda, m, c, per_proc):
+    """Counts with more than 8 hash groups run as successive launches of 8 groups (the last
+    group may be partial): every counter equals the oracle's, also over a stream window."""
+    import torch
+    from paper_1811_09136_amd import rept
+    e = synth.er(300, 3000, 51 + m, 52 + c)
+    _say(f"ER n=300 E=3000 m={m} c={c} per_proc={per_proc} groups={-(-c // m)}")
+    got = _run(cuda, e, 300, m, c, 7 + c, per_proc=per_proc)
+    og, ol = _check(e, 300, m, c, 7 + c, got, per_proc=per_proc)
+    assert og.sum() > 0
+    p = rept.Params(m, c, 7 + c, per_proc)
+    g = rept.Graph(rept.to_device_edges(e, cuda), 300)
+    out = g.outputs(p)
+    out[0].zero_()
+    out[1].zero_()
+    g.count_range(p, 1000, 2500, out)
+    torch.cuda.synchronize()
+    wg, wl = oracle.rept(e, 300, m, c, 7 + c, per_proc=per_proc, t0=1000, t1=2500)
+    assert np.array_equal(out[0].cpu().numpy(), wg) and np.array_equal(out[1].cpu().numpy(), wl)
+    if c % m == 0:  # (c mod m != 0 takes Algorithm 2's estimator, at most 8 groups)
+        th, tv = rept.rept_estimate(300, p, out[0].cpu().numpy(), out[1].cpu().numpy())
+        oth, otv = oracle.estimate(300, m, c, wg, wl)
+        assert th == oth and np.array_equal(tv.view(np.uint64), otv.view(np.uint64))
+    g.close()
