@@ -68,9 +68,9 @@ typedef enum rept_status {
 /* REPT sampling parameters (Table I: p = 1/m, c processors; plus the hash seed). */
 typedef struct rept_params {
     uint32_t m;     /* 1/p, 1 <= m <= 65536 (m = 1 counts every triangle once per group) */
-    uint32_t c;     /* processors, c >= 1; G = ceil(c/m) hash groups (c with REPT_MASCOT).  rept_count and
-                       rept_count_range take any G; the batched, Algorithm 2 and incremental calls
-                       take G <= 8 */
+    uint32_t c;     /* processors, c >= 1; G = ceil(c/m) hash groups (c with REPT_MASCOT).  rept_count,
+                       rept_count_range and rept_count_eta take any G; the batched and incremental
+                       calls take G <= 8 */
     uint64_t seed;  /* seed of the hash parameters */
     uint32_t flags; /* REPT_LOCAL_PER_PROC, REPT_MASCOT, both, or 0 */
     uint32_t reserved; /* must be 0 */
@@ -209,8 +209,9 @@ rept_status rept_estimate_sums(uint32_t n, const rept_params* params, const int6
 
 /*
  * Device bytes of the workspace of rept_count_eta: the slot table of rept_count_workspace_size,
- * then two uint32 counters per stored edge and group (the per-edge counts below), rounded up to
- * 256 bytes.  Host only.  Errors: EINVAL; ENOTSUP (more than 8 groups, m > 65536).
+ * then two uint32 counters per stored edge and group of one launch (at most 8 groups; the
+ * per-edge counts below), rounded up to 256 bytes.  Host only.  Errors: EINVAL; ENOTSUP
+ * (m > 65536).
  */
 rept_status rept_count_eta_workspace_size(const rept_graph* graph, const rept_params* params,
                                           size_t* bytes);
@@ -233,8 +234,9 @@ rept_status rept_count_eta_workspace_size(const rept_graph* graph, const rept_pa
  *   tuning:    launch shape (rept_tuning, below) or NULL for the default shape; a shape that
  *              does not fit the LDS is EINVAL.
  * The combined estimator (rept_estimate_combined) takes the sums of row 0.  Any c is
- * accepted.  Asynchronous on `stream`.  Errors: EINVAL, ENOMEM (workspace too small), ENOTSUP
- * (more than 8 groups or m > 65536), EDEVICE.
+ * accepted; more than 8 groups run as launches of 8 groups as in rept_count, each adding its
+ * processors' pair counts.  Asynchronous on `stream`.  Errors: EINVAL, ENOMEM (workspace too
+ * small), ENOTSUP (REPT_MASCOT, m > 65536), EDEVICE.
  */
 struct rept_tuning;
 rept_status rept_count_eta(const rept_graph* graph, const rept_params* params, int64_t* global,

@@ -543,9 +543,9 @@ rept_status rept_reduce_local(const int64_t* local, uint32_t rows, uint32_t n, i
 
 rept_status rept_count_eta_workspace_size(const rept_graph* graph, const rept_params* params, size_t* bytes) {
     if (!valid_graph(graph) || !params_ok(params) || !bytes) return REPT_EINVAL;
-    const uint32_t G = groups_of(params);
-    if (G > REPT_GMAX) return REPT_ENOTSUP;
-    const size_t pairs = (size_t)8 * G * graph->E;
+    if (params->m > 65536) return REPT_ENOTSUP;
+    const uint32_t G = groups_of(params), Gl = G < REPT_GMAX ? G : REPT_GMAX;  // groups of one launch
+    const size_t pairs = (size_t)8 * Gl * graph->E;
     *bytes = table_bytes(graph, params) + ((pairs + 255) & ~(size_t)255);
     return REPT_OK;
 }
@@ -556,42 +556,60 @@ rept_status rept_count_eta(const rept_graph* graph, const rept_params* params, i
     if (!valid_graph(graph) || !params_ok(params) || !global || !local || !eta) return REPT_EINVAL;
     if (((uintptr_t)eta | (uintptr_t)eta_v) & 7u) return REPT_EINVAL;
     if (is_mascot(params)) return REPT_ENOTSUP;
-    const uint32_t G = groups_of(params);
-    if (G > REPT_GMAX || params->m > 65536) return REPT_ENOTSUP;
+    if (params->m > 65536) return REPT_ENOTSUP;
     size_t need = 0;
     rept_status st = rept_count_eta_workspace_size(graph, params, &need);
     if (st != REPT_OK) return st;
     if (!workspace || ((uintptr_t)workspace & 255u)) return REPT_EINVAL;
     if (workspace_bytes < need) return REPT_ENOMEM;
-    rept_job jb;
-    memset(&jb, 0, sizeof(jb));
-    jb.graph = graph;
-    jb.params = *params;
-    jb.global = global;
-    jb.local = local;
-    jb.t0 = 0;
-    jb.t1 = graph->E;
-    jb.unit0 = 0;
-    jb.unit1 = UINT32_MAX;
-    jb.workspace = workspace;
-    jb.workspace_bytes = table_bytes(graph, params);
-    JobDev d;
-    uint64_t zw = 0;
-    st = make_job(jb, &d, &zw);
-    if (st != REPT_OK) return st;
-    d.es = (uint32_t)graph->E;
-    d.pairs = (uint32_t*)((uint8_t*)workspace + table_bytes(graph, params));
-    BatchHeader h;
-    st = make_header(1, d.G, d.c, graph->max_out, zw, true, tuning, &h, true);
-    if (st != REPT_OK) return st;
-    h.any_fill = 1;
-    h.fill_edges = graph->E > UINT32_MAX ? UINT32_MAX : (uint32_t)graph->E;
+    // groups in launches of at most 8, as rept_count: launch q counts its groups' processors
+    // into its slice of the outputs and adds their pair counts to eta and eta_v
+    const uint32_t G = groups_of(params), m = params->m, n = graph->n, c = params->c;
+    const bool per_proc = (params->flags & REPT_LOCAL_PER_PROC) != 0;
+    const uint32_t passes = (G + REPT_GMAX - 1) / REPT_GMAX;
+    uint32_t* pairs = (uint32_t*)((uint8_t*)workspace + table_bytes(graph, params));
     hipStream_t s = (hipStream_t)stream;
-    if (rept_launch_zero(d.pairs, (uint64_t)8 * G * graph->E, s) != hipSuccess) return REPT_EDEVICE;
-    if (rept_launch_zero(eta, (uint64_t)16 * params->c, s) != hipSuccess) return REPT_EDEVICE;
-    if (eta_v && rept_launch_zero(eta_v, (uint64_t)16 * graph->n, s) != hipSuccess) return REPT_EDEVICE;
-    if (rept_launch_single(graph->ctrl, h, d, s) != hipSuccess) return REPT_EDEVICE;
-    if (rept_launch_eta(graph, d, eta, eta_v, s) != hipSuccess) return REPT_EDEVICE;
+    for (uint32_t check = 0; check < 2; ++check) {
+        if (check) {
+            if (rept_launch_zero(eta, (uint64_t)16 * c, s) != hipSuccess) return REPT_EDEVICE;
+            if (eta_v && rept_launch_zero(eta_v, (uint64_t)16 * n, s) != hipSuccess) return REPT_EDEVICE;
+        }
+        for (uint32_t q = 0; q < passes; ++q) {
+            const uint32_t k0 = q * REPT_GMAX, Gq = (G - k0) < REPT_GMAX ? (G - k0) : REPT_GMAX;
+            const uint64_t left = (uint64_t)c - (uint64_t)k0 * m;
+            rept_params pp = *params;
+            pp.c = (uint32_t)(left < (uint64_t)Gq * m ? left : (uint64_t)Gq * m);
+            const uint64_t goff = (uint64_t)k0 * m, loff = per_proc ? (uint64_t)k0 * m * n : (uint64_t)k0 * n;
+            rept_job jb;
+            memset(&jb, 0, sizeof(jb));
+            jb.graph = graph;
+            jb.params = pp;
+            jb.global = global + goff;
+            jb.local = local + loff;
+            jb.t0 = 0;
+            jb.t1 = graph->E;
+            jb.unit0 = 0;
+            jb.unit1 = UINT32_MAX;
+            jb.workspace = workspace;
+            jb.workspace_bytes = table_bytes(graph, params);
+            JobDev d;
+            uint64_t zw = 0;
+            st = make_job(jb, &d, &zw);
+            if (st != REPT_OK) return st;
+            group_params(params->seed, d.G, d.hp, k0);
+            d.es = (uint32_t)graph->E;
+            d.pairs = pairs;
+            BatchHeader h;
+            st = make_header(1, d.G, d.c, graph->max_out, zw, true, tuning, &h, true);
+            if (st != REPT_OK) return st;
+            if (!check) continue;
+            h.any_fill = 1;
+            h.fill_edges = graph->E > UINT32_MAX ? UINT32_MAX : (uint32_t)graph->E;
+            if (rept_launch_zero(pairs, (uint64_t)8 * d.G * graph->E, s) != hipSuccess) return REPT_EDEVICE;
+            if (rept_launch_single(graph->ctrl, h, d, s) != hipSuccess) return REPT_EDEVICE;
+            if (rept_launch_eta(graph, d, eta, eta_v, (uint32_t)goff, c, s) != hipSuccess) return REPT_EDEVICE;
+        }
+    }
     return REPT_OK;
 }
 

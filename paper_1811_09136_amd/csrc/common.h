@@ -137,7 +137,10 @@ hipError_t rept_launch_single(uint8_t* ctrl, const BatchHeader& hdr, const JobDe
 // slots per stored edge in a slot table for G groups (1, 2, 4 or 8)
 inline uint32_t rept_slot_stride(uint32_t G) { return G <= 1 ? 1u : (G <= 2 ? 2u : (G <= 4 ? 4u : 8u)); }
 hipError_t rept_launch_zero(void* p, uint64_t bytes, hipStream_t stream);
-hipError_t rept_launch_eta(const rept_graph* g, const JobDev& d, int64_t* eta, int64_t* eta_v, hipStream_t stream);
+// Algorithm 2's pair counts of one launch's processors, added to eta[r][proc0 + i] (rows of
+// `stride` = c entries) and to eta_v
+hipError_t rept_launch_eta(const rept_graph* g, const JobDev& d, int64_t* eta, int64_t* eta_v, uint32_t proc0,
+                           uint32_t stride, hipStream_t stream);
 hipError_t rept_launch_reduce(const int64_t* local, uint32_t rows, uint32_t n, int64_t* sums, hipStream_t stream);
 hipError_t rept_launch_slots(const uint64_t* hp, uint32_t G, uint32_t m, const uint32_t* edges,
                              uint64_t E, uint32_t* slots, hipStream_t stream);

@@ -993,6 +993,7 @@ constexpr uint32_t ETA_PROBES = 16;      // probes before a share goes to global
 __global__ void __launch_bounds__(256) k_eta(const uint32_t* __restrict__ off, const uint32_t* __restrict__ nbr,
                                              uint32_t n, const uint16_t* __restrict__ tab, uint32_t gs, uint32_t G,
                                              uint32_t m, uint32_t c, const uint32_t* __restrict__ pairs, uint32_t es,
+                                             uint32_t proc0, uint32_t stride,
                                              int64_t* __restrict__ eta, int64_t* __restrict__ eta_v) {
     __shared__ uint32_t so[FILL_NODES + 1];
     __shared__ unsigned long long acc[2][ETA_LDS_PROCS];
@@ -1031,8 +1032,8 @@ __global__ void __launch_bounds__(256) k_eta(const uint32_t* __restrict__ off, c
                         atomicAdd(&acc[0][proc], d);
                         atomicAdd(&acc[1][proc], l);
                     } else {
-                        atomicAdd((unsigned long long*)eta + proc, d);
-                        atomicAdd((unsigned long long*)eta + c + proc, l);
+                        atomicAdd((unsigned long long*)eta + proc0 + proc, d);
+                        atomicAdd((unsigned long long*)eta + stride + proc0 + proc, l);
                     }
                     fd += d;
                     fl += l;
@@ -1089,8 +1090,8 @@ __global__ void __launch_bounds__(256) k_eta(const uint32_t* __restrict__ off, c
     __syncthreads();
     if (in_lds) {
         for (uint32_t i = threadIdx.x; i < c; i += 256u) {
-            if (acc[0][i]) atomicAdd((unsigned long long*)eta + i, acc[0][i]);
-            if (acc[1][i]) atomicAdd((unsigned long long*)eta + c + i, acc[1][i]);
+            if (acc[0][i]) atomicAdd((unsigned long long*)eta + proc0 + i, acc[0][i]);
+            if (acc[1][i]) atomicAdd((unsigned long long*)eta + stride + proc0 + i, acc[1][i]);
         }
     }
 }
@@ -1369,13 +1370,14 @@ hipError_t rept_launch_zero(void* p, uint64_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t rept_launch_eta(const rept_graph* g, const JobDev& d, int64_t* eta, int64_t* eta_v, hipStream_t s) {
+hipError_t rept_launch_eta(const rept_graph* g, const JobDev& d, int64_t* eta, int64_t* eta_v, uint32_t proc0,
+                           uint32_t stride, hipStream_t s) {
     (void)hipGetLastError();
     uint64_t blocks = (g->E + FILL_CHUNK - 1) / FILL_CHUNK;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_eta, dim3((uint32_t)blocks), dim3(256), 0, s, g->off, g->nbr, g->n, (const uint16_t*)d.tab,
-                       d.gs, d.G, d.m, d.c, (const uint32_t*)d.pairs, d.es, eta, eta_v);
+                       d.gs, d.G, d.m, d.c, (const uint32_t*)d.pairs, d.es, proc0, stride, eta, eta_v);
     return hipGetLastError();
 }
 

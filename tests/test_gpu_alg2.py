@@ -149,8 +149,24 @@ def test_pair_counter_errors(cuda):
                             need, None, sp)
     assert ei.value.code == rept.REPT_EINVAL
     with pytest.raises(rept.ReptError) as ei:
-        rept.rept_count_eta(g.handle, rept.Params(2, 17, 1), glob.data_ptr(), loc.data_ptr(), eta.data_ptr(), None,
-                            ws.data_ptr(), need, None, sp)
+        rept.rept_count_eta(g.handle, rept.Params(2, 3, 1, mascot=True), glob.data_ptr(), loc.data_ptr(),
+                            eta.data_ptr(), None, ws.data_ptr(), need, None, sp)
     assert ei.value.code == rept.REPT_ENOTSUP
     torch.cuda.synchronize()
     g.close()
+
+
+@pytest.mark.parametrize("m,c,per_proc", [(2, 19, False), (3, 28, True), (2, 35, False)])
+def test_pair_counters_more_than_eight_groups(cuda, m, c, per_proc):
+    """Algorithm 2 with more than 8 hash groups (launches of 8 groups, each adding its pair
+    counts): every counter equals the oracle's, and the combined estimators agree to 0 ulp."""
+    from paper_1811_09136_amd import rept
+    e = synth.er(300, 3000, 61 + m, 62 + c)
+    _say(f"alg2 ER n=300 E=3000 m={m} c={c} per_proc={per_proc} groups={-(-c // m)}")
+    got = _run(cuda, e, 300, m, c, 5 + c, per_proc=per_proc)
+    og, ol, ed, vd = _check(e, 300, m, c, 5 + c, got, per_proc=per_proc)
+    assert ed.sum() > 0
+    p = rept.Params(m, c, 5 + c, per_proc)
+    th, tv = rept.rept_estimate_combined(300, p, got[0], got[1], int(got[2][0].sum()), got[3][0])
+    oth, otv = oracle.estimate2(300, m, c, og, ol, int(ed.sum()), vd, per_proc=per_proc)
+    assert th == oth and np.array_equal(tv.view(np.uint64), otv.view(np.uint64))
