@@ -365,10 +365,11 @@ typedef struct rept_job {
 
 /* Launch shape of the counting kernel; zero fields take the library defaults.  The kernel is
  * persistent: `blocks` workgroups of `threads` threads drain the work queue, first one apex per
- * workgroup (apexes whose out-degree exceeds wave_cap), then one apex per wavefront.  The LDS
+ * workgroup (units whose size exceeds wave_cap), then one unit per wavefront.  The LDS
  * footprint of a shape must fit the 160 KB of a compute unit (EINVAL otherwise). */
 typedef struct rept_tuning {
-    uint32_t wave_cap;   /* 8..256: largest apex list counted by one wavefront (default 64) */
+    uint32_t wave_cap;   /* 8..256: largest unit counted by one wavefront (default 64); a unit's
+                            size is max(its list length, its reverse-list length / 8) */
     uint32_t block_cap;  /* 64..4096: apex entries hashed in LDS per chunk by a workgroup (default:
                             smallest power of two >= the graphs' largest out-degree, at most 2048,
                             halved while a workgroup would need more than half the LDS) */
@@ -377,12 +378,12 @@ typedef struct rept_tuning {
     uint32_t blocks;     /* persistent workgroups (default: as many as fit, up to 4 per CU) */
     uint32_t threads;    /* 64..1024, a multiple of 64 (default 256) */
     uint32_t light_tile; /* 1..64: apexes taken per queue pop by a wavefront (default 8) */
-    uint32_t phase_launches; /* 1: both phases in one launch; 2: the light phase (apexes of at most
-                                wave_cap entries, one per wavefront) runs as a launch of its own
-                                after the heavy one, its workgroups holding no heavy team area in
-                                LDS, so more wavefronts are resident; 0 or 3: that launch on a
-                                second stream of the library's, forked from and joined back to
-                                `stream`, so it runs beside the heavy launch (default) */
+    uint32_t phase_launches; /* 1: both phases in one launch; 2: the light phase (units of at most
+                                wave_cap, one per wavefront) runs as a launch of its own after the
+                                heavy one, its workgroups holding no heavy team area in LDS, so
+                                more wavefronts are resident; 0 or 3: that launch on a second
+                                stream of the library's, forked from and joined back to `stream`,
+                                so it runs beside the heavy launch (default) */
     uint32_t reserved;       /* must be 0 */
 } rept_tuning;
 

@@ -182,7 +182,7 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     const uint32_t pl = tu ? tu->phase_launches : 0u;
     if (pl > 3 || (tu && tu->reserved)) return REPT_EINVAL;
     h->split = pl != 1 ? 1u : 0u;
-    h->split_streams = (pl == 0 || pl == 3) ? 1u : 0u;
+    h->split_streams = (pl == 0 || pl == 3) ? 1u : 0u;  // default (0): two launches, two streams
     if (h->split) {
         h->light_threads = threads;
         h->light_lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table, eta, false);

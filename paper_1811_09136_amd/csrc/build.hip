@@ -353,7 +353,17 @@ __device__ __forceinline__ void node_range(uint32_t n, uint32_t& a0, uint32_t& a
 
 // classify segments by size (sort path), histogram apexes by out-degree for the descending
 // apex order (bucket n-1-d), and the statistics of the oriented graph
-__global__ void __launch_bounds__(SCAN_THREADS) k_classify(const uint32_t* __restrict__ off, uint32_t n,
+// unit order key of node a (REPT_REV_SHIFT), at most n - 1; units are ordered by it, descending,
+// and the counting pass gives a workgroup to the units whose key exceeds its wavefront cap
+__device__ __forceinline__ uint32_t unit_key(const uint32_t* __restrict__ off, const uint32_t* __restrict__ roff,
+                                             uint32_t n, uint32_t a) {
+    const uint32_t d = off[a + 1] - off[a], r = (roff[a + 1] - roff[a]) >> REPT_REV_SHIFT;
+    const uint32_t k = d > r ? d : r;
+    return k < n - 1 ? k : n - 1;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_classify(const uint32_t* __restrict__ off,
+                                                           const uint32_t* __restrict__ roff, uint32_t n,
                                                            uint32_t* ahist, uint32_t* medium,
                                                            uint32_t* large, BuildStats* st) {
     __shared__ uint32_t h[APEX_LDS_BINS];
@@ -370,8 +380,9 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_classify(const uint32_t* __res
         sq += (unsigned long long)d * d;
         mx = d > mx ? d : mx;
         if (d >= 2) {
-            if (d < APEX_LDS_BINS) atomicAdd(&h[d], 1u);
-            else atomicAdd(&ahist[n - 1 - d], 1u);
+            const uint32_t k = unit_key(off, roff, n, a);
+            if (k < APEX_LDS_BINS) atomicAdd(&h[k], 1u);
+            else atomicAdd(&ahist[n - 1 - k], 1u);
             ++napex;
         }
         if (d > SMALL_MAX && d <= MEDIUM_MAX) atomicAdd(&cnt[0], 1u);
@@ -405,7 +416,8 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_classify(const uint32_t* __res
 }
 
 // place apexes in out-degree-descending order: reserve each bin's range once per workgroup
-__global__ void __launch_bounds__(SCAN_THREADS) k_apex_scatter(const uint32_t* __restrict__ off, uint32_t n,
+__global__ void __launch_bounds__(SCAN_THREADS) k_apex_scatter(const uint32_t* __restrict__ off,
+                                                               const uint32_t* __restrict__ roff, uint32_t n,
                                                                const uint32_t* __restrict__ aoff, uint32_t* acur,
                                                                uint32_t* apex) {
     __shared__ uint32_t h[APEX_LDS_BINS];
@@ -415,17 +427,20 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_apex_scatter(const uint32_t* _
     node_range(n, a0, a1);
     for (uint32_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
         const uint32_t d = off[a + 1] - off[a];
-        if (d >= 2 && d < APEX_LDS_BINS) atomicAdd(&h[d], 1u);
+        if (d < 2) continue;
+        const uint32_t k = unit_key(off, roff, n, a);
+        if (k < APEX_LDS_BINS) atomicAdd(&h[k], 1u);
     }
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < APEX_LDS_BINS; d += blockDim.x)
-        if (h[d]) h[d] = aoff[n - 1 - d] + atomicAdd(&acur[n - 1 - d], h[d]);
+    for (uint32_t k = threadIdx.x; k < APEX_LDS_BINS; k += blockDim.x)
+        if (h[k]) h[k] = aoff[n - 1 - k] + atomicAdd(&acur[n - 1 - k], h[k]);
     __syncthreads();
     for (uint32_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
         const uint32_t d = off[a + 1] - off[a];
         if (d < 2) continue;
-        const uint32_t pos = d < APEX_LDS_BINS ? atomicAdd(&h[d], 1u)
-                                               : aoff[n - 1 - d] + atomicAdd(&acur[n - 1 - d], 1u);
+        const uint32_t k = unit_key(off, roff, n, a);
+        const uint32_t pos = k < APEX_LDS_BINS ? atomicAdd(&h[k], 1u)
+                                               : aoff[n - 1 - k] + atomicAdd(&acur[n - 1 - k], 1u);
         apex[pos] = a;
     }
 }
@@ -778,7 +793,7 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     hipLaunchKernelGGL(k_rev_roff, dim3(gN), dim3(256), 0, s, sofs, n, roff, st);
     hipLaunchKernelGGL(k_copy_u32, dim3(gS), dim3(256), 0, s, sofs, nsh, scnt);  // shard cursors
     const RevOut RO{scnt, rrec, rpos};
-    hipLaunchKernelGGL(k_classify, dim3(gA), dim3(256), 0, s, off, n, ahist, medium, large, st);
+    hipLaunchKernelGGL(k_classify, dim3(gA), dim3(256), 0, s, off, roff, n, ahist, medium, large, st);
     hipLaunchKernelGGL(k_sort_small, dim3(grid_for((uint64_t)n, 4, cap * 4)), dim3(256), 0, s, off, n, packed,
                        nbr, tim, RO, st);
     hipLaunchKernelGGL(k_sort_medium, dim3(cus ? cus * 4 : 1024), dim3(512), 0, s, off, medium, packed, nbr,
@@ -789,7 +804,7 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
                        nbr, tim, RO, st);
     if (scan_u32(ahist, n, part, aoff, s) != hipSuccess) return REPT_EDEVICE;
     hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, cursor, (uint64_t)n, 0u);
-    hipLaunchKernelGGL(k_apex_scatter, dim3(gA), dim3(256), 0, s, off, n, aoff, cursor, apex);
+    hipLaunchKernelGGL(k_apex_scatter, dim3(gA), dim3(256), 0, s, off, roff, n, aoff, cursor, apex);
     if (hipGetLastError() != hipSuccess) return REPT_EDEVICE;
 
     BuildStats hs;

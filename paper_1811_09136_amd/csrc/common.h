@@ -7,6 +7,9 @@
 #include "rept.h"
 
 #define REPT_GMAX 8           // hash groups handled by one launch (c <= 8*m)
+// a unit's order key is max(list length, reverse-list length >> REPT_REV_SHIFT): a long reverse
+// list is many lists to walk even under a short own list
+#define REPT_REV_SHIFT 3
 #define REPT_HIST_CAP 1024    // processors aggregated in LDS; larger c uses direct atomics
 #define REPT_CTRL_BYTES 4096  // control block at the head of a graph's persistent buffer
 #define REPT_MAGIC 0x52455054u

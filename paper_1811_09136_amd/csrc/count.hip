@@ -858,12 +858,16 @@ __global__ void __launch_bounds__(1024) k_setup(BatchHeader* hdr, JobDev* jobs) 
         const uint32_t j = j0 + threadIdx.x;
         if (j < nj) {
             JobDev& J = jobs[j];
-            // apexes are sorted by out-degree, descending: the ones above `cap` form a prefix
-            uint32_t lo = 0, hi = J.unit1;  // first index whose out-degree <= cap (unit1 <= num_apex)
+            // units are sorted by key = max(list length, reverse-list length >> REPT_REV_SHIFT), at
+            // most n - 1, descending: the ones above `cap` (a workgroup each) form a prefix
+            uint32_t lo = 0, hi = J.unit1;  // first index whose key <= cap (unit1 <= num_apex)
             while (lo < hi) {
                 const uint32_t mid = (lo + hi) >> 1;
                 const uint32_t a = J.apex[mid];
-                if (J.off[a + 1] - J.off[a] > cap) lo = mid + 1; else hi = mid;
+                const uint32_t d = J.off[a + 1] - J.off[a], r = (J.roff[a + 1] - J.roff[a]) >> REPT_REV_SHIFT;
+                const uint32_t k = d > r ? d : r;
+                const uint32_t key = k < J.n - 1 ? k : J.n - 1;
+                if (key > cap) lo = mid + 1; else hi = mid;
             }
             const uint32_t u0 = J.unit0, u1 = J.unit1;
             const uint32_t hend = u1 < lo ? u1 : lo;
