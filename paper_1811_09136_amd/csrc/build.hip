@@ -233,53 +233,100 @@ __global__ void __launch_bounds__(1024) k_deg_count(const uint32_t* __restrict__
 // increments spread over that many addresses.
 constexpr uint32_t REV_SHARDS = 8;
 
-// out-degree of each lower-ranked endpoint, and each edge's orientation ab[t] = (a, b) from
-// its lower- to its higher-ranked endpoint (NO_EDGE for an invalid edge), so the scatter
-// below need not look the degrees up again
+// an invalid edge's orientation
 constexpr uint32_t NO_EDGE = 0xffffffffu;
-// Both edge passes take EDGE_UNROLL edges per thread per step, one grid stride apart, so the
-// independent scattered loads and atomics of those edges are in flight together.
-constexpr uint32_t EDGE_UNROLL = 4;
-__global__ void __launch_bounds__(256) k_orient_count(const uint2* __restrict__ edges, uint64_t E, uint32_t n,
-                                                      const uint32_t* __restrict__ deg, uint32_t* dout,
-                                                      uint2* __restrict__ ab) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t0 < E; t0 += EDGE_UNROLL * stride) {
-        uint2 e[EDGE_UNROLL];
-        bool ok[EDGE_UNROLL];
-        uint32_t dx[EDGE_UNROLL], dy[EDGE_UNROLL];
-#pragma unroll
-        for (uint32_t u = 0; u < EDGE_UNROLL; ++u) {
-            const uint64_t t = t0 + u * stride;
-            e[u] = t < E ? edges[t] : make_uint2(0u, 0u);
-            ok[u] = t < E && e[u].x < n && e[u].y < n && e[u].x != e[u].y;
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < EDGE_UNROLL; ++u) {
-            dx[u] = ok[u] ? deg[e[u].x] : 0u;
-            dy[u] = ok[u] ? deg[e[u].y] : 0u;
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < EDGE_UNROLL; ++u) {
-            const uint64_t t = t0 + u * stride;
-            if (t >= E) continue;
-            if (!ok[u]) {
-                ab[t] = make_uint2(NO_EDGE, NO_EDGE);
-                continue;
-            }
-            const bool xa = rank_less(e[u].x, dx[u], e[u].y, dy[u]);
-            const uint32_t a = xa ? e[u].x : e[u].y, b = xa ? e[u].y : e[u].x;
-            ab[t] = make_uint2(a, b);
-            atomicAdd(&dout[a], 1u);
-        }
-    }
-}
 
 __global__ void k_copy_u32(const uint32_t* __restrict__ src, uint64_t count, uint32_t* __restrict__ dst) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
 }
 
+// ---- out-degrees without global atomics: each edge is oriented from its lower- to its
+// higher-ranked endpoint and partitioned by the bucket of that lower endpoint a (buckets of
+// 2^shift ids, as for the degrees), and the out-degrees are counted per bucket in LDS.  (A
+// placement per bucket with LDS cursors was tried too: the densest bucket, the top-degree
+// nodes, held 18 times the mean of entries, and one workgroup placing it took 5.5 ms.)
+
+// orientation ab[t] = (a, b) of every edge (NO_EDGE for an invalid one) and the per-workgroup
+// histogram of the lower endpoints' buckets
+__global__ void __launch_bounds__(1024) k_orient_hist(const uint2* __restrict__ edges, uint64_t E, uint32_t n,
+                                                      const uint32_t* __restrict__ deg, uint32_t shift, uint32_t NB,
+                                                      uint64_t per_block, uint2* __restrict__ ab,
+                                                      uint32_t* __restrict__ bhist) {
+    __shared__ uint32_t h[DEG_BUCKETS];
+    for (uint32_t i = threadIdx.x; i < NB; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const uint64_t e0 = (uint64_t)blockIdx.x * per_block;
+    const uint64_t e1 = (e0 + per_block) < E ? (e0 + per_block) : E;
+    for (uint64_t t = e0 + threadIdx.x; t < e1; t += blockDim.x) {
+        const uint2 e = edges[t];
+        if (e.x >= n || e.y >= n || e.x == e.y) {
+            ab[t] = make_uint2(NO_EDGE, NO_EDGE);
+            continue;
+        }
+        const bool xa = rank_less(e.x, deg[e.x], e.y, deg[e.y]);
+        const uint32_t a = xa ? e.x : e.y, b = xa ? e.y : e.x;
+        ab[t] = make_uint2(a, b);
+        atomicAdd(&h[a >> shift], 1u);
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < NB; b += blockDim.x) bhist[(uint64_t)b * gridDim.x + blockIdx.x] = h[b];
+}
+
+// the oriented entries (a, b, t) in bucket order of a (order within a bucket is free)
+__global__ void __launch_bounds__(1024) k_orient_part(const uint2* __restrict__ ab, uint64_t E, uint32_t shift,
+                                                      uint32_t NB, uint64_t per_block,
+                                                      const uint32_t* __restrict__ boff, uint4* __restrict__ opart) {
+    __shared__ uint32_t base[DEG_BUCKETS];
+    for (uint32_t b = threadIdx.x; b < NB; b += blockDim.x) base[b] = boff[(uint64_t)b * gridDim.x + blockIdx.x];
+    __syncthreads();
+    const uint64_t e0 = (uint64_t)blockIdx.x * per_block;
+    const uint64_t e1 = (e0 + per_block) < E ? (e0 + per_block) : E;
+    for (uint64_t t = e0 + threadIdx.x; t < e1; t += blockDim.x) {
+        const uint2 e = ab[t];
+        if (e.x == NO_EDGE) continue;
+        opart[atomicAdd(&base[e.x >> shift], 1u)] = make_uint4(e.x, e.y, (uint32_t)t, 0u);
+    }
+}
+
+// out-degrees: workgroups take fixed slices of the partition and count each bucket's part of
+// the slice in LDS, one atomic per distinct node (`dout` zero on entry)
+__global__ void __launch_bounds__(1024) k_out_count(const uint4* __restrict__ opart,
+                                                    const uint32_t* __restrict__ boff, uint32_t nblk, uint32_t NB,
+                                                    uint32_t shift, uint32_t n, uint32_t* __restrict__ dout) {
+    __shared__ uint32_t cnt[DEG_SUB];
+    const uint32_t total = boff[(uint64_t)NB * nblk];
+    const uint64_t span = (uint64_t)1 << shift;
+    for (uint64_t s0 = (uint64_t)blockIdx.x * DEG_SLICE; s0 < total; s0 += (uint64_t)gridDim.x * DEG_SLICE) {
+        const uint64_t s1 = (s0 + DEG_SLICE) < total ? (s0 + DEG_SLICE) : total;
+        const uint32_t b_first = opart[s0].x >> shift, b_last = opart[s1 - 1].x >> shift;
+        for (uint32_t b = b_first; b <= b_last; ++b) {
+            const uint64_t start = boff[(uint64_t)b * nblk];
+            const uint64_t end = (b + 1 < NB) ? boff[(uint64_t)(b + 1) * nblk] : total;
+            const uint64_t lo = start > s0 ? start : s0, hi = end < s1 ? end : s1;
+            if (lo >= hi) continue;
+            const uint64_t v0 = (uint64_t)b << shift;
+            for (uint64_t r0 = 0; r0 < span && v0 + r0 < n; r0 += DEG_SUB) {
+                for (uint32_t i = threadIdx.x; i < DEG_SUB; i += blockDim.x) cnt[i] = 0;
+                __syncthreads();
+                for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+                    const uint64_t x = (uint64_t)opart[i].x - v0 - r0;
+                    if (x < DEG_SUB) atomicAdd(&cnt[x], 1u);
+                }
+                __syncthreads();
+                for (uint32_t i = threadIdx.x; i < DEG_SUB; i += blockDim.x) {
+                    const uint64_t v = v0 + r0 + i;
+                    if (cnt[i] && v < n) atomicAdd(&dout[v], cnt[i]);
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
+// The placement pass takes EDGE_UNROLL edges per thread per step, one grid stride apart, so the
+// independent scattered loads and atomics of those edges are in flight together.
+constexpr uint32_t EDGE_UNROLL = 4;
 // place every oriented entry in its apex segment (unordered within the segment) as
 // b << 32 | rev << 31 | t, where rev marks a reverse pair (out(a) shorter than out(b); the
 // stream position t is below 2^31, and rev, a function of b within a's segment, leaves the
@@ -611,7 +658,8 @@ struct Layout {
     size_t ctrl, off, nbr, tim, apex, roff, rrec, rpos, total;
 };
 struct ScratchLayout {
-    size_t stats, deg, dout, cursor, ahist, aoff, part, packed, alt, medium, large, bhist, bscan, scnt, sofs, total;
+    size_t stats, deg, dout, cursor, ahist, aoff, part, packed, alt, opart, medium, large, bhist, bscan, scnt, sofs,
+        total;
 };
 
 // partition of endpoints for the degree count: buckets of 2^shift ids, NB <= DEG_BUCKETS of
@@ -681,6 +729,8 @@ ScratchLayout scratch_layout(uint32_t n, uint64_t E) {
     p += align256((size_t)E * 8);
     S.alt = p;
     p += align256((size_t)E * 8);
+    S.opart = p;  // oriented entries (a, b, t) partitioned by the bucket of a
+    p += align256((size_t)E * 16);
     S.medium = p;
     p += align256((size_t)n * 4);
     S.large = p;
@@ -749,6 +799,7 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     uint32_t* part = (uint32_t*)(X + S.part);
     unsigned long long* packed = (unsigned long long*)(X + S.packed);
     unsigned long long* alt = (unsigned long long*)(X + S.alt);
+    uint4* opart = (uint4*)(X + S.opart);
     uint32_t* medium = (uint32_t*)(X + S.medium);
     uint32_t* large = (uint32_t*)(X + S.large);
     uint32_t* bhist = (uint32_t*)(X + S.bhist);
@@ -779,14 +830,23 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     hipLaunchKernelGGL(k_deg_count, dim3(grid_for(2 * E, DEG_SLICE, 4096)), dim3(1024), 0, s, ends, bscan, D.nblk,
                        D.NB, D.shift, n, deg);
 
-    // orientation of every edge into `alt` (free until the large-segment sort)
+    // orientation of every edge into `alt` (free until the large-segment sort), partitioned by
+    // the bucket of its lower endpoint into `opart`, whose out-degrees are counted per bucket
+    // with LDS counters (the degree partition's buckets); then the placement in the segments
     uint2* ab = (uint2*)alt;
-    hipLaunchKernelGGL(k_orient_count, dim3(gE), dim3(256), 0, s, e2, E, n, deg, dout, ab);
+    hipLaunchKernelGGL(k_orient_hist, dim3(D.nblk), dim3(1024), 0, s, e2, E, n, deg, D.shift, D.NB, D.per_block,
+                       ab, bhist);
+    if (scan_u32(bhist, (uint64_t)D.NB * D.nblk, part, bscan, s) != hipSuccess) return REPT_EDEVICE;
+    hipLaunchKernelGGL(k_orient_part, dim3(D.nblk), dim3(1024), 0, s, ab, E, D.shift, D.NB, D.per_block, bscan,
+                       opart);
+    hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, dout, (uint64_t)n, 0u);
+    hipLaunchKernelGGL(k_out_count, dim3(grid_for(E, DEG_SLICE, 4096)), dim3(1024), 0, s, opart, bscan, D.nblk, D.NB,
+                       D.shift, n, dout);
     if (scan_u32(dout, n, part, off, s) != hipSuccess) return REPT_EDEVICE;
-    hipLaunchKernelGGL(k_copy_u32, dim3(gN), dim3(256), 0, s, off, (uint64_t)n, cursor);
     const uint64_t nsh = (uint64_t)n * REV_SHARDS;
     const uint32_t gS = grid_for(nsh, 256, cap);
     hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
+    hipLaunchKernelGGL(k_copy_u32, dim3(gN), dim3(256), 0, s, off, (uint64_t)n, cursor);
     hipLaunchKernelGGL(k_scatter, dim3(gE), dim3(256), 0, s, ab, E, dout, cursor, packed, scnt, st);
     // reverse lists: shard starts from k_scatter's counts; the sorts place the records
     if (scan_u32(scnt, nsh, part, sofs, s) != hipSuccess) return REPT_EDEVICE;
