@@ -324,6 +324,131 @@ __global__ void __launch_bounds__(1024) k_out_count(const uint4* __restrict__ op
     }
 }
 
+// ---- placement by slices: each bucket's part of the partition is cut into slices of
+// SLICE_ENTRIES entries, one workgroup each (the densest bucket, the top-degree nodes, holds many
+// times the mean).  A slice counts its entries per node of its bucket in LDS; a pass per node
+// sums those counts into the out-degree and, after the scan, turns them into the node's base in
+// each slice (its segment start plus its entries in the bucket's earlier slices); a slice then
+// places its entries with LDS cursors from those bases.  Needs a bucket span of at most DEG_SUB
+// ids (n <= 2^25).
+constexpr uint32_t SLICE_ENTRIES = 16384;
+
+// slice_off[b] = first slice of bucket b (slice_off[NB] = the number of slices); one workgroup
+__global__ void __launch_bounds__(1024) k_slice_plan(const uint32_t* __restrict__ boff, uint32_t nblk, uint32_t NB,
+                                                     uint32_t* __restrict__ slice_off) {
+    __shared__ uint32_t cnt[DEG_BUCKETS];
+    const uint32_t total = boff[(uint64_t)NB * nblk];
+    for (uint32_t b = threadIdx.x; b < NB; b += blockDim.x) {
+        const uint32_t lo = boff[(uint64_t)b * nblk], hi = (b + 1 < NB) ? boff[(uint64_t)(b + 1) * nblk] : total;
+        cnt[b] = (hi - lo + SLICE_ENTRIES - 1) / SLICE_ENTRIES;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (uint32_t b = 0; b < NB; ++b) {
+            slice_off[b] = run;
+            run += cnt[b];
+        }
+        slice_off[NB] = run;
+    }
+}
+
+// the slice of workgroup s: its bucket b and entry range [lo, hi); false past the last slice
+__device__ __forceinline__ bool slice_of(uint32_t s, const uint32_t* __restrict__ slice_off,
+                                         const uint32_t* __restrict__ boff, uint32_t nblk, uint32_t NB, uint32_t& b,
+                                         uint64_t& lo, uint64_t& hi) {
+    if (s >= slice_off[NB]) return false;
+    uint32_t l = 0, h = NB;  // last bucket with slice_off[b] <= s
+    while (h - l > 1) {
+        const uint32_t mid = (l + h) >> 1;
+        if (slice_off[mid] <= s) l = mid; else h = mid;
+    }
+    while (l + 1 < NB && slice_off[l + 1] <= s) ++l;  // skip buckets without slices
+    b = l;
+    const uint32_t total = boff[(uint64_t)NB * nblk];
+    const uint64_t b0 = boff[(uint64_t)b * nblk], b1 = (b + 1 < NB) ? boff[(uint64_t)(b + 1) * nblk] : total;
+    lo = b0 + (uint64_t)(s - slice_off[b]) * SLICE_ENTRIES;
+    hi = (lo + SLICE_ENTRIES) < b1 ? (lo + SLICE_ENTRIES) : b1;
+    return true;
+}
+
+// per slice, its entries per node of its bucket: scnt[s][i] for node (b << shift) + i
+__global__ void __launch_bounds__(1024) k_slice_count(const uint4* __restrict__ opart,
+                                                      const uint32_t* __restrict__ boff, uint32_t nblk, uint32_t NB,
+                                                      uint32_t shift, const uint32_t* __restrict__ slice_off,
+                                                      uint32_t* __restrict__ scount) {
+    __shared__ uint32_t cnt[DEG_SUB];
+    uint32_t b;
+    uint64_t lo, hi;
+    if (!slice_of(blockIdx.x, slice_off, boff, nblk, NB, b, lo, hi)) return;
+    const uint32_t span = 1u << shift, v0 = b << shift;
+    for (uint32_t i = threadIdx.x; i < span; i += blockDim.x) cnt[i] = 0;
+    __syncthreads();
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&cnt[opart[i].x - v0], 1u);
+    __syncthreads();
+    uint32_t* out = scount + (uint64_t)blockIdx.x * span;
+    for (uint32_t i = threadIdx.x; i < span; i += blockDim.x) out[i] = cnt[i];
+}
+
+// dout[v] = the entries of v over its bucket's slices
+__global__ void k_slice_dout(const uint32_t* __restrict__ scount, const uint32_t* __restrict__ slice_off,
+                             uint32_t shift, uint32_t n, uint32_t* __restrict__ dout) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const uint32_t b = v >> shift, i = v - (b << shift), span = 1u << shift;
+        uint32_t d = 0;
+        for (uint32_t s = slice_off[b]; s < slice_off[b + 1]; ++s) d += scount[(uint64_t)s * span + i];
+        dout[v] = d;
+    }
+}
+
+// scount[s][i] <- the position of node v's first entry of slice s in v's segment
+__global__ void k_slice_base(uint32_t* __restrict__ scount, const uint32_t* __restrict__ slice_off,
+                             uint32_t shift, uint32_t n, const uint32_t* __restrict__ off) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const uint32_t b = v >> shift, i = v - (b << shift), span = 1u << shift;
+        uint32_t run = off[v];
+        for (uint32_t s = slice_off[b]; s < slice_off[b + 1]; ++s) {
+            uint32_t* c = scount + (uint64_t)s * span + i;
+            const uint32_t k = *c;
+            *c = run;
+            run += k;
+        }
+    }
+}
+
+// place the slice's entries in their segments (as k_scatter below, with LDS cursors)
+constexpr uint32_t REV_BIT = 0x80000000u;
+__global__ void __launch_bounds__(1024) k_slice_place(const uint4* __restrict__ opart,
+                                                      const uint32_t* __restrict__ boff, uint32_t nblk, uint32_t NB,
+                                                      uint32_t shift, const uint32_t* __restrict__ slice_off,
+                                                      const uint32_t* __restrict__ sbase,
+                                                      const uint32_t* __restrict__ dout,
+                                                      unsigned long long* __restrict__ packed,
+                                                      uint32_t* __restrict__ rcnt, BuildStats* st) {
+    __shared__ uint32_t cur[DEG_SUB];
+    uint32_t b;
+    uint64_t lo, hi;
+    if (!slice_of(blockIdx.x, slice_off, boff, nblk, NB, b, lo, hi)) return;
+    const uint32_t span = 1u << shift, v0 = b << shift;
+    const uint32_t* base = sbase + (uint64_t)blockIdx.x * span;
+    for (uint32_t i = threadIdx.x; i < span; i += blockDim.x) cur[i] = base[i];
+    __syncthreads();
+    unsigned long long work = 0;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const uint4 e = opart[i];
+        const uint32_t pos = atomicAdd(&cur[e.x - v0], 1u);
+        const uint32_t da = dout[e.x], db = dout[e.y];
+        // the counting pass walks the shorter out-list of the pair (see emit_rev)
+        const bool rev = da < db;
+        packed[pos] = ((unsigned long long)e.y << 32) | (rev ? REV_BIT : 0u) | e.z;
+        work += db <= da ? db : da;
+        if (rev) atomicAdd(&rcnt[(uint64_t)e.y * REV_SHARDS + (e.x % REV_SHARDS)], 1u);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) work += __shfl_xor(work, d, 64);
+    if ((threadIdx.x & 63) == 0 && work) atomicAdd(&st->work, work);
+}
+
 // The placement pass takes EDGE_UNROLL edges per thread per step, one grid stride apart, so the
 // independent scattered loads and atomics of those edges are in flight together.
 constexpr uint32_t EDGE_UNROLL = 4;
@@ -332,7 +457,6 @@ constexpr uint32_t EDGE_UNROLL = 4;
 // stream position t is below 2^31, and rev, a function of b within a's segment, leaves the
 // order by (b, t) unchanged), and count the reverse pairs per target shard.  cursor[a] starts
 // at off[a].
-constexpr uint32_t REV_BIT = 0x80000000u;
 __global__ void __launch_bounds__(SCAN_THREADS) k_scatter(const uint2* __restrict__ ab, uint64_t E,
                                                           const uint32_t* __restrict__ dout, uint32_t* cursor,
                                                           unsigned long long* __restrict__ packed,
@@ -658,8 +782,8 @@ struct Layout {
     size_t ctrl, off, nbr, tim, apex, roff, rrec, rpos, total;
 };
 struct ScratchLayout {
-    size_t stats, deg, dout, cursor, ahist, aoff, part, packed, alt, opart, medium, large, bhist, bscan, scnt, sofs,
-        total;
+    size_t stats, deg, dout, cursor, ahist, aoff, part, packed, alt, opart, slice_off, scount, medium, large, bhist,
+        bscan, scnt, sofs, total;
 };
 
 // partition of endpoints for the degree count: buckets of 2^shift ids, NB <= DEG_BUCKETS of
@@ -731,6 +855,14 @@ ScratchLayout scratch_layout(uint32_t n, uint64_t E) {
     p += align256((size_t)E * 8);
     S.opart = p;  // oriented entries (a, b, t) partitioned by the bucket of a
     p += align256((size_t)E * 16);
+    // placement slices (bucket spans of at most DEG_SUB ids): their offsets per bucket and their
+    // per-node counts, then bases
+    const bool sliced = D.shift <= 13;
+    const uint64_t smax = sliced ? (E + SLICE_ENTRIES - 1) / SLICE_ENTRIES + D.NB : 0;
+    S.slice_off = p;
+    p += align256(((size_t)D.NB + 1) * 4);
+    S.scount = p;
+    p += align256((size_t)smax * ((size_t)1 << D.shift) * 4);
     S.medium = p;
     p += align256((size_t)n * 4);
     S.large = p;
@@ -800,6 +932,8 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     unsigned long long* packed = (unsigned long long*)(X + S.packed);
     unsigned long long* alt = (unsigned long long*)(X + S.alt);
     uint4* opart = (uint4*)(X + S.opart);
+    uint32_t* slice_off = (uint32_t*)(X + S.slice_off);
+    uint32_t* scount = (uint32_t*)(X + S.scount);
     uint32_t* medium = (uint32_t*)(X + S.medium);
     uint32_t* large = (uint32_t*)(X + S.large);
     uint32_t* bhist = (uint32_t*)(X + S.bhist);
@@ -839,15 +973,28 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     if (scan_u32(bhist, (uint64_t)D.NB * D.nblk, part, bscan, s) != hipSuccess) return REPT_EDEVICE;
     hipLaunchKernelGGL(k_orient_part, dim3(D.nblk), dim3(1024), 0, s, ab, E, D.shift, D.NB, D.per_block, bscan,
                        opart);
-    hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, dout, (uint64_t)n, 0u);
-    hipLaunchKernelGGL(k_out_count, dim3(grid_for(E, DEG_SLICE, 4096)), dim3(1024), 0, s, opart, bscan, D.nblk, D.NB,
-                       D.shift, n, dout);
-    if (scan_u32(dout, n, part, off, s) != hipSuccess) return REPT_EDEVICE;
     const uint64_t nsh = (uint64_t)n * REV_SHARDS;
     const uint32_t gS = grid_for(nsh, 256, cap);
-    hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
-    hipLaunchKernelGGL(k_copy_u32, dim3(gN), dim3(256), 0, s, off, (uint64_t)n, cursor);
-    hipLaunchKernelGGL(k_scatter, dim3(gE), dim3(256), 0, s, ab, E, dout, cursor, packed, scnt, st);
+    if (D.shift <= 13) {  // placement by slices of the partition, LDS cursors
+        const uint64_t smax = (E + SLICE_ENTRIES - 1) / SLICE_ENTRIES + D.NB;
+        hipLaunchKernelGGL(k_slice_plan, dim3(1), dim3(1024), 0, s, bscan, D.nblk, D.NB, slice_off);
+        hipLaunchKernelGGL(k_slice_count, dim3((uint32_t)smax), dim3(1024), 0, s, opart, bscan, D.nblk, D.NB,
+                           D.shift, slice_off, scount);
+        hipLaunchKernelGGL(k_slice_dout, dim3(gN), dim3(256), 0, s, scount, slice_off, D.shift, n, dout);
+        if (scan_u32(dout, n, part, off, s) != hipSuccess) return REPT_EDEVICE;
+        hipLaunchKernelGGL(k_slice_base, dim3(gN), dim3(256), 0, s, scount, slice_off, D.shift, n, off);
+        hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
+        hipLaunchKernelGGL(k_slice_place, dim3((uint32_t)smax), dim3(1024), 0, s, opart, bscan, D.nblk, D.NB,
+                           D.shift, slice_off, scount, dout, packed, scnt, st);
+    } else {  // wider buckets: out-degrees per bucket in LDS, placement by global cursors
+        hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, dout, (uint64_t)n, 0u);
+        hipLaunchKernelGGL(k_out_count, dim3(grid_for(E, DEG_SLICE, 4096)), dim3(1024), 0, s, opart, bscan, D.nblk,
+                           D.NB, D.shift, n, dout);
+        if (scan_u32(dout, n, part, off, s) != hipSuccess) return REPT_EDEVICE;
+        hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
+        hipLaunchKernelGGL(k_copy_u32, dim3(gN), dim3(256), 0, s, off, (uint64_t)n, cursor);
+        hipLaunchKernelGGL(k_scatter, dim3(gE), dim3(256), 0, s, ab, E, dout, cursor, packed, scnt, st);
+    }
     // reverse lists: shard starts from k_scatter's counts; the sorts place the records
     if (scan_u32(scnt, nsh, part, sofs, s) != hipSuccess) return REPT_EDEVICE;
     hipLaunchKernelGGL(k_rev_roff, dim3(gN), dim3(256), 0, s, sofs, n, roff, st);
