@@ -21,7 +21,6 @@ constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 constexpr int MEDIUM_MAX = 4096;  // segments sorted in LDS by one workgroup
 constexpr int SMALL_MAX = 64;     // segments sorted in registers by one wavefront
-constexpr uint32_t TINY_MAX = 8;  // segments sorted by an 8-lane group, eight per wavefront
 
 __device__ __forceinline__ bool rank_less(uint32_t x, uint32_t dx, uint32_t y, uint32_t dy) {
     return dx < dy || (dx == dy && x < y);
@@ -642,38 +641,17 @@ __device__ __forceinline__ void emit_sorted(unsigned long long v, uint32_t idx, 
     }
 }
 
-// segments of at most 64 entries: bitonic networks across lanes (eight segments of at most 8
-// entries per wavefront, then one longer segment per wavefront)
+// segments of at most 64 entries: one wavefront, bitonic network across lanes
 __global__ void __launch_bounds__(256) k_sort_small(const uint32_t* __restrict__ off, uint32_t n,
                                                     const unsigned long long* __restrict__ packed,
                                                     uint32_t* __restrict__ nbr, uint32_t* __restrict__ tim,
                                                     RevOut R, BuildStats* st) {
     const int lane = threadIdx.x & 63;
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     uint32_t dup = 0;
-    // segments of at most TINY_MAX entries: eight nodes per wavefront, one 8-lane group each
-    const uint32_t il = (uint32_t)lane & (TINY_MAX - 1);
-    for (uint32_t a0 = wave * (64 / TINY_MAX); a0 < n; a0 += waves * (64 / TINY_MAX)) {
-        const uint32_t a = a0 + (uint32_t)lane / TINY_MAX;
-        const uint32_t s = a < n ? off[a] : 0u, d = a < n ? off[a + 1] - s : 0u;
-        const bool mine = d >= 1 && d <= TINY_MAX;
-        unsigned long long v = mine && il < d ? packed[s + il] : ~0ull;
-        for (uint32_t k = 2; k <= TINY_MAX; k <<= 1) {
-            for (uint32_t j = k >> 1; j >= 1; j >>= 1) {
-                const unsigned long long o = __shfl_xor(v, (int)j, 64);  // stays in the 8-lane group
-                const bool up = (il & k) == 0, lower = (il & j) == 0;
-                v = (lower == up) ? (o < v ? o : v) : (o > v ? o : v);
-            }
-        }
-        const unsigned long long prev = __shfl_up(v, 1, 64);
-        if (mine && il > 0 && il < d && (prev >> 32) == (v >> 32)) dup = 1;
-        if (mine) emit_sorted(v, il, a, s, d, nbr, tim, R);
-    }
-    // segments of TINY_MAX + 1 .. SMALL_MAX entries: one wavefront each
-    for (uint32_t a = wave; a < n; a += waves) {
+    for (uint32_t a = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); a < n; a += waves) {
         const uint32_t s = off[a], d = off[a + 1] - s;
-        if (d <= TINY_MAX || d > SMALL_MAX) continue;
+        if (d == 0 || d > SMALL_MAX) continue;
         unsigned long long v = lane < (int)d ? packed[s + lane] : ~0ull;
         for (int k = 2; k <= 64; k <<= 1) {
             for (int j = k >> 1; j >= 1; j >>= 1) {
