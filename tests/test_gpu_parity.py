@@ -148,6 +148,32 @@ def test_invalid_streams(cuda, case):
     assert ei.value.code == code
 
 
+@pytest.mark.parametrize("K", [40, 100, 300])
+@pytest.mark.parametrize("flipped", [False, True])
+def test_duplicate_in_each_sort_class(cuda, K, flipped):
+    """A duplicate edge inside one adjacency segment of K entries (segments of at most 64
+    entries are sorted by one wavefront, longer ones up to 4096 by a workgroup in LDS, with
+    networks of 128 and 512 entries here): a K-clique in which every node but 0 and 1 has one
+    pendant edge, so node 0 ranks lowest in the clique and its out-list holds the K - 1 other
+    clique nodes plus the second copy of {0, 1}."""
+    from paper_1811_09136_amd import rept
+    clique = [(u, v) for u in range(K) for v in range(u + 1, K)]
+    pend = [(i, K + i) for i in range(2, K)]
+    dup = (1, 0) if flipped else (0, 1)
+    e = np.array(clique + pend + [dup], np.uint32)
+    n = 2 * K
+    assert oracle.validate(n, e) == rept.REPT_EDUP
+    _say(f"duplicate in a segment of {K} entries flipped={flipped}")
+    with pytest.raises(rept.ReptError) as ei:
+        rept.Graph(rept.to_device_edges(e, cuda), n)
+    assert ei.value.code == rept.REPT_EDUP
+    # without the duplicate the same stream builds and counts like the oracle
+    e = e[:-1]
+    got = _run(cuda, e, n, 2, 3, 5)
+    _check(e, n, 2, 3, 5, got)
+    assert got[2].max_out_degree == K - 1
+
+
 def test_degenerate_streams(cuda):
     # empty stream, one edge, a path (no triangles), a single triangle in all 6 orders
     cases = [(np.zeros((0, 2), np.uint32), 5), (np.array([[0, 1]], np.uint32), 2),
