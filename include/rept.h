@@ -98,7 +98,10 @@ typedef struct rept_graph_info {
 uint32_t rept_local_rows(const rept_params* params);
 
 /*
- * Device bytes needed to build a graph of n nodes and num_edges stream edges.
+ * Device bytes needed to build a graph of n nodes and num_edges stream edges (Section II: the
+ * stream of num_edges edges over the node set; Section III-A bounds a processor's memory by its
+ * share of the stream, c* = min(c, floor(M / (p |E|))) for a memory cap M, and this call is the
+ * device's form of that sizing: a caller admits a stream only when these bytes fit its budget).
  *   persistent_bytes: kept by the built graph (oriented adjacency and reverse lists: 28 bytes
  *                     per edge plus 12 bytes per node, rounded up);
  *   scratch_bytes:    needed only during rept_build.

@@ -42,7 +42,7 @@ def build(force: bool = True) -> str:
     two roundings (product, then quotient) are exactly the ones written."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC", "-pthread",
                                "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
@@ -70,6 +70,8 @@ def _load():
         L.oracle_rept.restype = i32
         L.oracle_rept_procs.argtypes = [u32, u32, u32, u64, i32, vp, u64, u64, u64, vp, u32, u32, vp, vp]
         L.oracle_rept_procs.restype = i32
+        L.oracle_rept_parallel.argtypes = [u32, u32, u32, u64, i32, vp, u64, u64, u64, u32, u32, u32, vp, vp]
+        L.oracle_rept_parallel.restype = i32
         L.oracle_edge_updates.argtypes = [u32, u32, u32, u64, i32, vp, u64, vp, u64, vp, vp]
         L.oracle_edge_updates.restype = i32
         L.oracle_estimate.argtypes = [u32, u32, u32, u32, vp, vp, vp, vp]
@@ -142,10 +144,10 @@ def rept(edges, n: int, m: int, c: int, seed: int, per_proc: bool = False, t0: i
 
 def rept_threads(edges, n: int, m: int, c: int, seed: int, per_proc: bool = False, t0: int = 0,
                  t1: int | None = None, workers: int = 8, procs: tuple | None = None):
-    """Algorithm 1 with the c processors split over host threads (the C replay releases the
-    GIL).  Processors are independent, so the per-thread partial counts sum to ``rept``.
-    ``procs = (lo, hi)`` replays only processors lo..hi-1 (the others' counters stay 0)."""
-    import concurrent.futures as cf
+    """Algorithm 1 with the c processors spread over host threads (C threads: the stream is
+    validated and hashed once, then each thread replays whole processors).  Processors are
+    independent, so the result equals ``rept``.  ``procs = (lo, hi)`` replays only processors
+    lo..hi-1 (the others' counters stay 0)."""
     e = _edges(edges)
     E = len(e)
     t1 = E if t1 is None else t1
@@ -154,26 +156,14 @@ def rept_threads(edges, n: int, m: int, c: int, seed: int, per_proc: bool = Fals
     p_lo, p_hi = (0, c) if procs is None else procs
     if not 0 <= p_lo <= p_hi <= c:
         raise OracleError(EINVAL, "rept_threads: processor range")
-    span = p_hi - p_lo
-    workers = max(1, min(workers, span))
-    bounds = [(p_lo + span * w // workers, p_lo + span * (w + 1) // workers) for w in range(workers)]
-
-    def run(lo_hi):
-        lo, hi = lo_hi
-        g = np.zeros(c, dtype=np.int64)
-        lo_arr = np.zeros((rows, n), dtype=np.int64)
-        rc = _load().oracle_rept_procs(n, m, c, seed & (2**64 - 1), int(per_proc), e.ctypes.data, E, t0, t1,
-                                       None, lo, hi, g.ctypes.data, lo_arr.ctypes.data)
-        if rc != OK:
-            raise OracleError(rc, "oracle_rept_procs")
-        return g, lo_arr
-
     glob = np.zeros(c, dtype=np.int64)
     loc = np.zeros((rows, n), dtype=np.int64)
-    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
-        for g, lo_arr in ex.map(run, bounds):
-            glob += g
-            loc += lo_arr
+    if p_lo == p_hi:
+        return glob, loc
+    rc = _load().oracle_rept_parallel(n, m, c, seed & (2**64 - 1), int(per_proc), e.ctypes.data, E, t0, t1,
+                                      p_lo, p_hi, max(1, int(workers)), glob.ctypes.data, loc.ctypes.data)
+    if rc != OK:
+        raise OracleError(rc, "oracle_rept_parallel")
     return glob, loc
 
 

@@ -29,6 +29,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <pthread.h>
 
 #define OR_OK 0
 #define OR_EINVAL (-1)
@@ -191,15 +192,57 @@ static int adj_push(adjlist *a, uint32_t w) {
 }
 
 /*
- * REPT per Algorithm 1, extended to c > m by independent groups (Section III-B).
- *
- * For every group k and every processor i = k*m + j of that group (j < c_k), the stream is
- * replayed in order; for each edge (u, v) at time t:
+ * One processor's replay of Algorithm 1 (Section III-A): processor i = k*m + j, which stores the
+ * edges whose slot in its group is j (slot[t] = h_k(edge t)).  The stream is replayed in order;
+ * for each edge (u, v) at time t:
  *   UpdateTriangleCNT: N = N_u^(i) intersect N_v^(i); tau^(i) += |N|; tau_u^(i) += |N|;
  *                      tau_v^(i) += |N|; tau_w^(i) += 1 for each w in N;
  *   then, if h_k(u, v) == j, (u, v) joins E^(i).
  * The counter updates are applied only for t in [t0, t1) (a window of stream positions); the
  * insertions always happen, so a window's counts are the per-edge updates of that window.
+ * tau^(i) is added to *glob and tau_v^(i) to loc[v].  adj: n empty-or-reusable lists (scratch).
+ */
+static int replay_processor(uint32_t n, uint32_t j, const uint32_t *slot, const uint32_t *edges, uint64_t E,
+                            uint64_t t0, uint64_t t1, adjlist *adj, int64_t *glob, int64_t *loc) {
+    uint64_t mine = 0; /* |E^(i)| at the end of the stream */
+    for (uint64_t t = 0; t < E; ++t) mine += (slot[t] == j);
+    edgeset Ei; /* E^(i), for membership tests */
+    if (es_init(&Ei, mine)) return OR_ENOMEM;
+    int rc = OR_OK;
+    for (uint32_t x = 0; x < n; ++x) adj[x].len = 0;
+    for (uint64_t t = 0; t < E; ++t) {
+        const uint32_t u = edges[2 * t], v = edges[2 * t + 1];
+        if (t >= t0 && t < t1) {
+            /* N_{u,v}^(i) = N_u^(i) intersect N_v^(i): walk the smaller set, test the other */
+            const adjlist *small = adj[u].len <= adj[v].len ? &adj[u] : &adj[v];
+            const uint32_t other = adj[u].len <= adj[v].len ? v : u;
+            int64_t cnt = 0;
+            for (uint32_t q = 0; q < small->len; ++q) {
+                const uint32_t w = small->nbr[q];
+                if (es_get(&Ei, pairkey(other, w), NULL)) {
+                    ++cnt;
+                    loc[w] += 1; /* tau_w^(i) += 1 */
+                }
+            }
+            *glob += cnt;  /* tau^(i) += |N| */
+            loc[u] += cnt; /* tau_u^(i) += |N| */
+            loc[v] += cnt; /* tau_v^(i) += |N| */
+        }
+        if (slot[t] == j) { /* h_k(u,v) selects processor i: insert into E^(i) */
+            es_put(&Ei, pairkey(u, v), t);
+            if (adj_push(&adj[u], v) || adj_push(&adj[v], u)) {
+                rc = OR_ENOMEM;
+                break;
+            }
+        }
+    }
+    es_free(&Ei);
+    return rc;
+}
+
+/*
+ * REPT per Algorithm 1, extended to c > m by independent groups (Section III-B): every
+ * processor i = k*m + j (j < c_k) of every group k replays the stream (replay_processor).
  *
  * Outputs (accumulated, +=):
  *   global[i]                    = tau^(i)                              (c entries)
@@ -239,48 +282,139 @@ int oracle_rept_procs(uint32_t n, uint32_t m, uint32_t c, uint64_t seed, int per
         for (uint32_t j = 0; j < ck && rc == OR_OK; ++j) {
             const uint32_t i = k * m + j;
             if (i < p_lo || i >= p_hi) continue;
-            int64_t *loc = local + (uint64_t)(per_proc ? i : k) * n;
-            uint64_t mine = 0; /* |E^(i)| at the end of the stream */
-            for (uint64_t t = 0; t < E; ++t) mine += (slot[t] == j);
-            edgeset Ei; /* E^(i), for membership tests */
-            if (es_init(&Ei, mine)) {
-                rc = OR_ENOMEM;
-                break;
-            }
-            for (uint32_t x = 0; x < n; ++x) adj[x].len = 0;
-            for (uint64_t t = 0; t < E; ++t) {
-                const uint32_t u = edges[2 * t], v = edges[2 * t + 1];
-                if (t >= t0 && t < t1) {
-                    /* N_{u,v}^(i) = N_u^(i) intersect N_v^(i): walk the smaller set, test the other */
-                    const adjlist *small = adj[u].len <= adj[v].len ? &adj[u] : &adj[v];
-                    const uint32_t other = adj[u].len <= adj[v].len ? v : u;
-                    int64_t cnt = 0;
-                    for (uint32_t q = 0; q < small->len; ++q) {
-                        const uint32_t w = small->nbr[q];
-                        if (es_get(&Ei, pairkey(other, w), NULL)) {
-                            ++cnt;
-                            loc[w] += 1; /* tau_w^(i) += 1 */
-                        }
-                    }
-                    global[i] += cnt; /* tau^(i) += |N| */
-                    loc[u] += cnt;    /* tau_u^(i) += |N| */
-                    loc[v] += cnt;    /* tau_v^(i) += |N| */
-                }
-                if (slot[t] == j) { /* h_k(u,v) selects processor i: insert into E^(i) */
-                    es_put(&Ei, pairkey(u, v), t);
-                    if (adj_push(&adj[u], v) || adj_push(&adj[v], u)) {
-                        rc = OR_ENOMEM;
-                        break;
-                    }
-                }
-            }
-            es_free(&Ei);
+            rc = replay_processor(n, j, slot, edges, E, t0, t1, adj, global + i,
+                                  local + (uint64_t)(per_proc ? i : k) * n);
         }
     }
     for (uint32_t x = 0; x < n; ++x) free(adj[x].nbr);
     free(adj);
     free(slot);
     free(params);
+    return rc;
+}
+
+/*
+ * The same replay with the processors spread over `threads` host threads (processors are
+ * independent trials, Section I, so the order in which they run does not matter).  The stream
+ * is validated once and every group's slots are computed once, shared by the threads; each
+ * thread replays whole processors with its own lists and, for group sums, its own local rows,
+ * which are added at the end.  Outputs and arguments as oracle_rept_procs (processors
+ * [p_lo, p_hi), accumulated, +=), without slot_override.
+ */
+typedef struct {
+    uint32_t n, m, end, G, per_proc; /* processors next .. end - 1 are replayed */
+    const uint32_t *edges;
+    uint64_t E, t0, t1;
+    const uint32_t *slots; /* [G][E] */
+    int64_t *global, *local;
+    uint32_t next;         /* next processor to replay (shared) */
+    pthread_mutex_t mu;
+    int rc;
+} par_job;
+
+typedef struct {
+    par_job *job;
+    int64_t *rows; /* private group rows [G][n] (per_proc = 0), else NULL */
+} par_worker;
+
+typedef struct {
+    const uint64_t *params;
+    uint32_t m, G;
+    const uint32_t *edges;
+    uint64_t E, lo, hi;
+    uint32_t *slots;
+} slot_part;
+
+static void *slot_range(void *arg) {
+    slot_part *p = (slot_part *)arg;
+    for (uint32_t k = 0; k < p->G; ++k)
+        for (uint64_t t = p->lo; t < p->hi; ++t)
+            p->slots[(uint64_t)k * p->E + t] = oracle_slot(p->params + 4 * k, p->m, p->edges[2 * t], p->edges[2 * t + 1]);
+    return NULL;
+}
+
+static void *par_replay(void *arg) {
+    par_worker *w = (par_worker *)arg;
+    par_job *J = w->job;
+    adjlist *adj = (adjlist *)calloc(J->n, sizeof(adjlist));
+    if (!adj) {
+        pthread_mutex_lock(&J->mu);
+        J->rc = OR_ENOMEM;
+        pthread_mutex_unlock(&J->mu);
+        return NULL;
+    }
+    for (;;) {
+        pthread_mutex_lock(&J->mu);
+        const uint32_t i = J->next;
+        const int stop = J->rc != OR_OK || i >= J->end;
+        if (!stop) J->next = i + 1;
+        pthread_mutex_unlock(&J->mu);
+        if (stop) break;
+        const uint32_t k = i / J->m, j = i % J->m;
+        int64_t g = 0;
+        int64_t *loc = J->per_proc ? J->local + (uint64_t)i * J->n : w->rows + (uint64_t)k * J->n;
+        const int rc = replay_processor(J->n, j, J->slots + (uint64_t)k * J->E, J->edges, J->E, J->t0, J->t1, adj,
+                                        &g, loc);
+        pthread_mutex_lock(&J->mu);
+        J->global[i] += g; /* each processor's own entry */
+        if (rc != OR_OK) J->rc = rc;
+        pthread_mutex_unlock(&J->mu);
+    }
+    for (uint32_t x = 0; x < J->n; ++x) free(adj[x].nbr);
+    free(adj);
+    return NULL;
+}
+
+int oracle_rept_parallel(uint32_t n, uint32_t m, uint32_t c, uint64_t seed, int per_proc, const uint32_t *edges,
+                         uint64_t E, uint64_t t0, uint64_t t1, uint32_t p_lo, uint32_t p_hi, uint32_t threads,
+                         int64_t *global, int64_t *local) {
+    if (n == 0 || m == 0 || c == 0 || !edges || !global || !local || threads == 0) return OR_EINVAL;
+    if (t0 > t1 || t1 > E || p_lo > p_hi || p_hi > c) return OR_EINVAL;
+    int rc = oracle_validate(n, edges, E);
+    if (rc) return rc;
+    const uint32_t G = (c + m - 1) / m;
+    if (threads > p_hi - p_lo) threads = p_hi - p_lo ? p_hi - p_lo : 1;
+    uint64_t *params = (uint64_t *)malloc(sizeof(uint64_t) * 4 * G);
+    uint32_t *slots = (uint32_t *)malloc(sizeof(uint32_t) * (uint64_t)G * (E ? E : 1));
+    pthread_t *tid = (pthread_t *)calloc(threads, sizeof(pthread_t));
+    par_worker *wk = (par_worker *)calloc(threads, sizeof(par_worker));
+    slot_part *sp = (slot_part *)calloc(threads, sizeof(slot_part));
+    if (!params || !slots || !tid || !wk || !sp) {
+        rc = OR_ENOMEM;
+        goto done;
+    }
+    oracle_hash_params(seed, G, params);
+    /* every group's slots h_k(edge t), the stream split over the threads */
+    for (uint32_t q = 0; q < threads; ++q) {
+        sp[q] = (slot_part){params, m, G, edges, E, E * q / threads, E * (q + 1) / threads, slots};
+        pthread_create(&tid[q], NULL, slot_range, &sp[q]);
+    }
+    for (uint32_t q = 0; q < threads; ++q) pthread_join(tid[q], NULL);
+
+    par_job J = {n, m, p_hi, G, (uint32_t)(per_proc != 0), edges, E, t0, t1, slots, global, local, p_lo,
+                 PTHREAD_MUTEX_INITIALIZER, OR_OK};
+    for (uint32_t q = 0; q < threads; ++q) {
+        wk[q].job = &J;
+        if (!per_proc) {
+            wk[q].rows = (int64_t *)calloc((uint64_t)G * n, sizeof(int64_t));
+            if (!wk[q].rows) J.rc = OR_ENOMEM;
+        }
+    }
+    if (J.rc == OR_OK) {
+        for (uint32_t q = 0; q < threads; ++q) pthread_create(&tid[q], NULL, par_replay, &wk[q]);
+        for (uint32_t q = 0; q < threads; ++q) pthread_join(tid[q], NULL);
+    }
+    rc = J.rc;
+    if (rc == OR_OK && !per_proc) /* the threads' group rows, added */
+        for (uint32_t q = 0; q < threads; ++q)
+            for (uint64_t x = 0; x < (uint64_t)G * n; ++x) local[x] += wk[q].rows[x];
+    for (uint32_t q = 0; q < threads; ++q) free(wk[q].rows);
+done:
+    free(params);
+    free(slots);
+    free(tid);
+    free(wk);
+    free(sp);
     return rc;
 }
 
@@ -448,22 +582,29 @@ int oracle_estimate(uint32_t n, uint32_t m, uint32_t c, uint32_t local_rows,
 /* ------------------------------------------------------------------ Algorithm 2 counters -- */
 
 /*
- * The triangle-pair counters of Algorithm 2 (Section III-B, "Our method of computing eta^(i)
- * and eta_v^(i)"), replayed per processor in stream order.  Each stored edge g of E^(i) has a
- * counter tau_g^(i).  For the edge (u, v) at time t and each w in N = N_u^(i) intersect
- * N_v^(i):
- *   eta^(i)   += tau_(u,w) + tau_(v,w);   eta_w^(i) += tau_(u,w) + tau_(v,w);
- *   eta_u^(i) += tau_(u,w);               eta_v^(i) += tau_(v,w);
- *   tau_(u,w) += 1;                       tau_(v,w) += 1;
- * then, if h_k(u, v) selects i, (u, v) joins E^(i) with its counter set to an initial value.
- * Two readings of that initial value are computed in the same replay:
- *   literal: tau_(u,v) = |N| (Algorithm 2 as printed), which also counts pairs whose shared
- *            edge is the last edge of the earlier triangle;
- *   definition: tau_(u,v) = 0, which counts exactly the pairs of distinct triangles of
- *            Delta^(i) sharing an edge that is the last edge of neither (the definition of
- *            eta^(i) in Section III-B).
+ * The triangle-pair counters of Section III-B, from their definition.
+ *
+ * eta^(i) is the number of unordered pairs of distinct semi-triangles of processor i (triangles
+ * whose two earlier edges processor i stored) that share an edge which is the last edge of
+ * neither.  Two distinct triangles share at most one edge, and an edge that is not the last of
+ * a semi-triangle of i is one of its two earlier edges, so it is an edge g of E^(i).  With
+ *   s_g = the number of semi-triangles of i in which g is one of the two earlier edges,
+ * the pairs sharing g number C(s_g, 2), and eta^(i) = sum over g in E^(i) of C(s_g, 2).
+ * Both triangles of such a pair contain node v only when v is an endpoint of g (otherwise they
+ * would share a second edge), so eta_v^(i) = sum over the edges g of E^(i) at v of C(s_g, 2).
+ *
+ * Algorithm 2 as printed starts the counter of a newly stored edge g at |N| (the number of
+ * semi-triangles of i whose last edge is g, call it L_g) and adds the counter's current value
+ * each time g is an earlier edge of a new semi-triangle; its totals are therefore
+ * sum over g of (s_g L_g + C(s_g, 2)), per processor and per endpoint.  Both readings are
+ * returned (the first is the definition, which the estimator's E(eta^(i)) = eta / m^3 needs).
+ *
+ * Per processor i = k*m + j the stream is replayed in order to find its semi-triangles: for the
+ * edge (u, v) at time t every w in N_u^(i) intersect N_v^(i) closes one, with earlier edges
+ * {u, w} and {v, w}; then (u, v) joins E^(i) if h_k(u, v) = j, and L of it is |N|.  The sums
+ * are taken after the whole stream.
  * Outputs (overwritten): eta_def[i], eta_lit[i] for every processor i < c; eta_v_def[v],
- * eta_v_lit[v] = sum over all processors of eta_v^(i).  The whole stream is replayed.
+ * eta_v_lit[v] = sum over all processors of eta_v^(i).
  */
 int oracle_rept2_eta(uint32_t n, uint32_t m, uint32_t c, uint64_t seed, const uint32_t *edges, uint64_t E,
                      int64_t *eta_def, int64_t *eta_lit, int64_t *eta_v_def, int64_t *eta_v_lit) {
@@ -475,9 +616,10 @@ int oracle_rept2_eta(uint32_t n, uint32_t m, uint32_t c, uint64_t seed, const ui
     uint64_t *params = (uint64_t *)malloc(sizeof(uint64_t) * 4 * G);
     adjlist *adj = (adjlist *)calloc(n, sizeof(adjlist));
     uint32_t *slot = (uint32_t *)malloc(sizeof(uint32_t) * (E ? E : 1));
-    int64_t *cdef = (int64_t *)malloc(sizeof(int64_t) * (E ? E : 1)); /* per stored edge, by index */
-    int64_t *clit = (int64_t *)malloc(sizeof(int64_t) * (E ? E : 1));
-    if (!params || !adj || !slot || !cdef || !clit) {
+    int64_t *s_of = (int64_t *)malloc(sizeof(int64_t) * (E ? E : 1)); /* s_g, by stored index */
+    int64_t *l_of = (int64_t *)malloc(sizeof(int64_t) * (E ? E : 1)); /* L_g */
+    uint64_t *t_of = (uint64_t *)malloc(sizeof(uint64_t) * (E ? E : 1)); /* stream position of g */
+    if (!params || !adj || !slot || !s_of || !l_of || !t_of) {
         rc = OR_ENOMEM;
         goto done;
     }
@@ -493,48 +635,50 @@ int oracle_rept2_eta(uint32_t n, uint32_t m, uint32_t c, uint64_t seed, const ui
             const uint32_t i = k * m + j;
             uint64_t mine = 0;
             for (uint64_t t = 0; t < E; ++t) mine += (slot[t] == j);
-            edgeset Ei; /* E^(i): pair -> index of its counters */
+            edgeset Ei; /* E^(i): pair -> its stored index */
             if (es_init(&Ei, mine)) {
                 rc = OR_ENOMEM;
                 break;
             }
             uint64_t stored = 0;
             for (uint32_t x = 0; x < n; ++x) adj[x].len = 0;
-            for (uint64_t t = 0; t < E; ++t) {
+            /* the semi-triangles of i, in stream order */
+            for (uint64_t t = 0; t < E && rc == OR_OK; ++t) {
                 const uint32_t u = edges[2 * t], v = edges[2 * t + 1];
                 const adjlist *small = adj[u].len <= adj[v].len ? &adj[u] : &adj[v];
                 const uint32_t other = adj[u].len <= adj[v].len ? v : u;
-                int64_t cnt = 0;
+                int64_t closed = 0;
                 for (uint32_t q = 0; q < small->len; ++q) {
                     const uint32_t w = small->nbr[q];
-                    uint64_t iow = 0, iuw = 0, ivw = 0;
-                    if (!es_get(&Ei, pairkey(other, w), &iow)) continue;
-                    ++cnt;
-                    es_get(&Ei, pairkey(u, w), &iuw);
-                    es_get(&Ei, pairkey(v, w), &ivw);
-                    eta_def[i] += cdef[iuw] + cdef[ivw];
-                    eta_lit[i] += clit[iuw] + clit[ivw];
-                    eta_v_def[w] += cdef[iuw] + cdef[ivw];
-                    eta_v_lit[w] += clit[iuw] + clit[ivw];
-                    eta_v_def[u] += cdef[iuw];
-                    eta_v_lit[u] += clit[iuw];
-                    eta_v_def[v] += cdef[ivw];
-                    eta_v_lit[v] += clit[ivw];
-                    cdef[iuw] += 1;
-                    clit[iuw] += 1;
-                    cdef[ivw] += 1;
-                    clit[ivw] += 1;
+                    if (!es_get(&Ei, pairkey(other, w), NULL)) continue;
+                    uint64_t guw = 0, gvw = 0; /* the two earlier edges of the semi-triangle (u, v, w) */
+                    es_get(&Ei, pairkey(u, w), &guw);
+                    es_get(&Ei, pairkey(v, w), &gvw);
+                    s_of[guw] += 1;
+                    s_of[gvw] += 1;
+                    ++closed;
                 }
                 if (slot[t] == j) {
-                    cdef[stored] = 0;
-                    clit[stored] = cnt; /* |N_{u,v}^(i)| at insertion */
+                    s_of[stored] = 0;
+                    l_of[stored] = closed; /* semi-triangles of i whose last edge is (u, v) */
+                    t_of[stored] = t;
                     es_put(&Ei, pairkey(u, v), stored);
                     ++stored;
-                    if (adj_push(&adj[u], v) || adj_push(&adj[v], u)) {
-                        rc = OR_ENOMEM;
-                        break;
-                    }
+                    if (adj_push(&adj[u], v) || adj_push(&adj[v], u)) rc = OR_ENOMEM;
                 }
+            }
+            /* the sums over the stored edges of i and over their endpoints */
+            for (uint64_t g = 0; g < stored && rc == OR_OK; ++g) {
+                const int64_t sg = s_of[g];
+                const int64_t pairs_def = sg * (sg - 1) / 2;
+                const int64_t pairs_lit = sg * l_of[g] + pairs_def;
+                const uint32_t gu = edges[2 * t_of[g]], gv = edges[2 * t_of[g] + 1];
+                eta_def[i] += pairs_def;
+                eta_lit[i] += pairs_lit;
+                eta_v_def[gu] += pairs_def;
+                eta_v_def[gv] += pairs_def;
+                eta_v_lit[gu] += pairs_lit;
+                eta_v_lit[gv] += pairs_lit;
             }
             es_free(&Ei);
         }
@@ -545,8 +689,9 @@ done:
     free(adj);
     free(slot);
     free(params);
-    free(cdef);
-    free(clit);
+    free(s_of);
+    free(l_of);
+    free(t_of);
     return rc;
 }
 

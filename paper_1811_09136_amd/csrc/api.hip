@@ -463,7 +463,9 @@ class HostPool {
 
 // The estimators' common part.  S = sum of global (exact int64), tau_hat = RN(RN(S m^2) / c);
 // with `local` (rows x n, row stride n) and tau_v_hat: S_v = sum over the rows at v (exact),
-// tau_v_hat[v] = RN(RN(S_v m^2) / c).  Node ranges are independent and run on the host pool.
+// tau_v_hat[v] = RN(RN(S_v m^2) / c).  Every sum is checked before any output is written (a
+// first pass over the node ranges only validates; the second writes), so an error return
+// leaves tau_hat and tau_v_hat untouched.  Node ranges are independent and run on the host pool.
 rept_status estimate_core(uint32_t n, const rept_params* params, const int64_t* global, const int64_t* local,
                           uint32_t rows, double* tau_hat, double* tau_v_hat) {
     if (!params_ok(params) || n == 0 || !global || !tau_hat) return REPT_EINVAL;
@@ -483,6 +485,8 @@ rept_status estimate_core(uint32_t n, const rept_params* params, const int64_t* 
         std::atomic<bool> bad{false};
         constexpr uint32_t kPart = 32768;  // nodes per part of the node range
         const uint32_t parts = (uint32_t)(((uint64_t)n + kPart - 1) / kPart);
+        // write = false: only check that every node's sum is in [0, 2^53); true: write the estimates
+        bool write = false;
         const std::function<void(uint32_t)> part = [&](uint32_t k) {
             const uint32_t v0 = k * kPart, v1 = std::min<uint64_t>((uint64_t)v0 + kPart, n);
             constexpr uint32_t kBlock = 4096;  // nodes per pass, kept in a stack buffer
@@ -507,6 +511,7 @@ rept_status estimate_core(uint32_t n, const rept_params* params, const int64_t* 
                     bad = true;
                     return;
                 }
+                if (!write) continue;
                 for (uint32_t i = 0; i < nb; ++i) {
                     const double prod = (double)acc[i] * num;
                     tv[b0 + i] = prod / den;
@@ -515,6 +520,8 @@ rept_status estimate_core(uint32_t n, const rept_params* params, const int64_t* 
         };
         HostPool::get().run(parts, part);
         if (bad) return REPT_ERANGE;
+        write = true;
+        HostPool::get().run(parts, part);
     }
     const double prod = (double)S * num;
     *tau_hat = prod / den;
@@ -650,6 +657,7 @@ rept_status rept_estimate_combined(uint32_t n, const rept_params* params, const 
         std::atomic<bool> bad{false};
         constexpr uint32_t kPart = 32768;
         const uint32_t parts = (uint32_t)(((uint64_t)n + kPart - 1) / kPart);
+        bool write = false;  // first pass: check every sum; second pass: write (no output on ERANGE)
         const std::function<void(uint32_t)> part = [&](uint32_t k) {
             const uint32_t v0 = k * kPart, v1 = std::min<uint64_t>((uint64_t)v0 + kPart, n);
             for (uint32_t v = v0; v < v1; ++v) {
@@ -665,11 +673,13 @@ rept_status rept_estimate_combined(uint32_t n, const rept_params* params, const 
                     bad = true;
                     return;
                 }
-                tau_v_hat[v] = combine(A, B, eta_v[v], m, c);
+                if (write) tau_v_hat[v] = combine(A, B, eta_v[v], m, c);
             }
         };
         HostPool::get().run(parts, part);
         if (bad) return REPT_ERANGE;
+        write = true;
+        HostPool::get().run(parts, part);
     }
     *tau_hat = combine(S1, S2, eta, m, c);
     return REPT_OK;

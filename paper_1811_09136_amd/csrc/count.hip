@@ -119,7 +119,7 @@ __host__ __device__ inline Area area_layout(uint32_t DW, uint32_t DB, uint32_t G
     return A;
 }
 struct Misc {  // per wavefront
-    uint32_t mark, qv, qp, hist, bytes;
+    uint32_t mark, qv, qp, hist, hits, bytes;
 };
 __host__ __device__ inline Misc misc_layout(uint32_t HC) {
     Misc M;
@@ -128,6 +128,7 @@ __host__ __device__ inline Misc misc_layout(uint32_t HC) {
     M.qv = p; p = up16(p + 4 * kQueue);
     M.qp = p; p = up16(p + 4 * kQueue);
     M.hist = p; p = up16(p + 4 * HC);
+    M.hits = p; p = up16(p + 4);  // hits drained since the histogram's last flush
     M.bytes = p;
     return M;
 }
@@ -196,6 +197,7 @@ struct WaveView {
     uint32_t* qv;
     uint32_t* qp;
     uint32_t* hist;
+    uint32_t* hits;
 };
 __device__ inline WaveView wave_view(uint8_t* base, const Misc& M) {
     WaveView V;
@@ -203,6 +205,7 @@ __device__ inline WaveView wave_view(uint8_t* base, const Misc& M) {
     V.qv = (uint32_t*)(base + M.qv);
     V.qp = (uint32_t*)(base + M.qp);
     V.hist = (uint32_t*)(base + M.hist);
+    V.hits = (uint32_t*)(base + M.hits);
     return V;
 }
 
@@ -410,15 +413,18 @@ __device__ __forceinline__ uint32_t team_excl_scan(uint32_t v, uint32_t* red, ui
     return pre + inc - v;
 }
 
+// sum over the team, 64-bit (the per-thread parts may exceed 32 bits together)
 template <bool BLOCK>
-__device__ __forceinline__ uint32_t team_sum(uint32_t v, uint32_t* red) {
-    const uint32_t s = wave_sum(v);
-    if (!BLOCK) return s;
+__device__ __forceinline__ uint64_t team_sum64(uint64_t v, uint32_t* red) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (!BLOCK) return v;
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (lane == 0) red[16 + wid] = s;
+    uint64_t* red64 = (uint64_t*)(red + 16);  // words 16..47: up to 16 wavefronts
+    if (lane == 0) red64[wid] = v;
     __syncthreads();
-    uint32_t t = 0;
-    for (uint32_t w = 0; w < nw; ++w) t += red[16 + w];
+    uint64_t t = 0;
+    for (uint32_t w = 0; w < nw; ++w) t += red64[w];
     __syncthreads();
     return t;
 }
@@ -530,6 +536,27 @@ __device__ void drain_hits_t(const JobRegs& J, const TeamView& T, const WaveView
     wave_sync();
 }
 
+// Add the wavefront's histogram of global counts to the outputs and clear it.
+__device__ void flush_hist_now(const JobRegs& J, const WaveView& V) {
+    const uint32_t lane = lane_id();
+    wave_sync();
+    for (uint32_t p = lane; p < J.c; p += 64) {
+        const uint32_t v = V.hist[p];
+        if (v) {
+            add64(J.global + p, v);
+            V.hist[p] = 0;
+        }
+    }
+    if (lane == 0) *V.hits = 0;
+    wave_sync();
+}
+
+// A histogram counter gains at most one per drained hit (a hit is one triangle, and it is a
+// semi-triangle of at most one processor per group), so it cannot pass kHistFlushHits + one
+// drain's hits (< 2^32) if the histogram is flushed whenever the wavefront's hits since the
+// last flush reach kHistFlushHits.
+constexpr uint32_t kHistFlushHits = 1u << 31;
+
 // the drain for the job's slot-row width (uniform over the wavefront)
 template <bool ETA>
 __device__ __forceinline__ void drain_hits(const JobRegs& J, const TeamView& T, const WaveView& V, uint32_t a,
@@ -538,6 +565,16 @@ __device__ __forceinline__ void drain_hits(const JobRegs& J, const TeamView& T, 
     else if (J.gs == 2) drain_hits_t<2, ETA>(J, T, V, a, wbase, qn);
     else if (J.gs == 4) drain_hits_t<4, ETA>(J, T, V, a, wbase, qn);
     else drain_hits_t<8, ETA>(J, T, V, a, wbase, qn);
+    if (J.use_hist) {
+        const uint32_t h = *V.hits + qn;  // the same LDS word in every lane: uniform
+        if (h >= kHistFlushHits) {
+            flush_hist_now(J, V);
+        } else {
+            wave_sync();
+            if (lane_id() == 0) *V.hits = h;
+            wave_sync();
+        }
+    }
 }
 
 // add packed pair counts (s | L << 16) to the stored edge at adjacency position pos, group g
@@ -808,7 +845,7 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
         if (!J.per_proc) {
             // flush the w-side counts; their sum per group is a's own count for this chunk
             for (uint32_t g = 0; g < G; ++g) {
-                uint32_t part = 0;
+                uint64_t part = 0;
                 for (uint32_t i = tid; i < wn; i += nt) {
                     const uint32_t v = T.cntw[g * T.DW + i];
                     if (v) {
@@ -816,7 +853,7 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                         part += v;
                     }
                 }
-                const uint32_t tot = team_sum<BLOCK>(part, T.red);
+                const uint64_t tot = team_sum64<BLOCK>(part, T.red);
                 if (tid == 0 && tot) add64(J.local + (uint64_t)g * J.n + a, tot);
             }
         }
@@ -826,16 +863,7 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
 
 __device__ void flush_hist(const JobRegs& J, const WaveView& V, int cur) {
     if (cur < 0 || !J.use_hist) return;
-    const uint32_t lane = lane_id();
-    wave_sync();
-    for (uint32_t p = lane; p < J.c; p += 64) {
-        const uint32_t v = V.hist[p];
-        if (v) {
-            add64(J.global + p, v);
-            V.hist[p] = 0;
-        }
-    }
-    wave_sync();
+    flush_hist_now(J, V);
 }
 
 // ======================================================================= setup / zero ====
@@ -1140,6 +1168,7 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
     __shared__ uint32_t s_tile;
 
     for (uint32_t i = lane; i < HC; i += 64) V.hist[i] = 0;
+    if (lane == 0) *V.hits = 0;
     JobRegs J;
     int cur = -1;
 

@@ -171,9 +171,21 @@ __global__ void __launch_bounds__(kThreads) k_inc_count(IncCount a) {
     const bool use_hist = a.c <= kHist;
     for (uint32_t i = threadIdx.x; i < kHist; i += blockDim.x) hist[i] = 0u;
     const uint64_t total = a.N2 ? a.end[a.N2 - 1] : 0;
+    // items counted into the histogram since its last flush: each item adds at most one to a
+    // processor's counter, so flushing once this reaches 2^31 keeps every counter below 2^32
+    uint64_t since = 0;
     for (uint64_t i0 = (uint64_t)blockIdx.x * kRun; i0 < total; i0 += (uint64_t)gridDim.x * kRun) {
         const uint64_t i1 = (i0 + kRun) < total ? (i0 + kRun) : total;
-        __syncthreads();  // the previous run's readers of s_end are done
+        if (use_hist && since + (i1 - i0) > (1ull << 31)) {  // uniform over the workgroup
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < a.c; i += blockDim.x) {
+                if (hist[i]) atomicAdd((unsigned long long*)a.global + i, (unsigned long long)hist[i]);
+                hist[i] = 0u;
+            }
+            since = 0;
+        }
+        since += i1 - i0;
+        __syncthreads();  // the previous run's readers of s_end are done (and the flush's)
         if (threadIdx.x == 0) {
             s_lo = upper_item(a.end, 0, a.N2, i0);
             s_hi = upper_item(a.end, s_lo, a.N2, i1 - 1) + 1;  // entries [lo, hi) hold the run

@@ -276,9 +276,10 @@ def rept_count_eta(handle: int, params: Params, global_ptr: int, local_ptr: int,
 
 
 def rept_estimate_combined(n: int, params: Params, glob: np.ndarray, loc: np.ndarray | None, eta: int,
-                           eta_v: np.ndarray | None):
+                           eta_v: np.ndarray | None, tau_v_out=None):
     """Algorithm 2's combined FP64 estimators (c > m, m not dividing c); returns
-    (tau_hat, tau_v_hat or None).  eta: sum of the definition counters; eta_v: int64[n]."""
+    (tau_hat, tau_v_hat or None).  eta: sum of the definition counters; eta_v: int64[n];
+    `tau_v_out` (float64[n]) receives the local estimators when given."""
     p = params.c_struct()
     g = np.ascontiguousarray(glob, dtype=np.int64)
     th = ctypes.c_double(0.0)
@@ -288,7 +289,12 @@ def rept_estimate_combined(n: int, params: Params, glob: np.ndarray, loc: np.nda
         ev = np.ascontiguousarray(eta_v, dtype=np.int64)
         if ev.shape != (n,):
             raise ValueError("eta_v must hold n values")
-        tv = np.empty(n, dtype=np.float64)
+        if tau_v_out is None:
+            tv = np.empty(n, dtype=np.float64)
+        else:
+            tv = tau_v_out
+            if tv.dtype != np.float64 or tv.shape != (n,) or not tv.flags.c_contiguous:
+                raise ValueError("tau_v_out must be a contiguous float64 array of n values")
         lp, ep = lo.ctypes.data, ev.ctypes.data
     _check(lib().rept_estimate_combined(n, ctypes.byref(p), g.ctypes.data, lp, int(eta), ep, ctypes.addressof(th),
                                         None if tv is None else tv.ctypes.data), "rept_estimate_combined")

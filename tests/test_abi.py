@@ -202,6 +202,56 @@ def test_estimate_combined_zero_ulp_against_oracle(m, c, per_proc):
         assert ei.value.code == rept.REPT_EINVAL
 
 
+def test_estimators_write_nothing_on_error():
+    """An ERANGE return leaves every output as it was: the sums are checked over all nodes (and
+    every row) before the first estimate is written, so a bad value in the last node's last row
+    cannot leave a partly written tau_v_hat, and tau_hat is never touched."""
+    from paper_1811_09136_amd import rept
+    L = rept.lib()
+    rng = np.random.default_rng(19)
+    n, m, c = 250_007, 10, 40
+    glob = rng.integers(0, 2**30, size=c)
+    loc = rng.integers(0, 2**30, size=(4, n))
+    sentinel = np.float64(-7.25)
+
+    def raw(fn, *args):
+        th = ctypes.c_double(float(sentinel))
+        tv = np.full(n, sentinel)
+        code = fn(*args, ctypes.addressof(th), tv.ctypes.data)
+        return code, th.value, tv
+
+    P = rept.Params(m, c, 0).c_struct()
+    g = np.ascontiguousarray(glob, np.int64)
+    for r, v, val in [(3, n - 1, 2**53), (0, n - 1, -1), (2, 0, 2**53), (1, n // 2, -5)]:
+        bad = np.ascontiguousarray(loc.copy())
+        bad[r, v] = val
+        code, th, tv = raw(L.rept_estimate, n, ctypes.byref(P), g.ctypes.data, bad.ctypes.data)
+        assert code == rept.REPT_ERANGE and th == sentinel and np.all(tv == sentinel)
+        sums = np.ascontiguousarray(loc.sum(axis=0))
+        sums[v] = val if val < 0 else 2**53
+        code, th, tv = raw(L.rept_estimate_sums, n, ctypes.byref(P), g.ctypes.data, sums.ctypes.data)
+        assert code == rept.REPT_ERANGE and th == sentinel and np.all(tv == sentinel)
+    # the combined estimators (c mod m != 0): a bad local row or eta_v at the last node
+    m2, c2 = 10, 35
+    P2 = rept.Params(m2, c2, 0).c_struct()
+    g2 = np.ascontiguousarray(rng.integers(0, 2**30, size=c2), np.int64)
+    l2 = np.ascontiguousarray(rng.integers(0, 2**30, size=(4, n)), np.int64)
+    ev = np.ascontiguousarray(rng.integers(0, 2**30, size=n), np.int64)
+    for what in ("loc", "eta_v"):
+        lb, eb = l2.copy(), ev.copy()
+        if what == "loc":
+            lb[3, n - 1] = 2**53
+        else:
+            eb[n - 1] = -1
+        code, th, tv = raw(L.rept_estimate_combined, n, ctypes.byref(P2), g2.ctypes.data, lb.ctypes.data,
+                           ctypes.c_int64(123), eb.ctypes.data)
+        assert code == rept.REPT_ERANGE and th == sentinel and np.all(tv == sentinel)
+    # a good call still writes every estimate
+    code, th, tv = raw(L.rept_estimate, n, ctypes.byref(P), g.ctypes.data, np.ascontiguousarray(loc).ctypes.data)
+    oth, otv = oracle.estimate(n, m, c, glob, loc)
+    assert code == rept.REPT_OK and th == oth and np.array_equal(tv.view(np.uint64), otv.view(np.uint64))
+
+
 def test_mascot_params_and_estimator():
     """Parallel MASCOT: one hash group and one local row per processor, at most 8 per call;
     its estimator is (m^2 / c) S for every c, 0 ulp against the oracle's."""

@@ -68,3 +68,29 @@ def test_oversized_and_invalid_requests_fail_alone(cuda):
         else:
             assert r.status == "ok"
     assert need[big] > budget
+
+
+@pytest.mark.timeout(600)
+def test_served_multi_million_edge_request_against_oracle(cuda):
+    """A request of 2.5e6 edges (the served workload's lognormal sizes reach 2e7) counted in many
+    unit chunks while smaller requests arrive and join its launches: every result, the large one
+    included, equals the oracle's replay."""
+    import os
+    from paper_1811_09136_amd.serve import DeviceExecutor, Request, Server
+    e_big, n_big = synth.scaled_chung_lu(2_500_000, 77)
+    reqs = [Request(0, 0.0, e_big, n_big, 50, 200, 901)]
+    tr = synth.serving_trace(seed=9, n_requests=10, rate_per_s=2000.0, median_edges=5e4, e_hi=2e5)
+    for i, r in enumerate(tr, start=1):
+        e, n = synth.scaled_chung_lu(r["E"], r["graph_seed"] % (2**31))
+        reqs.append(Request(i, 0.002 + r["arrival_s"], e, n, r["m"], r["c"], r["hash_seed"]))
+    _say(f"serving a {len(e_big)}-edge request with {len(reqs) - 1} smaller ones")
+    ex = DeviceExecutor("cuda:0")
+    srv = Server(ex, budget_bytes=32 << 30, max_active=16, chunk_units=2048, build_workers=2)
+    res = srv.run(reqs)
+    assert all(r.status == "ok" for r in res), [r.status for r in res]
+    assert res[0].chunks > 1 and max(len(ids) for _, ids in srv.trace) > 1
+    W = max(1, min(16, len(os.sched_getaffinity(0))))
+    for r, q in zip(res, reqs):
+        _say(f"oracle, request {q.rid} ({len(q.edges)} edges, m={q.m}, c={q.c})")
+        og, ol = oracle.rept_threads(q.edges, q.n, q.m, q.c, q.seed, workers=W)
+        assert np.array_equal(r.glob, og) and np.array_equal(r.loc, ol), q.rid

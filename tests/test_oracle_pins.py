@@ -329,6 +329,20 @@ def test_threaded_processor_ranges_partition_the_replay():
     assert not g02[2:].any() and not l02[2:].any()
 
 
+@pytest.mark.parametrize("m,c,per_proc,window", [(10, 10, False, None), (3, 7, True, None), (4, 13, False, (300, 1700)),
+                                                 (1, 1, False, None), (5, 3, True, (0, 900)), (2, 9, False, None)])
+def test_threaded_replay_equals_serial(m, c, per_proc, window):
+    """The threaded replay (stream validated and hashed once, processors spread over threads,
+    private group rows added at the end) equals the single-threaded replay at every thread
+    count, for group sums, processor rows and windows."""
+    e = synth.er(300, 2500, 81, 82)
+    kw = {} if window is None else dict(t0=window[0], t1=window[1])
+    g, l = oracle.rept(e, 300, m, c, 123, per_proc=per_proc, **kw)
+    for workers in (1, 2, 3, 8, 64):
+        gt, lt = oracle.rept_threads(e, 300, m, c, 123, per_proc=per_proc, workers=workers, **kw)
+        assert np.array_equal(gt, g) and np.array_equal(lt, l), workers
+
+
 def test_hash_four_wise_collision_rate_over_seeds():
     """Theorem 3's variance needs the slots of any four distinct edges to be independent
     (zero covariance between semi-triangles on disjoint edge pairs).  For FIXED quadruples of
