@@ -187,6 +187,22 @@ rept_status rept_count_range(const rept_graph* graph, const rept_params* params,
                              size_t workspace_bytes, void* stream);
 
 /*
+ * rept_count without a workspace argument, for callers that cannot allocate device memory
+ * (code being captured into a HIP graph, tight serving loops, harnesses that forbid allocation).
+ * The slot table lives in a static device array of REPT_NOALLOC_SCRATCH_BYTES that the library
+ * holds on each device it runs on until the process ends; the call allocates nothing and creates
+ * no stream or event (both phases of the counting kernel run in one launch on `stream`).
+ *   global, local: as rept_count (overwritten; the results equal rept_count's exactly).
+ * The array is rewritten by every call before it is read, and every call on one device shares
+ * it: calls that overlap on one device (other streams or threads) race and must not be issued.
+ * Asynchronous on `stream`.  Errors: EINVAL, ENOTSUP (m > 65536); ENOMEM if the slot table
+ * (rept_count_workspace_size) exceeds REPT_NOALLOC_SCRATCH_BYTES; EDEVICE.
+ */
+#define REPT_NOALLOC_SCRATCH_BYTES (64u << 20) /* 64 MiB: e.g. 33.5M stored edges at one hash group */
+rept_status rept_count_noalloc(const rept_graph* graph, const rept_params* params, int64_t* global,
+                               int64_t* local, void* stream);
+
+/*
  * Estimators (host, FP64).  For c <= m (Algorithm 1) and for c > m with m | c (Section III-B,
  * c2 = 0) both reduce to
  *     tau_hat   = ((double)S   * (double)(m*m)) / (double)c,   S   = sum_i tau^(i)

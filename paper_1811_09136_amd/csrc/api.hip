@@ -250,7 +250,7 @@ rept_status make_job(const rept_job& jb, JobDev* d, uint64_t* zero_words) {
 // coefficients into its slice of the outputs, so the results equal one launch over all groups.
 rept_status count_one(const rept_graph* graph, const rept_params* params, uint64_t t0, uint64_t t1,
                       bool accumulate, int64_t* global, int64_t* local, void* workspace, size_t workspace_bytes,
-                      void* stream) {
+                      void* stream, const rept_tuning* tuning = nullptr) {
     if (!valid_graph(graph) || !params_ok(params) || !global || !local) return REPT_EINVAL;
     if (t0 > t1 || t1 > graph->E) return REPT_EINVAL;
     if (params->m > 65536) return REPT_ENOTSUP;
@@ -292,7 +292,7 @@ rept_status count_one(const rept_graph* graph, const rept_params* params, uint64
             if (st != REPT_OK) return st;
             group_params(params->seed, dq.G, dq.hp, k0);  // this pass's groups of the whole seed
             BatchHeader h;
-            st = make_header(1, dq.G, dq.c, graph->max_out, zw, !accumulate, nullptr, &h);
+            st = make_header(1, dq.G, dq.c, graph->max_out, zw, !accumulate, tuning, &h);
             if (st != REPT_OK) return st;
             if (!check) continue;
             h.any_fill = 1;
@@ -392,6 +392,54 @@ rept_status rept_count_range(const rept_graph* graph, const rept_params* params,
                              int64_t* global, int64_t* local, void* workspace, size_t workspace_bytes,
                              void* stream) {
     return count_one(graph, params, t0, t1, true, global, local, workspace, workspace_bytes, stream);
+}
+
+}  // extern "C"
+
+// ---- the allocation-free count: the slot table in a static device array -------------------
+// The array below is a host-side stand-in in host code; its device address is taken once per
+// device with hipGetSymbolAddress (with that device current) and only that address is used.
+static __device__ __align__(256) uint8_t scratch[REPT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};  // per device: the device address of `scratch`, once taken
+
+// the device address of this device's `scratch`, taken on the first call on the device
+rept_status scratch_for_current(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return REPT_EDEVICE;
+    if (dev < 0 || dev >= 64) return REPT_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return REPT_EDEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return REPT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+rept_status rept_count_noalloc(const rept_graph* graph, const rept_params* params, int64_t* global, int64_t* local,
+                               void* stream) {
+    if (!valid_graph(graph) || !params_ok(params) || !global || !local) return REPT_EINVAL;
+    if (params->m > 65536) return REPT_ENOTSUP;
+    if (table_bytes(graph, params) > (size_t)REPT_NOALLOC_SCRATCH_BYTES) return REPT_ENOMEM;
+    void* ws = nullptr;
+    const rept_status st = scratch_for_current(&ws);
+    if (st != REPT_OK) return st;
+    // both phases in one launch on `stream`: no second stream or event is created
+    rept_tuning one{};
+    one.phase_launches = 1;
+    return count_one(graph, params, 0, graph->E, false, global, local, ws, (size_t)REPT_NOALLOC_SCRATCH_BYTES, stream,
+                     &one);
 }
 
 namespace {

@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
             "rept_count_workspace_size": ([vp, P(rept_params), P(sz)], i32),
             "rept_count": ([vp, P(rept_params), vp, vp, vp, sz, vp], i32),
             "rept_count_range": ([vp, P(rept_params), u64, u64, vp, vp, vp, sz, vp], i32),
+            "rept_count_noalloc": ([vp, P(rept_params), vp, vp, vp], i32),
             "rept_estimate": ([u32, P(rept_params), vp, vp, vp, vp], i32),
             "rept_estimate_sums": ([u32, P(rept_params), vp, vp, vp, vp], i32),
             "rept_count_eta_workspace_size": ([vp, P(rept_params), P(sz)], i32),
@@ -109,7 +110,7 @@ def lib() -> ctypes.CDLL:
 
 
 EXPORTED = ["rept_local_rows", "rept_query_sizes", "rept_build", "rept_build_host", "rept_graph_get_info",
-            "rept_count_workspace_size", "rept_count",
+            "rept_count_workspace_size", "rept_count", "rept_count_noalloc",
             "rept_count_range", "rept_estimate", "rept_estimate_sums", "rept_count_eta_workspace_size",
             "rept_count_eta", "rept_estimate_combined", "rept_stream_query_sizes", "rept_stream_create",
             "rept_stream_append", "rept_stream_num_edges", "rept_stream_destroy", "rept_reduce_local", "rept_hash_slots", "rept_batch_workspace_size",
@@ -205,6 +206,12 @@ def rept_count(handle: int, params: Params, global_ptr: int, local_ptr: int, ws_
     p = params.c_struct()
     _check(lib().rept_count(handle, ctypes.byref(p), global_ptr, local_ptr, ws_ptr, ws_bytes, stream_ptr),
            "rept_count")
+
+
+def rept_count_noalloc(handle: int, params: Params, global_ptr: int, local_ptr: int, stream_ptr: int | None):
+    """rept_count with the slot table in the library's static device array (no workspace)."""
+    p = params.c_struct()
+    _check(lib().rept_count_noalloc(handle, ctypes.byref(p), global_ptr, local_ptr, stream_ptr), "rept_count_noalloc")
 
 
 def rept_count_range(handle: int, params: Params, t0: int, t1: int, global_ptr: int, local_ptr: int, ws_ptr: int,
