@@ -6,16 +6,19 @@ the reduction of the local rows to node sums on the device (rept_reduce_local), 
 device-to-host copy of the c global counters and the n sums, and the FP64 estimators on the
 host (rept_estimate_sums).
 
-Default workload: Chung-Lu power-law stream, 1,000,000 nodes, 20,000,000 edges, exponent 2.1,
-random order, m = 10 (p = 0.1), c = 40 (four hash groups).  Prints one JSON line.
+Default workload (the largest single-GPU one): R-MAT scale 24, edge factor 16,
+(a, b, c) = (0.57, 0.19, 0.19), deduplicated, generation order (260,384,039 edges), m = c = 100.
+Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-batched] [--no-served]
-                  [--no-alg2] [--no-mascot] [--no-incremental] [--workload NAME]
+                  [--no-alg2] [--no-mascot] [--no-incremental] [--no-side] [--workload NAME]
 
-The line also carries "batched" (512 jobs: plain one-by-one vs one graph-captured batched launch)
-and "served" (Poisson requests: continuous batching vs a FIFO plain loop) comparisons, "alg2"
-(Algorithm 2's pass, c mod m != 0, against the plain count), "mascot" (parallel MASCOT
-against REPT with the same m and c) and "incremental" (the stream appended in ten chunks).
+The line also carries "config2" (the Chung-Lu 1M/20M stream, m = 10, c = 40: its steps and
+roofline), "batched" (512 jobs: plain one-by-one vs one graph-captured batched launch) and
+"served" (Poisson requests: continuous batching vs a FIFO plain loop) comparisons, and, on the
+1M/20M stream, "alg2" (Algorithm 2's pass, c mod m != 0, against the plain count), "mascot"
+(parallel MASCOT against REPT with the same m and c) and "incremental" (the stream appended in
+ten chunks).
 """
 from __future__ import annotations
 
@@ -40,6 +43,7 @@ WORKLOADS = {
                 "config3", 1 << 24, 100, 100),
 }
 HASH_SEED = 20181122
+SIDE_WORKLOAD = "config2"  # measured beside the headline; the next rows run on it
 
 
 def say(*a):
@@ -52,7 +56,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="config3", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-side", action="store_true",
+                    help=f"skip the {SIDE_WORKLOAD} workload's steps (the next rows then run only if it is the headline)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--no-served", action="store_true", help="skip the served-vs-plain comparison")
@@ -116,37 +122,23 @@ def streaming_model_bytes(deg_sq_half_sum: int, E: int, groups: int, semi: int, 
 
 
 def cpu_baseline(edges, n, m, c):
-    """The oracle (Algorithm 1 replay, one host thread per processor) timed on the host cores
-    (at most 16) for a sample of the job's processors: processors 0..W-1 of the c, one per
-    core, over the full stream.  Every processor replays the whole stream with its own sample
-    of about E/m edges, so the whole job on W cores takes c/W times the sample's wall time."""
+    """The oracle (Algorithm 1 replay) timed on the host cores this process may use, capped at the
+    16 that the GPU machine allots to one GPU: a sample of the job's processors, 0..W-1 of the c, one
+    per thread, each replaying the whole stream with its own sample of about E/m edges.  Every
+    processor does the same kind of work, so the whole job on W cores takes c/W times the
+    sample's wall time."""
     import oracle
-    W = max(1, min(16, os.cpu_count() or 1, c))
+    usable = len(os.sched_getaffinity(0))
+    W = max(1, min(16, usable, c))
     t0 = time.perf_counter()
     oracle.rept_threads(edges, n, m, c, HASH_SEED, workers=W, procs=(0, W))
     dt = time.perf_counter() - t0
     job_s = dt * c / W
     return {"value": len(edges) / job_s, "unit": "stream edges/s", "cores": W, "kind": "oracle",
+            "host_cpu_count": os.cpu_count(), "host_cores_usable": usable,
             "sample": f"Algorithm 1 replay of processors 0..{W - 1} of {c} over all {len(edges)} stream edges, "
-                      f"one thread each, took {dt:.2f} s on {W} cores; whole job = {c}/{W} x that"}
-
-
-def cpu_single_core(edges, n, m, c):
-    """The single-threaded oracle on one pinned host core: processor 0 of the c replayed over
-    the whole stream; the whole job is c times that."""
-    import oracle
-    mask = os.sched_getaffinity(0)
-    core = min(mask)
-    os.sched_setaffinity(0, {core})
-    try:
-        t0 = time.perf_counter()
-        oracle.rept_threads(edges, n, m, c, HASH_SEED, workers=1, procs=(0, 1))
-        dt = time.perf_counter() - t0
-    finally:
-        os.sched_setaffinity(0, mask)
-    return {"value": len(edges) / (dt * c), "unit": "stream edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"Algorithm 1 replay of processor 0 of {c} over all {len(edges)} stream edges on core {core} "
-                      f"(pinned) took {dt:.2f} s; whole job = {c} x that"}
+                      f"one thread each, took {dt:.2f} s on {W} cores (os.cpu_count() = {os.cpu_count()}, "
+                      f"{usable} usable by this process); whole job = {c}/{W} x that"}
 
 
 def bench_alg2(dev, edges, n: int, m: int, c: int, reps: int = 3):
@@ -343,21 +335,17 @@ def bench_served(dev, n_requests: int = 64, mults=(0.25, 0.5, 1.0, 1.5, 2.0)):
             "total_edges": int(sum(len(e) for e, _ in graphs)), "sweep": sweep}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
-                                   "run with --gpus 1"}))
-        sys.exit(2)
+def measure_plain(dev, workload: str, steps: int, warmup: int, host_input: bool = True) -> dict:
+    """Time `steps` whole-path steps (after `warmup`) of one workload resident in HBM, then the
+    counting kernel alone for the roofline; returns the figures of the JSON line."""
     import numpy as np
     import torch
     from paper_1811_09136_amd import rept
 
-    desc, _, n, m, c = WORKLOADS[args.workload]
-    dev = torch.device("cuda:0")
-    edges = stream_for(args.workload)
+    desc, _, n, m, c = WORKLOADS[workload]
+    edges = stream_for(workload)
     E = len(edges)
-    say(f"workload {args.workload}: n={n} E={E} m={m} c={c}")
+    say(f"workload {workload}: n={n} E={E} m={m} c={c}")
     params = rept.Params(m, c, HASH_SEED)
     rows = params.rows
     d_edges = rept.to_device_edges(edges, dev)
@@ -410,20 +398,21 @@ def main():
             estimate_ms.append(1e3 * (t3 - t2))
         return tau_hat, info
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         tau_hat, info = step(True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms_per_step = 1e3 * dt / args.steps
-    value = E * args.steps / dt
-    say(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, count {sum(count_ms) / len(count_ms):.3f} ms")
+    ms_per_step = 1e3 * dt / steps
+    value = E * steps / dt
+    say(f"{workload}: timed {steps} steps: {ms_per_step:.2f} ms/step, count {sum(count_ms) / len(count_ms):.3f} ms")
 
     # the counting kernel alone, for the roofline: one job whose slot table an earlier launch
-    # wrote (REPT_JOB_TABLE_READY), so a launch runs setup, the output clear and k_count only
+    # wrote (REPT_JOB_TABLE_READY), so a launch runs setup, the output clear and k_count only;
+    # HIP events on the stream the kernels are launched on
     h = rept.rept_build(n, d_edges.data_ptr(), E, persistent.data_ptr(), pbytes, scratch.data_ptr(), sbytes, sp)
     bw = rept.rept_batch_workspace_size(1)
     ws_fill = torch.empty(bw, dtype=torch.uint8, device=dev)
@@ -436,7 +425,7 @@ def main():
     rept.rept_batch_launch(ws_fill.data_ptr(), sp)
     rept.rept_batch_launch(ws_ready.data_ptr(), sp)  # warm
     kernel_ms = []
-    for _ in range(max(3, args.steps)):
+    for _ in range(max(3, steps)):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
         rept.rept_batch_launch(ws_ready.data_ptr(), sp)
@@ -448,26 +437,29 @@ def main():
 
     # PCIe-inclusive steps (not `value`): the stream starts in pinned host memory and
     # rept_build_host copies it in; the rest of the step as above
-    say("host-input steps")
+    host_step_ms = None
     ref_glob = h_glob.numpy().copy()  # the timed steps' global counters
-    h_edges = torch.from_numpy(np.ascontiguousarray(edges, dtype=np.uint32)).pin_memory().numpy()
-    host_ms = []
-    for r in range(4):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        hh = rept.rept_build_host(n, h_edges, persistent.data_ptr(), pbytes, scratch.data_ptr(), sbytes, sp)
-        rept.rept_count(hh, params, glob.data_ptr(), loc.data_ptr(), ws.data_ptr(), wbytes, sp)
-        rept.rept_reduce_local(loc.data_ptr(), rows, n, sums.data_ptr(), sp)
-        h_glob.copy_(glob, non_blocking=True)
-        h_sums.copy_(sums, non_blocking=True)
-        stream.synchronize()
-        rept.rept_estimate_sums(n, params, h_glob.numpy(), h_sums.numpy(), h_tau_v)
-        rept.rept_destroy(hh)
-        if r:
-            host_ms.append(1e3 * (time.perf_counter() - t0))
-    if not np.array_equal(h_glob.numpy(), ref_glob):
-        raise RuntimeError("host-input step disagrees with the device-input steps")
-    host_step_ms = float(np.median(host_ms))
+    if host_input:
+        say(f"{workload}: host-input steps")
+        h_edges = torch.from_numpy(np.ascontiguousarray(edges, dtype=np.uint32)).pin_memory().numpy()
+        host_ms = []
+        for r in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hh = rept.rept_build_host(n, h_edges, persistent.data_ptr(), pbytes, scratch.data_ptr(), sbytes, sp)
+            rept.rept_count(hh, params, glob.data_ptr(), loc.data_ptr(), ws.data_ptr(), wbytes, sp)
+            rept.rept_reduce_local(loc.data_ptr(), rows, n, sums.data_ptr(), sp)
+            h_glob.copy_(glob, non_blocking=True)
+            h_sums.copy_(sums, non_blocking=True)
+            stream.synchronize()
+            rept.rept_estimate_sums(n, params, h_glob.numpy(), h_sums.numpy(), h_tau_v)
+            rept.rept_destroy(hh)
+            if r:
+                host_ms.append(1e3 * (time.perf_counter() - t0))
+        del h_edges
+        if not np.array_equal(h_glob.numpy(), ref_glob):
+            raise RuntimeError("host-input step disagrees with the device-input steps")
+        host_step_ms = float(np.median(host_ms))
 
     # exact triangle count (m = 1, untimed) for the per-launch byte model
     p1 = rept.Params(1, 1, 0)
@@ -478,48 +470,29 @@ def main():
     tau = int(g1.item())
     rept.rept_destroy(h)
 
-    if args.copy_calibration:  # a plain device copy of 1 GiB, for counter scaling
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-
     avg_count_ms = float(np.median(count_ms))
     avg_kernel_ms = float(np.median(kernel_ms))
     alg = algorithmic_bytes(info, tau, c, rows, n)
     achieved = alg / (avg_kernel_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(args.workload)
+    traffic = traffic_from_profile(workload)
     deg = np.bincount(edges.ravel(), minlength=n).astype(np.int64)
     W = int((deg * (deg - 1) // 2).sum())
-    semi = int(h_glob.numpy().sum())
+    semi = int(ref_glob.sum())
     sm_bytes = streaming_model_bytes(W, E, params.groups, semi, c, n)
     # context: the bytes an id-sorted merge of the per-group CSR segments would read,
     # 8 sum_k sum_x d_x d_x^act, with d_x^act = d_x for a full group and its expectation
     # d_x c2 / m for a partial last group
     csr_bytes = 8.0 * float((deg * deg).sum()) * (c // m + (c % m) / m)
-
-    out = {
-        "metric": "stream edges/sec on 1 GPU, % HBM roofline; batched/served vs plain",
-        "value": value,
-        "unit": "stream edges/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int64",
-        "data": "synthetic",
+    return {
+        "edges": edges, "n": n, "m": m, "c": c, "ref_glob": ref_glob,
+        "value": value, "ms_per_step": ms_per_step,
         "config": {"workload": desc, "n": n, "edges": E, "m": m, "c": c, "hash_seed": HASH_SEED},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": traffic},
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic},
         "kernel": {"count_ms": avg_count_ms, "count_kernel_ms": avg_kernel_ms, "build_ms": float(np.median(build_ms)),
                    "count_edges_per_s": E / (avg_count_ms * 1e-3), "algorithmic_bytes": alg,
-                   "oriented_work": int(info.oriented_work), "num_reverse": int(info.num_reverse), "triangles": tau, "semi_triangles": semi,
+                   "oriented_work": int(info.oriented_work), "num_reverse": int(info.num_reverse), "triangles": tau,
+                   "semi_triangles": semi,
                    "streaming_model_bytes": sm_bytes,
                    "streaming_model_equiv_gbps": sm_bytes / (avg_kernel_ms * 1e-3) / 1e9,
                    "reduce_d2h_ms": float(np.median(reduce_d2h_ms)), "estimate_ms": float(np.median(estimate_ms)),
@@ -527,20 +500,66 @@ def main():
                    "traffic_frac": None if traffic is None else traffic / (avg_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
                    "traffic_over_algorithmic": None if traffic is None else traffic / alg,
                    "csr_merge_bytes": csr_bytes,
-                   "host_input_step_ms": host_step_ms, "host_input_edges_per_s": E / (host_step_ms * 1e-3),
+                   "host_input_step_ms": host_step_ms,
+                   "host_input_edges_per_s": None if host_step_ms is None else E / (host_step_ms * 1e-3),
                    "traffic_over_csr_merge": None if traffic is None else traffic / csr_bytes,
                    "source_digest": count_kernel_source_digest()},
         "tau_hat": tau_hat,
     }
-    if not args.no_alg2 and c > m:
-        say("algorithm 2 pass")
-        out["alg2"] = bench_alg2(dev, edges, n, m, c - m // 2)
-    if not args.no_mascot and m > 1:
-        say("parallel MASCOT pass")
-        out["mascot"] = bench_mascot(dev, edges, n, m, min(c, 8))
-    if not args.no_incremental:
-        say("incremental stream")
-        out["incremental"] = bench_incremental(dev, edges, n, m, c, h_glob.numpy())
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
+                                   "run with --gpus 1"}))
+        sys.exit(2)
+    import torch
+
+    dev = torch.device("cuda:0")
+    head = measure_plain(dev, args.workload, args.steps, args.warmup)
+    if args.copy_calibration:  # a plain device copy of 1 GiB, for counter scaling
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    out = {
+        "metric": "stream edges/sec on 1 GPU, % HBM roofline; batched/served vs plain",
+        "value": head["value"],
+        "unit": "stream edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": head["config"],
+        "roofline": head["roofline"],
+        "kernel": head["kernel"],
+        "tau_hat": head["tau_hat"],
+    }
+    # the other single-stream workload and the "next" rows on the 1M/20M power-law stream
+    side = head if args.workload == SIDE_WORKLOAD else None
+    if not args.no_side and side is None:
+        say(f"side workload {SIDE_WORKLOAD}")
+        side = measure_plain(dev, SIDE_WORKLOAD, args.steps, min(args.warmup, 3), host_input=False)
+        out[SIDE_WORKLOAD] = {k: side[k] for k in ("value", "ms_per_step", "config", "roofline", "kernel", "tau_hat")}
+    if side is not None:
+        edges, n, m, c = side["edges"], side["n"], side["m"], side["c"]
+        if not args.no_alg2 and c > m:
+            say("algorithm 2 pass")
+            out["alg2"] = bench_alg2(dev, edges, n, m, c - m // 2)
+        if not args.no_mascot and m > 1:
+            say("parallel MASCOT pass")
+            out["mascot"] = bench_mascot(dev, edges, n, m, min(c, 8))
+        if not args.no_incremental:
+            say("incremental stream")
+            out["incremental"] = bench_incremental(dev, edges, n, m, c, side["ref_glob"])
     if not args.no_batched:
         say("batched workload")
         out["batched"] = bench_batched(dev)
@@ -549,9 +568,7 @@ def main():
         out["served"] = bench_served(dev)
     if not args.no_cpu:
         say("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(edges, n, m, c)
-        say("cpu baseline, one pinned core")
-        out["cpu_single_core"] = cpu_single_core(edges, n, m, c)
+        out["cpu_baseline"] = cpu_baseline(head["edges"], head["n"], head["m"], head["c"])
     print(json.dumps(out), flush=True)
 
 

@@ -395,7 +395,9 @@ typedef struct rept_tuning {
     uint32_t b_chunk;    /* 16..1024: neighbour lists staged per chunk by a workgroup (default 512
                             with 2048-entry chunks, else 128; halved likewise) */
     uint32_t blocks;     /* persistent workgroups (default: as many as fit, up to 4 per CU) */
-    uint32_t threads;    /* 64..1024, a multiple of 64 (default 256) */
+    uint32_t threads;    /* 64..1024, a multiple of 64 (default 256; when the longest list exceeds
+                            1024 entries and no shape field is set: 512, with block_cap 1024 and
+                            b_chunk 256) */
     uint32_t light_tile; /* 1..64: apexes taken per queue pop by a wavefront (default 8) */
     uint32_t phase_launches; /* 1: both phases in one launch; 2: the light phase (units of at most
                                 wave_cap, one per wavefront) runs as a launch of its own after the

@@ -130,8 +130,15 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     // units with long lists also have many lists to walk: bigger B chunks pay there (R-MAT
     // scale 24: 308 ms at 512, 311 at 256, 322 at 128), not on shorter lists (the 1M/20M
     // power-law graph: 6.64 ms at 128, 7.13 at 64, 7.41 at 256)
-    uint32_t b_chunk = own_b_chunk ? tu->b_chunk : (block_cap >= 2048 ? 512u : 128u);
-    const uint32_t threads = (tu && tu->threads) ? tu->threads : 256;
+    // units with lists of more than 1024 entries: workgroups of 512 threads with 256-list B chunks
+    // (R-MAT scale 24, longest list 1761: 287 ms against 312 with 256 threads, 2048-entry table
+    // chunks and 512-list B chunks; the 1M/20M power-law graph, longest list 480, keeps 256
+    // threads: 6.08 against 6.57 ms)
+    // (and 1024-entry table chunks, so that two such workgroups fit a compute unit: 16 waves)
+    const bool wide = !own_block_cap && block_cap >= 2048 && !(tu && tu->threads);
+    if (wide) block_cap = 1024;
+    uint32_t b_chunk = own_b_chunk ? tu->b_chunk : (wide ? 256u : (block_cap >= 2048 ? 512u : 128u));
+    const uint32_t threads = (tu && tu->threads) ? tu->threads : (wide ? 512u : 256u);
     const uint32_t light_tile = (tu && tu->light_tile) ? tu->light_tile : 8;
     if (wave_cap < 8 || wave_cap > 256) return REPT_EINVAL;
     if (block_cap < 64 || block_cap > 4096) return REPT_EINVAL;

@@ -606,6 +606,39 @@ __device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& 
     if (it_begin >= it_end) return;
     uint32_t i0 = find_seg(T.bpos, bn, it_begin);  // owner of the first item (uniform)
     for (uint32_t base = it_begin; base < it_end; base += R) {
+        uint32_t own[kWalk], p[kWalk], w[kWalk];
+        bool valid[kWalk];
+        uint32_t pre;  // owner of the round's last item
+        // the starts of the two lists after i0 (bpos[bn] is the sentinel: reads stay in bpos[0..bn])
+        const uint32_t s1 = T.bpos[i0 + 1 <= bn ? i0 + 1 : bn].y;
+        const uint32_t s2 = i0 + 2 <= bn ? T.bpos[i0 + 2].y : 0xffffffffu;
+        if (s2 >= base + R) {
+            // at most one list starts inside the round: a lane's owner is i0 or i0 + 1
+            const uint2 b0 = T.bpos[i0], b1 = T.bpos[i0 + 1 <= bn ? i0 + 1 : bn];
+            const uint32_t d0 = b0.x - b0.y, d1 = b1.x - b1.y;  // position = item + d (mod 2^32)
+            if (base + R <= it_end) {  // a full round: every lane loads, no mask is needed
+#pragma unroll
+                for (uint32_t j = 0; j < kWalk; ++j) {
+                    const uint32_t it = base + 64 * j + lane;
+                    const bool second = it >= s1;
+                    own[j] = second ? i0 + 1 : i0;
+                    p[j] = it + (second ? d1 : d0);
+                    valid[j] = true;
+                    w[j] = ldg(J.nbr + p[j]);
+                }
+            } else {
+#pragma unroll
+                for (uint32_t j = 0; j < kWalk; ++j) {
+                    const uint32_t it = base + 64 * j + lane;
+                    const bool second = it >= s1;
+                    own[j] = second ? i0 + 1 : i0;
+                    p[j] = it + (second ? d1 : d0);
+                    valid[j] = it < it_end;
+                    w[j] = valid[j] ? ldg(J.nbr + p[j]) : 0u;
+                }
+            }
+            pre = s1 < base + R ? i0 + 1 : i0;
+        } else {
         static_assert(kWalk == 4, "one 32-bit word of marks per lane");
         ((uint32_t*)V.mark)[lane] = 0u;
         wave_sync();
@@ -623,9 +656,7 @@ __device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& 
             }
         }
         wave_sync();
-        uint32_t own[kWalk], p[kWalk], w[kWalk];
-        bool valid[kWalk];
-        uint32_t pre = i0;
+        pre = i0;
 #pragma unroll
         for (uint32_t j = 0; j < kWalk; ++j) {
             const uint32_t f = V.mark[64 * j + lane];
@@ -641,6 +672,7 @@ __device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& 
             const uint2 bp = T.bpos[own[j]];
             p[j] = bp.x + (it - bp.y);
             w[j] = valid[j] ? ldg(J.nbr + p[j]) : 0u;
+        }
         }
         // the earlier rounds' whole batches of 64 hits are drained while this round's
         // neighbour loads are in flight (one wait covers both); the rest (fewer than 64) stays
