@@ -77,8 +77,9 @@ def stream_for(name):
 
 
 def count_kernel_source_digest() -> str:
+    """Digest of the counting kernel's sources and of the file that picks its launch shape."""
     h = hashlib.sha256()
-    for f in ("count.hip", "common.h"):
+    for f in ("count.hip", "common.h", "api.hip"):
         with open(os.path.join(ROOT, "paper_1811_09136_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
