@@ -413,10 +413,14 @@ rept_status rept_batch_workspace_size(uint32_t njobs, size_t* bytes);
 
 /*
  * Write the job table of a batch into `workspace` (device, >= rept_batch_workspace_size
- * bytes, 256-byte aligned) with one host-to-device copy on `stream`.  After it, every
- * launch of rept_batch_launch(workspace) runs this batch; the job table holds only device
- * pointers and sizes, so a launch can be captured into a HIP graph and replayed.
- * Errors: EINVAL, ENOTSUP, ENOMEM, EDEVICE.
+ * bytes, 256-byte aligned) with one host-to-device copy on `stream`, staged through pinned host
+ * memory the library keeps (no device allocation, no stream synchronisation: the call may wait
+ * only for a staging buffer's earlier copy).  The copy is stream-ordered: launches of
+ * rept_batch_launch(workspace) enqueued on `stream` after this call run this batch (a launch on
+ * another stream must first wait for `stream`), and a launch still reading the workspace's
+ * previous table on `stream` finishes before the copy overwrites it.  The job table holds only
+ * device pointers and sizes, so a launch can be captured into a HIP graph and replayed.
+ * Errors: EINVAL, ENOTSUP, ENOMEM (workspace too small, or no pinned staging memory), EDEVICE.
  */
 rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_tuning* tuning,
                                void* workspace, size_t workspace_bytes, void* stream);

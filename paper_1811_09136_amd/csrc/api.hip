@@ -760,6 +760,60 @@ rept_status rept_batch_workspace_size(uint32_t njobs, size_t* bytes) {
     return REPT_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Pinned host staging of job tables: a ring of buffers, each reused only after the copy that last
+// read it has completed (an event recorded after that copy), so rept_batch_prepare needs no
+// stream synchronisation.  Buffers grow on demand and are kept for the process.
+struct StageSlot {
+    void* buf = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    int device = -1;
+    bool pending = false;  // `done` was recorded after a copy from `buf`
+};
+constexpr int kStageSlots = 8;
+std::mutex g_stage_mu;
+StageSlot g_stage[kStageSlots];
+int g_stage_next = 0;
+
+// a slot of at least `bytes` on the current device, free to write (caller holds g_stage_mu)
+rept_status stage_slot(size_t bytes, StageSlot** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return REPT_EDEVICE;
+    StageSlot& s = g_stage[g_stage_next];
+    g_stage_next = (g_stage_next + 1) % kStageSlots;
+    if (s.pending) {
+        if (hipEventSynchronize(s.done) != hipSuccess) return REPT_EDEVICE;
+        s.pending = false;
+    }
+    if (s.device != dev && s.done) {  // events belong to the device they were created on
+        (void)hipEventDestroy(s.done);
+        s.done = nullptr;
+    }
+    if (!s.done) {
+        if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return REPT_EDEVICE;
+        s.device = dev;
+    }
+    if (s.bytes < bytes) {
+        if (s.buf) (void)hipHostFree(s.buf);
+        s.buf = nullptr;
+        s.bytes = 0;
+        const size_t want = (bytes + 65535) & ~(size_t)65535;
+        if (hipHostMalloc(&s.buf, want, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return REPT_ENOMEM;
+        }
+        s.bytes = want;
+    }
+    *out = &s;
+    return REPT_OK;
+}
+}  // namespace
+
+extern "C" {
+
 rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_tuning* tuning, void* workspace,
                                size_t workspace_bytes, void* stream) {
     size_t need = 0;
@@ -767,8 +821,12 @@ rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_
     if ((uintptr_t)workspace & 255u) return REPT_EINVAL;
     if (workspace_bytes < need) return REPT_ENOMEM;
     const size_t bytes = sizeof(BatchHeader) + (size_t)njobs * sizeof(JobDev);
-    uint8_t* host = (uint8_t*)calloc(1, bytes);
-    if (!host) return REPT_ENOMEM;
+    std::lock_guard<std::mutex> stage_lock(g_stage_mu);
+    StageSlot* slot = nullptr;
+    rept_status sst = stage_slot(bytes, &slot);
+    if (sst != REPT_OK) return sst;
+    uint8_t* host = (uint8_t*)slot->buf;
+    memset(host, 0, bytes);
     JobDev* hj = (JobDev*)(host + sizeof(BatchHeader));
     uint32_t G_max = 1, c_max = 1, max_out = 0;
     uint64_t zero_words = 0;
@@ -777,10 +835,7 @@ rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_
     for (uint32_t j = 0; j < njobs; ++j) {
         uint64_t zw = 0;
         rept_status st = make_job(jobs[j], &hj[j], &zw);
-        if (st != REPT_OK) {
-            free(host);
-            return st;
-        }
+        if (st != REPT_OK) return st;
         G_max = hj[j].G > G_max ? hj[j].G : G_max;
         c_max = hj[j].c > c_max ? hj[j].c : c_max;
         max_out = jobs[j].graph->max_out > max_out ? jobs[j].graph->max_out : max_out;
@@ -795,17 +850,16 @@ rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_
     }
     BatchHeader h;
     rept_status st = make_header(njobs, G_max, c_max, max_out, zero_words, any_zero, tuning, &h);
-    if (st != REPT_OK) {
-        free(host);
-        return st;
-    }
+    if (st != REPT_OK) return st;
     h.any_fill = any_fill ? 1u : 0u;
     h.fill_edges = fill_edges > UINT32_MAX ? UINT32_MAX : (uint32_t)fill_edges;
     memcpy(host, &h, sizeof(h));
+    // stream-ordered: launches enqueued on `stream` after this call see the table; the staging
+    // buffer is reused only after this copy's event has completed
     hipError_t e = hipMemcpyAsync(workspace, host, bytes, hipMemcpyHostToDevice, (hipStream_t)stream);
-    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);  // `host` is freed below
-    free(host);
+    if (e == hipSuccess) e = hipEventRecord(slot->done, (hipStream_t)stream);
     if (e != hipSuccess) return REPT_EDEVICE;
+    slot->pending = true;
     std::lock_guard<std::mutex> lk(g_mu);
     g_shapes[workspace] = Shape{h};
     return REPT_OK;

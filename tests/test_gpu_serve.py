@@ -84,7 +84,7 @@ def test_served_multi_million_edge_request_against_oracle(cuda):
         e, n = synth.scaled_chung_lu(r["E"], r["graph_seed"] % (2**31))
         reqs.append(Request(i, 0.002 + r["arrival_s"], e, n, r["m"], r["c"], r["hash_seed"]))
     _say(f"serving a {len(e_big)}-edge request with {len(reqs) - 1} smaller ones")
-    ex = DeviceExecutor("cuda:0")
+    ex = DeviceExecutor("cuda:0", arena_bytes=4 << 30)  # buffers from an arena (with fallback)
     srv = Server(ex, budget_bytes=32 << 30, max_active=16, chunk_units=2048, build_workers=2)
     res = srv.run(reqs)
     assert all(r.status == "ok" for r in res), [r.status for r in res]

@@ -164,3 +164,22 @@ def test_failed_build_frees_budget_for_waiting_requests():
     res = srv.run(reqs, clock=clk, sleep=clk.sleep)
     assert res[0].status.startswith("failed")
     assert [r.status for r in res[1:]] == ["ok"] * (len(reqs) - 1)
+
+
+def test_arena_first_fit_and_coalescing():
+    """The serving executor's arena (CPU part: offsets only) hands out aligned, disjoint ranges
+    and merges freed neighbours back into one range."""
+    from paper_1811_09136_amd import serve
+    a = serve.Arena.__new__(serve.Arena)
+    a.size, a.free, a.lock = 4096, [(0, 4096)], threading.Lock()
+    x = a.alloc(100)
+    y = a.alloc(300)
+    z = a.alloc(256)
+    assert x == (0, 256) and y == (256, 512) and z == (768, 256)
+    assert a.alloc(4096) is None
+    a.release(*y)
+    assert a.alloc(512) == (256, 512)  # first fit reuses the hole
+    a.release(256, 512)
+    a.release(*x)
+    a.release(*z)
+    assert a.free == [(0, 4096)]
