@@ -236,6 +236,16 @@ class DeviceExecutor:
 
 # ------------------------------------------------------------------------------- scheduler
 
+def _nap(now, sleep, t_target: float):
+    """One step of a wait until t_target: a coarse sleep while far from it, then yields, so the
+    wake-up is not late by the OS timer's slack (tens of microseconds).  Callers loop on it."""
+    left = t_target - now()
+    if left > 3e-4:
+        sleep(min(0.05, left - 2e-4))
+    elif left > 0:
+        sleep(0)
+
+
 @dataclass
 class Server:
     executor: object
@@ -245,6 +255,7 @@ class Server:
     build_workers: int = 2
     max_inflight: int = 2       # batched launches queued on the device at once
     finish_workers: int = 2     # threads that copy results back and free requests
+    hold_lone_newcomer: bool = True  # see the admission below
     results: dict = field(default_factory=dict)
     trace: list = field(default_factory=list)
 
@@ -266,16 +277,25 @@ class Server:
         pool = cf.ThreadPoolExecutor(max_workers=self.build_workers)
         fpool = cf.ThreadPoolExecutor(max_workers=self.finish_workers)
 
+        # the workers stamp their own completion times, so a result is not made later by the
+        # scheduler being busy elsewhere when the worker ends
+        def build_job(r):
+            state = ex.build(r)
+            self.results[r.rid].built_s = now()
+            return state
+
+        def retire(r, state):
+            res = self.results[r.rid]
+            try:
+                res.glob, res.loc, res.tau_hat = ex.finish(state)
+            except Exception as exc:  # pragma: no cover - a device error while copying back
+                res.status = f"failed: {exc}"
+            res.done_s = now()
+
         def done_finishing():
             nonlocal used
             for fut in [f for f in finishing if f.done()]:
-                r, need = finishing.pop(fut)
-                res = self.results[r.rid]
-                try:
-                    res.glob, res.loc, res.tau_hat = fut.result()
-                except Exception as exc:  # pragma: no cover - a device error while copying back
-                    res.status = f"failed: {exc}"
-                res.done_s = now()
+                _, need = finishing.pop(fut)
                 used -= need
 
         try:
@@ -298,24 +318,23 @@ class Server:
                         res.status, res.done_s = f"failed: {exc}", now()
                         used -= need
                         continue
-                    res.built_s = now()
                     if ex.units(state) == 0:
-                        finishing[fpool.submit(ex.finish, state)] = (r, need)
+                        finishing[fpool.submit(retire, r, state)] = (r, need)
                     else:
                         active.append([r, state, need])
                 # requests whose last launch completed are retired by the finish workers, or here
-                # when nothing else is in the system (no hand-off to add to the latency)
+                # when nothing else needs the scheduler but at most one newcomer (held back by the
+                # admission below): no hand-off to add to the latency, and the newcomer's build
+                # does not share the host with this copy-back
                 still = []
                 for r, state, need, tok in draining:
                     if ready(tok):
                         progressed = True
-                        if not (active or building or finishing or waiting) and len(draining) == 1:
-                            res = self.results[r.rid]
-                            res.glob, res.loc, res.tau_hat = ex.finish(state)
-                            res.done_s = now()
+                        if not (active or building) and len(waiting) <= 1 and len(draining) == 1:
+                            retire(r, state)
                             used -= need
                         else:
-                            finishing[fpool.submit(ex.finish, state)] = (r, need)
+                            finishing[fpool.submit(retire, r, state)] = (r, need)
                     else:
                         still.append([r, state, need, tok])
                 draining = still
@@ -335,12 +354,22 @@ class Server:
                         continue
                     if used + need > self.budget_bytes:
                         break
+                    if self.hold_lone_newcomer and len(waiting) == 1 and not building and (
+                            (len(draining) == 1 and not active and inflight)
+                            or (len(active) == 1 and not draining
+                                and ex.units(active[0][1]) - active[0][1]["cursor"] <= self.chunk_units)):
+                        # the one request in service has all its remaining work in one launch
+                        # (enqueued, or about to be): a newcomer alone behind it would gain nothing
+                        # from building now (its build kernels would only compete with that launch
+                        # for the compute units and slow both), so it is admitted when that
+                        # launch completes
+                        break
                     waiting.popleft()
                     used += need
                     res = self.results[r.rid]
                     res.admitted_s = now()
                     progressed = True
-                    if not (active or building or draining or finishing or waiting):
+                    if not (active or building or draining or waiting):
                         # alone in the system: build here, without a hand-off to a worker
                         try:
                             state = ex.build(r)
@@ -350,13 +379,12 @@ class Server:
                             continue
                         res.built_s = now()
                         if ex.units(state) == 0:
-                            res.glob, res.loc, res.tau_hat = ex.finish(state)
-                            res.done_s = now()
+                            retire(r, state)
                             used -= need
                         else:
                             active.append([r, state, need])
                     else:
-                        building[pool.submit(ex.build, r)] = (r, need)
+                        building[pool.submit(build_job, r)] = (r, need)
                 while inflight and ready(inflight[0]):
                     inflight.popleft()
                 if active and len(inflight) < self.max_inflight:
@@ -382,7 +410,13 @@ class Server:
                     continue
                 # nothing moved: wait for the event that comes first
                 if inflight and (active or draining):
-                    wait(inflight[0])
+                    tok = inflight[0]
+                    if pending:
+                        # the oldest launch, or the next arrival if it comes first
+                        while not ready(tok) and now() < pending[0].arrival_s:
+                            sleep(0)
+                    else:
+                        wait(tok)
                 elif building:
                     cf.wait(list(building), timeout=0.002, return_when=cf.FIRST_COMPLETED)
                 elif finishing:
@@ -390,7 +424,7 @@ class Server:
                 elif draining:
                     wait(draining[0][3])
                 elif pending and not waiting:
-                    sleep(max(0.0, min(0.05, pending[0].arrival_s - now())))
+                    _nap(now, sleep, pending[0].arrival_s)
                 elif waiting:
                     # nothing holds budget or a slot, yet the head request was not admitted
                     raise RuntimeError(f"scheduler stalled: {len(waiting)} waiting, {used} bytes held")
@@ -407,7 +441,7 @@ def run_fifo_plain(executor, requests: list, clock=time.monotonic, sleep=time.sl
     now = lambda: clock() - t_start
     for r in sorted(requests, key=lambda r: r.arrival_s):
         while now() < r.arrival_s:
-            sleep(min(0.05, r.arrival_s - now()))
+            _nap(now, sleep, r.arrival_s)
         res = Result(r.rid, r.arrival_s, admitted_s=now())
         try:
             state = executor.build(r)
