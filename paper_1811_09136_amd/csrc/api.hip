@@ -122,48 +122,83 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     uint32_t fit = 64;
     // one W chunk per unit up to 2048 entries: re-walking a unit's B lists per extra chunk
     // costs more than the occupancy a smaller table would buy (R-MAT scale 24, largest list
-    // 1761: 322 ms at 2048, 338 at 1024, 450 at 512; 559 at 4096, one workgroup per CU)
+    // 1761, 256-thread workgroups: 322 ms at 2048, 338 at 1024, 450 at 512; 559 at 4096, one
+    // workgroup per CU)
     while (fit < max_out && fit < 2048) fit <<= 1;
     const bool own_block_cap = tu && tu->block_cap, own_b_chunk = tu && tu->b_chunk;
-    const uint32_t wave_cap = (tu && tu->wave_cap) ? tu->wave_cap : 64;
     uint32_t block_cap = own_block_cap ? tu->block_cap : fit;
-    // units with long lists also have many lists to walk: bigger B chunks pay there (R-MAT
-    // scale 24: 308 ms at 512, 311 at 256, 322 at 128), not on shorter lists (the 1M/20M
-    // power-law graph: 6.64 ms at 128, 7.13 at 64, 7.41 at 256)
-    // units with lists of more than 1024 entries: workgroups of 512 threads with 256-list B chunks
-    // (R-MAT scale 24, longest list 1761: 287 ms against 312 with 256 threads, 2048-entry table
-    // chunks and 512-list B chunks; the 1M/20M power-law graph, longest list 480, keeps 256
-    // threads: 6.08 against 6.57 ms)
-    // (and 1024-entry table chunks, so that two such workgroups fit a compute unit: 16 waves)
+    // Lists of more than 1024 entries: one workgroup of 1024 threads per compute unit (16 waves),
+    // one 2048-entry table chunk (no second walk of a unit's B lists below 2048 entries),
+    // 1024-list B chunks, and units of up to 128 entries left to single wavefronts (R-MAT scale
+    // 24, longest list 1761: 198 ms; 274 with 512-thread workgroups, 1024-entry table chunks and
+    // 256-list B chunks, two workgroups per compute unit; 206 with 512-list B chunks; 210 with
+    // units above 64 entries given to workgroups).  Shorter lists keep 256-thread workgroups
+    // (the 1M/20M power-law graph, longest list 480: 5.99 ms; 8.5-10.8 with 1024 threads).
     const bool wide = !own_block_cap && block_cap >= 2048 && !(tu && tu->threads);
-    if (wide) block_cap = 1024;
-    uint32_t b_chunk = own_b_chunk ? tu->b_chunk : (wide ? 256u : (block_cap >= 2048 ? 512u : 128u));
-    const uint32_t threads = (tu && tu->threads) ? tu->threads : (wide ? 512u : 256u);
+    const bool own_wave_cap = tu && tu->wave_cap;
+    uint32_t wave_cap = own_wave_cap ? tu->wave_cap : (wide ? 128u : 64u);
+    // units with long lists also have many lists to walk: bigger B chunks pay there, not on
+    // shorter lists (the 1M/20M power-law graph: 6.64 ms at 128, 7.13 at 64, 7.41 at 256)
+    uint32_t b_chunk = own_b_chunk ? tu->b_chunk : (wide ? 1024u : (block_cap >= 2048 ? 512u : 128u));
+    const uint32_t threads = (tu && tu->threads) ? tu->threads : (wide ? 1024u : 256u);
     const uint32_t light_tile = (tu && tu->light_tile) ? tu->light_tile : 8;
     if (wave_cap < 8 || wave_cap > 256) return REPT_EINVAL;
     if (block_cap < 64 || block_cap > 4096) return REPT_EINVAL;
     if (b_chunk < 16 || b_chunk > 1024) return REPT_EINVAL;
     if (threads < 64 || threads > 1024 || threads % 64) return REPT_EINVAL;
     if (light_tile < 1 || light_tile > 64) return REPT_EINVAL;  // one unit per lane of a wavefront
+    const uint32_t pl = tu ? tu->phase_launches : 0u;
+    if (pl > 3 || (tu && tu->reserved)) return REPT_EINVAL;
+    // default (0): the light phase in a launch of its own, on a second stream
+    const bool split = pl != 1;
+    // A light launch of its own needs no heavy team area, and a heavy launch then needs no light
+    // areas.  The light launch keeps the heavy launch's workgroup size where its wavefronts' areas
+    // fit; beside 1024-thread heavy workgroups whose light areas do not (more than one hash
+    // group), it takes 256-thread ones, whose LDS holds four wavefronts' areas while the
+    // registers still allow 16 waves per CU (R-MAT scale 24, one group: 198 ms with 1024-thread
+    // light workgroups, which fit with two hash slots per key; 200 with 256-thread ones, four
+    // slots per key, three per CU; 205 with 512)
+    uint32_t light_threads = threads;
     const uint32_t hist_c = c_max <= REPT_HIST_CAP ? c_max : 0;
-    // the light phase's hash tables are sparser (fewer probes) where the LDS budget allows;
-    // past the budget, the sparser tables go first, then the default chunk sizes shrink
-    // (a shape the caller chose is never changed: it is refused if it does not fit)
+    // the light phase's hash tables are sparser (fewer probes) where the LDS budget allows
     uint32_t light_table = 4;
-    uint32_t lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table, eta);
-    // default chunks keep two workgroups per CU where they can (down to 128 lists, 1024 entries)
-    while (lds > 80 * 1024 - 256 && ((!own_b_chunk && b_chunk > 128) || (!own_block_cap && block_cap > 1024))) {
+    auto heavy_lds = [&]() {  // the launch that runs the heavy phase (both phases if not split)
+        return rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table, eta, true, !split);
+    };
+    auto light_lds = [&]() {  // the light areas alone, in the launch that holds them
+        return rept_count_lds(split ? light_threads : threads, wave_cap, block_cap, b_chunk, G_max, hist_c,
+                              light_table, eta, false, true);
+    };
+    // Past the 160 KB of a CU (static LDS takes a few bytes more), the light areas shrink first
+    // (sparser tables, then smaller light workgroups, then a default wave cap halved down to 64),
+    // then the default heavy chunk sizes.  A shape the caller chose is never changed: it is
+    // refused if it does not fit.
+    const uint32_t cap = 160 * 1024 - 256;
+    while (light_lds() > cap) {
+        if (light_table == 4) {
+            light_table = 2;
+        } else if (split && wide && light_threads > 256) {
+            light_threads = 256;
+            light_table = 4;
+        } else if (!own_wave_cap && wave_cap > 64) {
+            wave_cap >>= 1;
+        } else {
+            return REPT_EINVAL;
+        }
+    }
+    // default chunks keep two workgroups per CU where they can (down to 128 lists, 1024 entries);
+    // a 1024-thread workgroup has a compute unit to itself anyway
+    while (threads <= 512 && heavy_lds() > 80 * 1024 - 256 &&
+           ((!own_b_chunk && b_chunk > 128) || (!own_block_cap && block_cap > 1024))) {
         if (!own_b_chunk && b_chunk > 128) b_chunk >>= 1;
         else block_cap >>= 1;
-        lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table, eta);
     }
-    while (lds > 160 * 1024 - 256) {  // static LDS takes a few bytes more
-        if (light_table == 4) light_table = 2;
-        else if (!own_b_chunk && b_chunk > 128) b_chunk >>= 1;
+    while (heavy_lds() > cap) {
+        if (!own_b_chunk && b_chunk > 128) b_chunk >>= 1;
         else if (!own_block_cap && block_cap > 64) block_cap >>= 1;
         else return REPT_EINVAL;
-        lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table, eta);
     }
+    const uint32_t lds = heavy_lds();
     uint32_t blocks = tu ? tu->blocks : 0;
     if (!blocks) {
         uint32_t per_cu = rept_count_blocks_per_cu(threads, lds, eta);
@@ -185,15 +220,12 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     h->any_zero = any_zero ? 1u : 0u;
     h->any_eta = eta ? 1u : 0u;
     h->zero_words = zero_words;
-    // the light phase in a launch of its own: the same workgroup size, no heavy team area
-    const uint32_t pl = tu ? tu->phase_launches : 0u;
-    if (pl > 3 || (tu && tu->reserved)) return REPT_EINVAL;
-    h->split = pl != 1 ? 1u : 0u;
-    h->split_streams = (pl == 0 || pl == 3) ? 1u : 0u;  // default (0): two launches, two streams
+    h->split = split ? 1u : 0u;
+    h->split_streams = (pl == 0 || pl == 3) ? 1u : 0u;
     if (h->split) {
-        h->light_threads = threads;
-        h->light_lds = rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table, eta, false);
-        uint32_t per_cu = rept_count_blocks_per_cu(threads, h->light_lds, eta);
+        h->light_threads = light_threads;
+        h->light_lds = light_lds();
+        uint32_t per_cu = rept_count_blocks_per_cu(light_threads, h->light_lds, eta);
         if (per_cu == 0) per_cu = 1;
         if (per_cu > 8) per_cu = 8;
         h->light_blocks = (tu && tu->blocks) ? tu->blocks : per_cu * cus;

@@ -148,9 +148,10 @@ hipError_t rept_launch_reduce(const int64_t* local, uint32_t rows, uint32_t n, i
 hipError_t rept_launch_slots(const uint64_t* hp, uint32_t G, uint32_t m, const uint32_t* edges,
                              uint64_t E, uint32_t* slots, hipStream_t stream);
 // LDS bytes of the counting kernel for a launch shape (eta: the form with Algorithm 2's counters;
-// heavy: the launch runs the heavy phase, whose team area shares the LDS with the light areas)
+// heavy / light: the launch runs the heavy / light phase; a launch running both shares one LDS
+// region between the heavy team area and the wavefronts' light areas)
 uint32_t rept_count_lds(uint32_t threads, uint32_t wave_cap, uint32_t block_cap, uint32_t b_chunk, uint32_t G,
-                        uint32_t hist_c, uint32_t light_table, bool eta, bool heavy = true);
+                        uint32_t hist_c, uint32_t light_table, bool eta, bool heavy = true, bool light = true);
 // resident workgroups per CU of the counting kernel for a launch shape (0 if unknown)
 uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes, bool eta);
 uint32_t rept_num_cus();

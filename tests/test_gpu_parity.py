@@ -367,6 +367,41 @@ def test_default_shape_shrinks_to_fit(cuda):
     assert outs[0][0].sum() > 0 and outs[0][1].sum() == 3 * outs[0][0].sum()
 
 
+
+@pytest.mark.parametrize("kind", ["two_groups", "alg2", "mascot"])
+def test_wide_default_shape_equals_small_shape(cuda, kind):
+    """Lists of more than 1024 entries take the wide default shape (1024-thread workgroups, one
+    2048-entry table chunk, 1024-list B chunks, the light launch sized to fit its LDS). With two
+    hash groups, with Algorithm 2's pair counters and with MASCOT's keep masks, its counts equal
+    those of an explicit small shape (which the other tests check against the oracle)."""
+    import torch
+    from paper_1811_09136_amd import rept
+    n = 1100
+    e = synth.shuffled(synth.complete(n), 77, flip_seed=78)
+    g = rept.Graph(rept.to_device_edges(e, cuda), n)
+    assert g.info.max_out_degree > 1024
+    small = rept.tuning(wave_cap=32, block_cap=256, b_chunk=64, threads=256)
+    outs = []
+    for tune in (None, small):
+        _say(f"K_{n} E={len(e)} {kind} shape={'default' if tune is None else 'small'}")
+        if kind == "alg2":
+            glob, loc, eta, eta_v = g.count_eta(rept.Params(2, 3, 13), tuning=tune)
+            torch.cuda.synchronize()
+            outs.append([x.cpu().numpy() for x in (glob, loc, eta, eta_v)])
+            continue
+        p = rept.Params(2, 8, 13, mascot=True) if kind == "mascot" else rept.Params(10, 20, 13)
+        out = g.outputs(p)
+        out[0].zero_()
+        out[1].zero_()
+        job = rept.make_job(g, p, out, g.new_workspace(p), accumulate=True)
+        ws = torch.empty(rept.rept_batch_workspace_size(1), dtype=torch.uint8, device=cuda)
+        rept.rept_batch_count([job], tune, ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        outs.append([out[0].cpu().numpy(), out[1].cpu().numpy()])
+    g.close()
+    assert all(np.array_equal(a, b) for a, b in zip(outs[0], outs[1]))
+    assert outs[0][0].sum() > 0
+
 def test_build_from_host_stream(cuda):
     """A host-resident stream built with rept_build_host: the same graph statistics as the
     device-input build and the oracle's counts; an invalid stream is reported as from the
