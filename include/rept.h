@@ -387,17 +387,23 @@ typedef struct rept_job {
  * workgroup (units whose size exceeds wave_cap), then one unit per wavefront.  The LDS
  * footprint of a shape must fit the 160 KB of a compute unit (EINVAL otherwise). */
 typedef struct rept_tuning {
-    uint32_t wave_cap;   /* 8..256: largest unit counted by one wavefront (default 64); a unit's
-                            size is max(its list length, its reverse-list length / 8) */
+    uint32_t wave_cap;   /* 8..256: largest unit counted by one wavefront (default 64, or 128 with
+                            the wide shape below; halved down to 64 if the light phase's LDS
+                            would not fit); a unit's size is max(its list length, its
+                            reverse-list length / 8) */
     uint32_t block_cap;  /* 64..4096: apex entries hashed in LDS per chunk by a workgroup (default:
-                            smallest power of two >= the graphs' largest out-degree, at most 2048,
-                            halved while a workgroup would need more than half the LDS) */
+                            smallest power of two >= the graphs' largest out-degree, at most 2048;
+                            with workgroups of up to 512 threads, halved down to 1024 while a
+                            workgroup would need more than half the LDS, and below that while
+                            it would not fit) */
     uint32_t b_chunk;    /* 16..1024: neighbour lists staged per chunk by a workgroup (default 512
-                            with 2048-entry chunks, else 128; halved likewise) */
+                            with 2048-entry chunks, else 128; 1024 with the wide shape; halved
+                            likewise, before block_cap) */
     uint32_t blocks;     /* persistent workgroups (default: as many as fit, up to 4 per CU) */
-    uint32_t threads;    /* 64..1024, a multiple of 64 (default 256; when the longest list exceeds
-                            1024 entries and no shape field is set: 512, with block_cap 1024 and
-                            b_chunk 256) */
+    uint32_t threads;    /* 64..1024, a multiple of 64 (default 256; the wide shape, taken when
+                            the longest list exceeds 1024 entries and none of block_cap and
+                            threads is set: 1024, with block_cap 2048, b_chunk 1024 and
+                            wave_cap 128) */
     uint32_t light_tile; /* 1..64: apexes taken per queue pop by a wavefront (default 8) */
     uint32_t phase_launches; /* 1: both phases in one launch; 2: the light phase (units of at most
                                 wave_cap, one per wavefront) runs as a launch of its own after the

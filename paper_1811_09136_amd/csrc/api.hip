@@ -161,13 +161,14 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     uint32_t light_threads = threads;
     const uint32_t hist_c = c_max <= REPT_HIST_CAP ? c_max : 0;
     // the light phase's hash tables are sparser (fewer probes) where the LDS budget allows
-    uint32_t light_table = 4;
+    uint32_t light_table = 4, heavy_table = 2;
     auto heavy_lds = [&]() {  // the launch that runs the heavy phase (both phases if not split)
-        return rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table, eta, true, !split);
+        return rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table, heavy_table, eta,
+                              true, !split);
     };
     auto light_lds = [&]() {  // the light areas alone, in the launch that holds them
         return rept_count_lds(split ? light_threads : threads, wave_cap, block_cap, b_chunk, G_max, hist_c,
-                              light_table, eta, false, true);
+                              light_table, heavy_table, eta, false, true);
     };
     // Past the 160 KB of a CU (static LDS takes a few bytes more), the light areas shrink first
     // (sparser tables, then smaller light workgroups, then a default wave cap halved down to 64),
@@ -198,14 +199,24 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
         else if (!own_block_cap && block_cap > 64) block_cap >>= 1;
         else return REPT_EINVAL;
     }
+    auto resident = [&](uint32_t bytes) {  // workgroups per CU, as the default grid counts them
+        uint32_t per_cu = rept_count_blocks_per_cu(threads, bytes, eta);
+        if (per_cu == 0) per_cu = 1;
+        return per_cu > 4 ? 4u : per_cu;
+    };
+    // Sparser heavy tables (four slots per key: fewer probes past the first bucket) where they
+    // fit and cost no resident workgroup (R-MAT scale 24, one 1024-thread workgroup per CU
+    // either way: 179 against 198 ms; the 1M/20M power-law graph would drop from four 256-thread
+    // workgroups per CU to three: 7.04 against 5.99 ms)
+    {
+        const uint32_t per_cu2 = resident(heavy_lds());
+        heavy_table = 4;
+        const uint32_t lds4 = heavy_lds();
+        if (lds4 > cap || resident(lds4) < per_cu2) heavy_table = 2;
+    }
     const uint32_t lds = heavy_lds();
     uint32_t blocks = tu ? tu->blocks : 0;
-    if (!blocks) {
-        uint32_t per_cu = rept_count_blocks_per_cu(threads, lds, eta);
-        if (per_cu == 0) per_cu = 1;
-        if (per_cu > 4) per_cu = 4;
-        blocks = per_cu * cus;
-    }
+    if (!blocks) blocks = resident(lds) * cus;
     h->njobs = njobs;
     h->wave_cap = wave_cap;
     h->block_cap = block_cap;
@@ -217,6 +228,7 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     h->G_max = G_max;
     h->lds_bytes = lds;
     h->light_table = light_table;
+    h->heavy_table = heavy_table;
     h->any_zero = any_zero ? 1u : 0u;
     h->any_eta = eta ? 1u : 0u;
     h->zero_words = zero_words;

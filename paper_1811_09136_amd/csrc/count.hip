@@ -38,7 +38,6 @@ namespace {
 constexpr uint32_t kHashMul = 0x9E3779B1u;  // table index: Fibonacci hashing of the node id
 constexpr uint32_t kWalk = 4;                // windows of 64 entries walked per round
 constexpr uint32_t kQueue = 64 * (kWalk + 1);  // per-wavefront hit queue: < 64 left + one round
-constexpr uint32_t kHeavyTable = 2;          // hash slots per key, at least (heavy phase)
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -138,11 +137,11 @@ struct Layout {
     uint32_t union_off, total;
 };
 __host__ __device__ inline Layout count_layout(uint32_t nwaves, uint32_t DL, uint32_t DW, uint32_t DB,
-                                               uint32_t G, uint32_t HC, uint32_t LT, bool eta, bool heavy,
-                                               bool light) {
+                                               uint32_t G, uint32_t HC, uint32_t LT, uint32_t HT, bool eta,
+                                               bool heavy, bool light) {
     Layout L;
     L.misc = misc_layout(HC);
-    L.heavy = area_layout(DW, DB, G, kHeavyTable, eta);
+    L.heavy = area_layout(DW, DB, G, HT, eta);
     L.light = area_layout(DL, DL, G, LT, eta);
     L.union_off = nwaves * L.misc.bytes;
     // a launch holds only the areas of the phases it runs
@@ -1195,8 +1194,8 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const uint32_t DL = hdr->wave_cap, DW = hdr->block_cap, DB = hdr->b_chunk;
     const uint32_t GM = hdr->G_max, HC = hdr->hist_c, njobs = hdr->njobs;
-    const uint32_t LT = hdr->light_table;
-    const Layout L = count_layout(nw, DL, DW, DB, GM, HC, LT, ETA, (phases & 1u) != 0, (phases & 2u) != 0);
+    const uint32_t LT = hdr->light_table, HT = hdr->heavy_table;
+    const Layout L = count_layout(nw, DL, DW, DB, GM, HC, LT, HT, ETA, (phases & 1u) != 0, (phases & 2u) != 0);
     const WaveView V = wave_view(lds + wid * L.misc.bytes, L.misc);
     uint8_t* uni = lds + L.union_off;
     __shared__ uint32_t s_tile;
@@ -1208,7 +1207,7 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
 
     // phase 1: long lists, one apex per workgroup
     if (phases & 1u) {
-        const TeamView T = team_view(uni, L.heavy, DW, DB, kHeavyTable);
+        const TeamView T = team_view(uni, L.heavy, DW, DB, HT);
         const uint32_t total = hdr->heavy_total;
         uint32_t q = blockIdx.x % kQueues, left = kQueues;  // used by thread 0
         for (;;) {
@@ -1393,8 +1392,10 @@ hipError_t launch_common(uint8_t* ws, const BatchHeader& h, hipStream_t s) {
 }  // namespace
 
 uint32_t rept_count_lds(uint32_t threads, uint32_t wave_cap, uint32_t block_cap, uint32_t b_chunk, uint32_t G,
-                        uint32_t hist_c, uint32_t light_table, bool eta, bool heavy, bool light) {
-    return count_layout(threads / 64, wave_cap, block_cap, b_chunk, G, hist_c, light_table, eta, heavy, light).total;
+                        uint32_t hist_c, uint32_t light_table, uint32_t heavy_table, bool eta, bool heavy,
+                        bool light) {
+    return count_layout(threads / 64, wave_cap, block_cap, b_chunk, G, hist_c, light_table, heavy_table, eta, heavy,
+                        light).total;
 }
 
 uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes, bool eta) {
