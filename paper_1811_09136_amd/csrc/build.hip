@@ -20,7 +20,8 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 constexpr int MEDIUM_MAX = 4096;  // segments sorted in LDS by one workgroup
-constexpr int SMALL_MAX = 64;     // segments sorted in registers by one wavefront
+constexpr int WAVE_MAX = 1024;    // segments sorted in registers by one wavefront each
+constexpr int SMALL_MAX = 64;     // segments sorted in registers, several per wavefront
 
 __device__ __forceinline__ bool rank_less(uint32_t x, uint32_t dx, uint32_t y, uint32_t dy) {
     return dx < dy || (dx == dy && x < y);
@@ -416,7 +417,8 @@ __global__ void k_slice_base(uint32_t* __restrict__ scount, const uint32_t* __re
     }
 }
 
-// place the slice's entries in their segments (as k_scatter below, with LDS cursors)
+// place the slice's entries in their segments (as k_scatter below, with LDS cursors); with
+// `rcnt`, also count the reverse pairs per target shard (the shard path of the reverse lists)
 constexpr uint32_t REV_BIT = 0x80000000u;
 __global__ void __launch_bounds__(1024) k_slice_place(const uint4* __restrict__ opart,
                                                       const uint32_t* __restrict__ boff, uint32_t nblk, uint32_t NB,
@@ -442,11 +444,77 @@ __global__ void __launch_bounds__(1024) k_slice_place(const uint4* __restrict__ 
         const bool rev = da < db;
         packed[pos] = ((unsigned long long)e.y << 32) | (rev ? REV_BIT : 0u) | e.z;
         work += db <= da ? db : da;
-        if (rev) atomicAdd(&rcnt[(uint64_t)e.y * REV_SHARDS + (e.x % REV_SHARDS)], 1u);
+        if (rev && rcnt) atomicAdd(&rcnt[(uint64_t)e.y * REV_SHARDS + (e.x % REV_SHARDS)], 1u);
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) work += __shfl_xor(work, d, 64);
     if ((threadIdx.x & 63) == 0 && work) atomicAdd(&st->work, work);
+}
+
+// ---- reverse lists by a bucketed transpose (bucket spans of at most DEG_SUB ids): after the
+// segment sorts, which mark each reverse pair's source at its adjacency position p, the pairs are
+// partitioned by the id bucket of their target b, counted per target in LDS by the placement
+// slices above, and placed with LDS cursors: one scan gives roff, and no global atomic touches a
+// target's counter.
+
+// per workgroup, the histogram of the target buckets of the reverse pairs in its range of
+// adjacency positions (positions past off[n], the placed entries, are never read)
+__global__ void __launch_bounds__(1024) k_rev_hist(const uint32_t* __restrict__ rsrc, const uint32_t* __restrict__ nbr,
+                                                   const uint32_t* __restrict__ off, uint32_t n, uint32_t shift,
+                                                   uint32_t NB, uint64_t per_block, uint32_t* __restrict__ bhist) {
+    __shared__ uint32_t h[DEG_BUCKETS];
+    for (uint32_t i = threadIdx.x; i < NB; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const uint64_t total = off[n];
+    const uint64_t e0 = (uint64_t)blockIdx.x * per_block;
+    const uint64_t e1 = (e0 + per_block) < total ? (e0 + per_block) : total;
+    for (uint64_t q = e0 + threadIdx.x; q < e1; q += blockDim.x)
+        if (rsrc[q] != NO_EDGE) atomicAdd(&h[nbr[q] >> shift], 1u);
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < NB; b += blockDim.x) bhist[(uint64_t)b * gridDim.x + blockIdx.x] = h[b];
+}
+
+// the reverse pairs (b, a, t, p) in bucket order of b (order within a bucket is free)
+__global__ void __launch_bounds__(1024) k_rev_part(const uint32_t* __restrict__ rsrc, const uint32_t* __restrict__ nbr,
+                                                   const uint32_t* __restrict__ tim, const uint32_t* __restrict__ off,
+                                                   uint32_t n, uint32_t shift, uint32_t NB, uint64_t per_block,
+                                                   const uint32_t* __restrict__ boff, uint4* __restrict__ rpart) {
+    __shared__ uint32_t base[DEG_BUCKETS];
+    for (uint32_t b = threadIdx.x; b < NB; b += blockDim.x) base[b] = boff[(uint64_t)b * gridDim.x + blockIdx.x];
+    __syncthreads();
+    const uint64_t total = off[n];
+    const uint64_t e0 = (uint64_t)blockIdx.x * per_block;
+    const uint64_t e1 = (e0 + per_block) < total ? (e0 + per_block) : total;
+    for (uint64_t q = e0 + threadIdx.x; q < e1; q += blockDim.x) {
+        const uint32_t a = rsrc[q];
+        if (a == NO_EDGE) continue;
+        const uint32_t b = nbr[q];
+        rpart[atomicAdd(&base[b >> shift], 1u)] = make_uint4(b, a, tim[q], (uint32_t)q);
+    }
+}
+
+// place the slice's reverse pairs in their targets' lists: the record (a, t, offset and length of
+// out(a)) and the pair's adjacency position
+__global__ void __launch_bounds__(1024) k_rev_place(const uint4* __restrict__ rpart, const uint32_t* __restrict__ boff,
+                                                    uint32_t nblk, uint32_t NB, uint32_t shift,
+                                                    const uint32_t* __restrict__ slice_off,
+                                                    const uint32_t* __restrict__ sbase, const uint32_t* __restrict__ off,
+                                                    uint4* __restrict__ rrec, uint32_t* __restrict__ rpos) {
+    __shared__ uint32_t cur[DEG_SUB];
+    uint32_t b;
+    uint64_t lo, hi;
+    if (!slice_of(blockIdx.x, slice_off, boff, nblk, NB, b, lo, hi)) return;
+    const uint32_t span = 1u << shift, v0 = b << shift;
+    const uint32_t* base = sbase + (uint64_t)blockIdx.x * span;
+    for (uint32_t i = threadIdx.x; i < span; i += blockDim.x) cur[i] = base[i];
+    __syncthreads();
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const uint4 e = rpart[i];
+        const uint32_t q = atomicAdd(&cur[e.x - v0], 1u);
+        const uint32_t s = off[e.y];
+        rrec[q] = make_uint4(e.y, e.z, s, off[e.y + 1] - s);
+        rpos[q] = e.w;
+    }
 }
 
 // The placement pass takes EDGE_UNROLL edges per thread per step, one grid stride apart, so the
@@ -522,8 +590,8 @@ __device__ __forceinline__ void node_range(uint32_t n, uint32_t& a0, uint32_t& a
     if (a0 > n) a0 = n;
 }
 
-// classify segments by size (sort path), histogram apexes by out-degree for the descending
-// apex order (bucket n-1-d), and the statistics of the oriented graph
+// classify segments by size (sort path: `medium` lists the wavefront class from its front and the
+// workgroup class from its back), and the statistics of the oriented graph
 // unit order key of node a (REPT_REV_SHIFT), at most n - 1; units are ordered by it, descending,
 // and the counting pass gives a workgroup to the units whose key exceeds its wavefront cap
 __device__ __forceinline__ uint32_t unit_key(const uint32_t* __restrict__ off, const uint32_t* __restrict__ roff,
@@ -533,14 +601,10 @@ __device__ __forceinline__ uint32_t unit_key(const uint32_t* __restrict__ off, c
     return k < n - 1 ? k : n - 1;
 }
 
-__global__ void __launch_bounds__(SCAN_THREADS) k_classify(const uint32_t* __restrict__ off,
-                                                           const uint32_t* __restrict__ roff, uint32_t n,
-                                                           uint32_t* ahist, uint32_t* medium,
-                                                           uint32_t* large, BuildStats* st) {
-    __shared__ uint32_t h[APEX_LDS_BINS];
-    __shared__ uint32_t cnt[2], base[2];
-    for (uint32_t i = threadIdx.x; i < APEX_LDS_BINS; i += blockDim.x) h[i] = 0;
-    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+__global__ void __launch_bounds__(SCAN_THREADS) k_classify(const uint32_t* __restrict__ off, uint32_t n,
+                                                           uint32_t* medium, uint32_t* large, BuildStats* st) {
+    __shared__ uint32_t cnt[3], base[3];
+    if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
     __syncthreads();
     uint32_t a0, a1;
     node_range(n, a0, a1);
@@ -550,27 +614,23 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_classify(const uint32_t* __res
         const uint32_t d = off[a + 1] - off[a];
         sq += (unsigned long long)d * d;
         mx = d > mx ? d : mx;
-        if (d >= 2) {
-            const uint32_t k = unit_key(off, roff, n, a);
-            if (k < APEX_LDS_BINS) atomicAdd(&h[k], 1u);
-            else atomicAdd(&ahist[n - 1 - k], 1u);
-            ++napex;
-        }
-        if (d > SMALL_MAX && d <= MEDIUM_MAX) atomicAdd(&cnt[0], 1u);
+        if (d >= 2) ++napex;
+        if (d > WAVE_MAX && d <= MEDIUM_MAX) atomicAdd(&cnt[0], 1u);
         if (d > MEDIUM_MAX) atomicAdd(&cnt[1], 1u);
+        if (d > SMALL_MAX && d <= WAVE_MAX) atomicAdd(&cnt[2], 1u);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         base[0] = cnt[0] ? atomicAdd(&st->n_medium, cnt[0]) : 0;
         base[1] = cnt[1] ? atomicAdd(&st->n_large, cnt[1]) : 0;
+        base[2] = cnt[2] ? atomicAdd(&st->n_wave, cnt[2]) : 0;
     }
-    for (uint32_t d = threadIdx.x; d < APEX_LDS_BINS; d += blockDim.x)
-        if (h[d]) atomicAdd(&ahist[n - 1 - d], h[d]);
     __syncthreads();
     for (uint32_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
         const uint32_t d = off[a + 1] - off[a];
-        if (d > SMALL_MAX && d <= MEDIUM_MAX) medium[atomicAdd(&base[0], 1u)] = a;
+        if (d > WAVE_MAX && d <= MEDIUM_MAX) medium[n - 1 - atomicAdd(&base[0], 1u)] = a;
         if (d > MEDIUM_MAX) large[atomicAdd(&base[1], 1u)] = a;
+        if (d > SMALL_MAX && d <= WAVE_MAX) medium[atomicAdd(&base[2], 1u)] = a;
     }
     unsigned long long s = block_reduce_sum256<unsigned long long>(sq);
     uint32_t na = block_reduce_sum256<uint32_t>(napex);
@@ -584,6 +644,30 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_classify(const uint32_t* __res
         if (s) atomicAdd(&st->sum_out_sq, s);
         if (na) atomicAdd(&st->num_apex, na);
     }
+}
+
+// histogram apexes by unit key for the descending unit order (bucket n-1-key); needs the reverse
+// lists' offsets, and records their total
+__global__ void __launch_bounds__(SCAN_THREADS) k_apex_hist(const uint32_t* __restrict__ off,
+                                                            const uint32_t* __restrict__ roff, uint32_t n,
+                                                            uint32_t* ahist, BuildStats* st) {
+    __shared__ uint32_t h[APEX_LDS_BINS];
+    for (uint32_t i = threadIdx.x; i < APEX_LDS_BINS; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    uint32_t a0, a1;
+    node_range(n, a0, a1);
+    for (uint32_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
+        const uint32_t d = off[a + 1] - off[a];
+        if (d >= 2) {
+            const uint32_t k = unit_key(off, roff, n, a);
+            if (k < APEX_LDS_BINS) atomicAdd(&h[k], 1u);
+            else atomicAdd(&ahist[n - 1 - k], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < APEX_LDS_BINS; d += blockDim.x)
+        if (h[d]) atomicAdd(&ahist[n - 1 - d], h[d]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->num_rev = roff[n];
 }
 
 // place apexes in out-degree-descending order: reserve each bin's range once per workgroup
@@ -616,12 +700,15 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_apex_scatter(const uint32_t* _
     }
 }
 
-// Where the sorts emit the entry (b, t) at position s + i of a's list (length d): for a reverse
-// pair (out(a) shorter than out(b)), also the reverse record in the next free slot of b's shard.
+// Where the sorts emit the entry (b, t) at position s + i of a's list (length d), a reverse pair
+// (out(a) shorter than out(b)) also goes either to its reverse record, in the next free slot of
+// b's shard (shard path), or, with `src`, is marked at its position for the bucketed transpose
+// below: src[s + i] = a for a reverse pair, NO_EDGE otherwise.
 struct RevOut {
     uint32_t* cur;  // per target shard, from the shard's start
     uint4* rrec;
     uint32_t* rpos;
+    uint32_t* src;  // null on the shard path
 };
 __device__ __forceinline__ void emit_rev(const RevOut& R, uint32_t a, uint32_t s, uint32_t d, uint32_t i, uint32_t b,
                                          uint32_t t) {
@@ -635,49 +722,166 @@ __device__ __forceinline__ void emit_sorted(unsigned long long v, uint32_t idx, 
                                             uint32_t* nbr, uint32_t* tim, const RevOut& R) {
     if (idx < d) {
         const uint32_t b = (uint32_t)(v >> 32), t = (uint32_t)v & ~REV_BIT;
+        const bool rev = ((uint32_t)v & REV_BIT) != 0;
         nbr[seg + idx] = b;
         tim[seg + idx] = t;
-        if ((uint32_t)v & REV_BIT) emit_rev(R, a, seg, d, idx, b, t);
+        if (R.src) R.src[seg + idx] = rev ? a : NO_EDGE;
+        else if (rev) emit_rev(R, a, seg, d, idx, b, t);
     }
 }
 
-// segments of at most 64 entries: one wavefront, bitonic network across lanes
+// Bitonic network over aligned groups of G lanes: each group sorts its G values ascending
+// (the partner lane ^ j of every step stays inside the group).  i: the value's index in the
+// sequence being sorted (lane for one value per lane).
+template <int G>
+__device__ __forceinline__ unsigned long long group_sort(unsigned long long v, uint32_t i) {
+#pragma unroll
+    for (int k = 2; k <= G; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j >= 1; j >>= 1) {
+            const unsigned long long o = __shfl_xor(v, j, 64);
+            const bool up = (i & k) == 0, lower = (i & j) == 0;
+            v = (lower == up) ? (o < v ? o : v) : (o > v ? o : v);
+        }
+    }
+    return v;
+}
+
+// Segments of 1..64 entries.  A wavefront takes 64 consecutive nodes at a time (one coalesced
+// load of their offsets) and sorts their segments in aligned lane groups of 8, 16, 32 or 64
+// lanes (the smallest that holds the segment), 64 / G segments per pass, so a short segment
+// costs a short network and shares it with others.
+template <int G>
+__device__ __forceinline__ void sort_class(bool in, uint32_t s, uint32_t d, uint32_t a0, int lane,
+                                           const unsigned long long* __restrict__ packed, uint32_t* __restrict__ nbr,
+                                           uint32_t* __restrict__ tim, const RevOut& R, uint32_t& dup) {
+    constexpr int per = 64 / G;
+    const int grp = lane / G;
+    const uint32_t li = (uint32_t)(lane % G);
+    unsigned long long mask = __ballot(in);
+    while (mask) {
+        unsigned long long m = mask;  // this group's segment: the grp-th node left in the mask
+        for (int k = 0; k < grp; ++k) m &= m - 1;
+        const int src = m ? __builtin_ctzll(m) : 0;
+        // every lane takes part in both shuffles: a lane left out would not supply its own values
+        const uint32_t gs = __shfl(s, src, 64), gd0 = __shfl(d, src, 64);
+        const uint32_t gd = m ? gd0 : 0u;
+        unsigned long long v = li < gd ? packed[gs + li] : ~0ull;
+        v = group_sort<G>(v, li);
+        const unsigned long long prev = __shfl_up(v, 1, 64);
+        if (li > 0 && li < gd && (prev >> 32) == (v >> 32)) dup = 1;
+        emit_sorted(v, li, a0 + (uint32_t)src, gs, gd, nbr, tim, R);
+#pragma unroll
+        for (int k = 0; k < per; ++k) mask &= mask - 1;  // the segments of this pass are done
+    }
+}
+
 __global__ void __launch_bounds__(256) k_sort_small(const uint32_t* __restrict__ off, uint32_t n,
                                                     const unsigned long long* __restrict__ packed,
                                                     uint32_t* __restrict__ nbr, uint32_t* __restrict__ tim,
                                                     RevOut R, BuildStats* st) {
     const int lane = threadIdx.x & 63;
-    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     uint32_t dup = 0;
-    for (uint32_t a = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); a < n; a += waves) {
-        const uint32_t s = off[a], d = off[a + 1] - s;
-        if (d == 0 || d > SMALL_MAX) continue;
-        unsigned long long v = lane < (int)d ? packed[s + lane] : ~0ull;
-        for (int k = 2; k <= 64; k <<= 1) {
-            for (int j = k >> 1; j >= 1; j >>= 1) {
-                unsigned long long o = __shfl_xor(v, j, 64);
-                bool up = (lane & k) == 0;
-                bool lower = (lane & j) == 0;
-                bool take_min = (lower == up);
-                v = take_min ? (o < v ? o : v) : (o > v ? o : v);
-            }
+    for (uint64_t a0 = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; a0 < n; a0 += waves * 64) {
+        const uint64_t a = a0 + lane;
+        uint32_t s = 0, d = 0;
+        if (a < n) {
+            s = off[a];
+            d = off[a + 1] - s;
         }
-        unsigned long long prev = __shfl_up(v, 1, 64);
-        if (lane > 0 && lane < (int)d && (prev >> 32) == (v >> 32)) dup = 1;
-        emit_sorted(v, lane, a, s, d, nbr, tim, R);
+        sort_class<8>(d >= 1 && d <= 8, s, d, (uint32_t)a0, lane, packed, nbr, tim, R, dup);
+        sort_class<16>(d > 8 && d <= 16, s, d, (uint32_t)a0, lane, packed, nbr, tim, R, dup);
+        sort_class<32>(d > 16 && d <= 32, s, d, (uint32_t)a0, lane, packed, nbr, tim, R, dup);
+        sort_class<64>(d > 32 && d <= 64, s, d, (uint32_t)a0, lane, packed, nbr, tim, R, dup);
     }
     if (dup) atomicOr(&st->flags, RF_DUP);
 }
 
-// segments of 65..4096 entries: one workgroup, bitonic sort in LDS
+// Segments of 65..1024 entries: one wavefront each, K values per lane (value i = r * 64 + lane in
+// register r), bitonic network in registers: steps with j < 64 exchange across lanes, steps with
+// j >= 64 between registers of one lane.  No barriers.
+template <int K>
+__device__ __forceinline__ void wave_sort(const unsigned long long* __restrict__ src, uint32_t a, uint32_t s,
+                                          uint32_t d, int lane, uint32_t* __restrict__ nbr,
+                                          uint32_t* __restrict__ tim, const RevOut& R, uint32_t& dup) {
+    unsigned long long v[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const uint32_t i = (uint32_t)(r * 64 + lane);
+        v[r] = i < d ? src[i] : ~0ull;
+    }
+    // fully unrolled: every register index is a constant (an index computed at run time would
+    // put the array in scratch memory)
+#pragma unroll
+    for (int k = 2; k <= 64 * K; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j >= 1; j >>= 1) {
+            if (j >= 64) {
+                const int jr = j >> 6;
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+                    if (r & jr) continue;
+                    const int r2 = r | jr;
+                    const bool up = (((uint32_t)(r * 64 + lane)) & (uint32_t)k) == 0;
+                    const unsigned long long x = v[r], y = v[r2];
+                    const bool sw = (x > y) == up;
+                    v[r] = sw ? y : x;
+                    v[r2] = sw ? x : y;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+                    const unsigned long long o = __shfl_xor(v[r], j, 64);
+                    const uint32_t i = (uint32_t)(r * 64 + lane);
+                    const bool up = (i & (uint32_t)k) == 0, lower = (i & (uint32_t)j) == 0;
+                    v[r] = (lower == up) ? (o < v[r] ? o : v[r]) : (o > v[r] ? o : v[r]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const uint32_t i = (uint32_t)(r * 64 + lane);
+        unsigned long long prev = __shfl_up(v[r], 1, 64);
+        if (r > 0) {
+            const unsigned long long last = __shfl(v[r - 1], 63, 64);
+            if (lane == 0) prev = last;
+        }
+        if (i > 0 && i < d && (prev >> 32) == (v[r] >> 32)) dup = 1;
+        emit_sorted(v[r], i, a, s, d, nbr, tim, R);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_sort_wave(const uint32_t* __restrict__ off, const uint32_t* __restrict__ list,
+                                                   const unsigned long long* __restrict__ packed,
+                                                   uint32_t* __restrict__ nbr, uint32_t* __restrict__ tim,
+                                                   RevOut R, BuildStats* st) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    const uint32_t cnt = st->n_wave;
+    uint32_t dup = 0;
+    for (uint32_t q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < cnt; q += waves) {
+        const uint32_t a = list[q];
+        const uint32_t s = off[a], d = off[a + 1] - s;
+        if (d <= 128) wave_sort<2>(packed + s, a, s, d, lane, nbr, tim, R, dup);
+        else if (d <= 256) wave_sort<4>(packed + s, a, s, d, lane, nbr, tim, R, dup);
+        else if (d <= 512) wave_sort<8>(packed + s, a, s, d, lane, nbr, tim, R, dup);
+        else wave_sort<16>(packed + s, a, s, d, lane, nbr, tim, R, dup);
+    }
+    if (dup) atomicOr(&st->flags, RF_DUP);
+}
+
+// segments of 1025..4096 entries: one workgroup, bitonic sort in LDS (their nodes are listed
+// from the back of `list`, which holds n entries)
 __global__ void __launch_bounds__(512) k_sort_medium(const uint32_t* __restrict__ off, const uint32_t* __restrict__ list,
-                                                     const unsigned long long* __restrict__ packed,
+                                                     uint32_t n, const unsigned long long* __restrict__ packed,
                                                      uint32_t* __restrict__ nbr, uint32_t* __restrict__ tim,
                                                      RevOut R, BuildStats* st) {
     __shared__ unsigned long long buf[MEDIUM_MAX];
     const uint32_t cnt = st->n_medium;
     for (uint32_t q = blockIdx.x; q < cnt; q += gridDim.x) {
-        const uint32_t a = list[q];
+        const uint32_t a = list[n - 1 - q];
         const uint32_t s = off[a], d = off[a + 1] - s;
         uint32_t P = 128;
         while (P < d) P <<= 1;
@@ -975,17 +1179,17 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
                        opart);
     const uint64_t nsh = (uint64_t)n * REV_SHARDS;
     const uint32_t gS = grid_for(nsh, 256, cap);
-    if (D.shift <= 13) {  // placement by slices of the partition, LDS cursors
-        const uint64_t smax = (E + SLICE_ENTRIES - 1) / SLICE_ENTRIES + D.NB;
+    const bool sliced = D.shift <= 13;
+    const uint64_t smax = (E + SLICE_ENTRIES - 1) / SLICE_ENTRIES + D.NB;
+    if (sliced) {  // placement by slices of the partition, LDS cursors
         hipLaunchKernelGGL(k_slice_plan, dim3(1), dim3(1024), 0, s, bscan, D.nblk, D.NB, slice_off);
         hipLaunchKernelGGL(k_slice_count, dim3((uint32_t)smax), dim3(1024), 0, s, opart, bscan, D.nblk, D.NB,
                            D.shift, slice_off, scount);
         hipLaunchKernelGGL(k_slice_dout, dim3(gN), dim3(256), 0, s, scount, slice_off, D.shift, n, dout);
         if (scan_u32(dout, n, part, off, s) != hipSuccess) return REPT_EDEVICE;
         hipLaunchKernelGGL(k_slice_base, dim3(gN), dim3(256), 0, s, scount, slice_off, D.shift, n, off);
-        hipLaunchKernelGGL(k_fill_u32, dim3(gS), dim3(256), 0, s, scnt, nsh, 0u);
         hipLaunchKernelGGL(k_slice_place, dim3((uint32_t)smax), dim3(1024), 0, s, opart, bscan, D.nblk, D.NB,
-                           D.shift, slice_off, scount, dout, packed, scnt, st);
+                           D.shift, slice_off, scount, dout, packed, (uint32_t*)nullptr, st);
     } else {  // wider buckets: out-degrees per bucket in LDS, placement by global cursors
         hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, dout, (uint64_t)n, 0u);
         hipLaunchKernelGGL(k_out_count, dim3(grid_for(E, DEG_SLICE, 4096)), dim3(1024), 0, s, opart, bscan, D.nblk,
@@ -995,20 +1199,49 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
         hipLaunchKernelGGL(k_copy_u32, dim3(gN), dim3(256), 0, s, off, (uint64_t)n, cursor);
         hipLaunchKernelGGL(k_scatter, dim3(gE), dim3(256), 0, s, ab, E, dout, cursor, packed, scnt, st);
     }
-    // reverse lists: shard starts from k_scatter's counts; the sorts place the records
-    if (scan_u32(scnt, nsh, part, sofs, s) != hipSuccess) return REPT_EDEVICE;
-    hipLaunchKernelGGL(k_rev_roff, dim3(gN), dim3(256), 0, s, sofs, n, roff, st);
-    hipLaunchKernelGGL(k_copy_u32, dim3(gS), dim3(256), 0, s, sofs, nsh, scnt);  // shard cursors
-    const RevOut RO{scnt, rrec, rpos};
-    hipLaunchKernelGGL(k_classify, dim3(gA), dim3(256), 0, s, off, roff, n, ahist, medium, large, st);
-    hipLaunchKernelGGL(k_sort_small, dim3(grid_for((uint64_t)n, 4, cap * 4)), dim3(256), 0, s, off, n, packed,
-                       nbr, tim, RO, st);
-    hipLaunchKernelGGL(k_sort_medium, dim3(cus ? cus * 4 : 1024), dim3(512), 0, s, off, medium, packed, nbr,
+    // Reverse lists.  Sliced: the sorts mark each reverse pair's source at its adjacency position
+    // (in the partition's space, free after the placement) and a bucketed transpose builds the
+    // lists below.  Otherwise: shard starts from k_scatter's counts, and the sorts place the
+    // records with shard cursors.
+    uint32_t* rsrc = (uint32_t*)opart;
+    RevOut RO{nullptr, rrec, rpos, rsrc};
+    if (!sliced) {
+        if (scan_u32(scnt, nsh, part, sofs, s) != hipSuccess) return REPT_EDEVICE;
+        hipLaunchKernelGGL(k_rev_roff, dim3(gN), dim3(256), 0, s, sofs, n, roff, st);
+        hipLaunchKernelGGL(k_copy_u32, dim3(gS), dim3(256), 0, s, sofs, nsh, scnt);  // shard cursors
+        RO = RevOut{scnt, rrec, rpos, nullptr};
+    }
+    hipLaunchKernelGGL(k_classify, dim3(gA), dim3(256), 0, s, off, n, medium, large, st);
+    hipLaunchKernelGGL(k_sort_small, dim3(grid_for((uint64_t)n, 256, cap)), dim3(256), 0, s, off, n, packed, nbr,
+                       tim, RO, st);
+    hipLaunchKernelGGL(k_sort_wave, dim3(cus ? cus * 8 : 2048), dim3(256), 0, s, off, medium, packed, nbr, tim,
+                       RO, st);
+    hipLaunchKernelGGL(k_sort_medium, dim3(cus ? cus * 4 : 1024), dim3(512), 0, s, off, medium, n, packed, nbr,
                        tim, RO, st);
     uint32_t id_bits = 1;
     while (id_bits < 32 && ((uint64_t)1 << id_bits) < (uint64_t)n) ++id_bits;
     hipLaunchKernelGGL(k_sort_large, dim3(cus ? cus : 256), dim3(64), 0, s, off, large, packed, alt, id_bits,
                        nbr, tim, RO, st);
+    if (sliced) {
+        // the reverse pairs (b, a, t, p) partitioned by the bucket of b into the sort buffers
+        // (`packed` and `alt`, 16 bytes per edge together, free after the sorts)
+        uint4* rpart = (uint4*)packed;
+        uint32_t* rcnt = cursor;
+        hipLaunchKernelGGL(k_rev_hist, dim3(D.nblk), dim3(1024), 0, s, rsrc, nbr, off, n, D.shift, D.NB,
+                           D.per_block, bhist);
+        if (scan_u32(bhist, (uint64_t)D.NB * D.nblk, part, bscan, s) != hipSuccess) return REPT_EDEVICE;
+        hipLaunchKernelGGL(k_rev_part, dim3(D.nblk), dim3(1024), 0, s, rsrc, nbr, tim, off, n, D.shift, D.NB,
+                           D.per_block, bscan, rpart);
+        hipLaunchKernelGGL(k_slice_plan, dim3(1), dim3(1024), 0, s, bscan, D.nblk, D.NB, slice_off);
+        hipLaunchKernelGGL(k_slice_count, dim3((uint32_t)smax), dim3(1024), 0, s, (const uint4*)rpart, bscan,
+                           D.nblk, D.NB, D.shift, slice_off, scount);
+        hipLaunchKernelGGL(k_slice_dout, dim3(gN), dim3(256), 0, s, scount, slice_off, D.shift, n, rcnt);
+        if (scan_u32(rcnt, n, part, roff, s) != hipSuccess) return REPT_EDEVICE;
+        hipLaunchKernelGGL(k_slice_base, dim3(gN), dim3(256), 0, s, scount, slice_off, D.shift, n, roff);
+        hipLaunchKernelGGL(k_rev_place, dim3((uint32_t)smax), dim3(1024), 0, s, (const uint4*)rpart, bscan, D.nblk,
+                           D.NB, D.shift, slice_off, scount, off, rrec, rpos);
+    }
+    hipLaunchKernelGGL(k_apex_hist, dim3(gA), dim3(256), 0, s, off, roff, n, ahist, st);
     if (scan_u32(ahist, n, part, aoff, s) != hipSuccess) return REPT_EDEVICE;
     hipLaunchKernelGGL(k_fill_u32, dim3(gN), dim3(256), 0, s, cursor, (uint64_t)n, 0u);
     hipLaunchKernelGGL(k_apex_scatter, dim3(gA), dim3(256), 0, s, off, roff, n, aoff, cursor, apex);

@@ -27,7 +27,8 @@ struct BuildStats {
     uint32_t n_medium;  // segments sorted by a workgroup in LDS
     uint32_t n_large;   // segments sorted by a workgroup in global memory
     uint32_t num_rev;   // pairs in the reverse lists
-    uint32_t pad[2];
+    uint32_t n_wave;    // segments sorted in registers by one wavefront each
+    uint32_t pad[1];
     unsigned long long work;        // sum over oriented edges a->b of min(outdeg(a), outdeg(b))
     unsigned long long sum_out_sq;  // sum over nodes of outdeg^2
 };
