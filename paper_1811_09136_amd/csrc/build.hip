@@ -332,7 +332,10 @@ __global__ void __launch_bounds__(1024) k_out_count(const uint4* __restrict__ op
 // each slice (its segment start plus its entries in the bucket's earlier slices); a slice then
 // places its entries with LDS cursors from those bases.  Needs a bucket span of at most DEG_SUB
 // ids (n <= 2^25).
-constexpr uint32_t SLICE_ENTRIES = 16384;
+// (R-MAT scale 24 build: 45.6-46.0 ms at 32768 entries, 45.9 at 65536, 46.9 at 16384, 48.4 at
+// 8192: fewer slices per bucket write fewer per-slice counts and interleave less in each
+// node's segment)
+constexpr uint32_t SLICE_ENTRIES = 32768;
 
 // slice_off[b] = first slice of bucket b (slice_off[NB] = the number of slices); one workgroup
 __global__ void __launch_bounds__(1024) k_slice_plan(const uint32_t* __restrict__ boff, uint32_t nblk, uint32_t NB,
