@@ -28,7 +28,7 @@ struct BuildStats {
     uint32_t n_large;   // segments sorted by a workgroup in global memory
     uint32_t num_rev;   // pairs in the reverse lists
     uint32_t n_wave;    // segments sorted in registers by one wavefront each
-    uint32_t pad[1];
+    uint32_t n_ends;    // endpoints of the valid edges (the degree partition's length)
     unsigned long long work;        // sum over oriented edges a->b of min(outdeg(a), outdeg(b))
     unsigned long long sum_out_sq;  // sum over nodes of outdeg^2
 };
