@@ -204,11 +204,13 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
         if (per_cu == 0) per_cu = 1;
         return per_cu > 4 ? 4u : per_cu;
     };
-    // Sparser heavy tables (four slots per key: fewer probes past the first bucket) where they
-    // fit and cost no resident workgroup (R-MAT scale 24, one 1024-thread workgroup per CU
-    // either way: 179 against 198 ms; the 1M/20M power-law graph would drop from four 256-thread
-    // workgroups per CU to three: 7.04 against 5.99 ms)
-    {
+    // Sparser heavy tables (four slots per key: fewer probes past the first bucket) with the wide
+    // shape, where they fit and cost no resident workgroup (R-MAT scale 24, one 1024-thread
+    // workgroup per CU either way: 179 against 198 ms).  Shorter lists keep two: on the 1M/20M
+    // power-law graph four slots would drop REPT's default launch from four workgroups per CU to
+    // three (7.04 against 5.99 ms), and where they keep the occupancy they cost MASCOT with eight
+    // processors 9.8 against 8.0 ms, for 4.9 against 5.1 ms for REPT with the same m and c.
+    if (wide) {
         const uint32_t per_cu2 = resident(heavy_lds());
         heavy_table = 4;
         const uint32_t lds4 = heavy_lds();
