@@ -387,7 +387,7 @@ typedef struct rept_job {
  * workgroup (units whose size exceeds wave_cap), then one unit per wavefront.  The LDS
  * footprint of a shape must fit the 160 KB of a compute unit (EINVAL otherwise). */
 typedef struct rept_tuning {
-    uint32_t wave_cap;   /* 8..256: largest unit counted by one wavefront (default 64, or 128 with
+    uint32_t wave_cap;   /* 8..256: largest unit counted by one wavefront (default 64, or 256 with
                             the wide shape below; halved down to 64 if the light phase's LDS
                             would not fit); a unit's size is max(its list length, its
                             reverse-list length / 8) */
@@ -402,9 +402,10 @@ typedef struct rept_tuning {
     uint32_t blocks;     /* persistent workgroups (default: as many as fit, up to 4 per CU) */
     uint32_t threads;    /* 64..1024, a multiple of 64 (default 256; the wide shape, taken when
                             the longest list exceeds 1024 entries and none of block_cap and
-                            threads is set: 1024, with block_cap 2048, b_chunk 1024 and
-                            wave_cap 128) */
-    uint32_t light_tile; /* 1..64: apexes taken per queue pop by a wavefront (default 8) */
+                            threads is set: 1024, with block_cap 2048, b_chunk 1024,
+                            wave_cap 256 and light_tile 16) */
+    uint32_t light_tile; /* 1..64: apexes taken per queue pop by a wavefront (default 8; 16 with
+                            the wide shape) */
     uint32_t phase_launches; /* 1: both phases in one launch; 2: the light phase (units of at most
                                 wave_cap, one per wavefront) runs as a launch of its own after the
                                 heavy one, its workgroups holding no heavy team area in LDS, so

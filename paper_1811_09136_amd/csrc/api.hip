@@ -129,19 +129,21 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     uint32_t block_cap = own_block_cap ? tu->block_cap : fit;
     // Lists of more than 1024 entries: one workgroup of 1024 threads per compute unit (16 waves),
     // one 2048-entry table chunk (no second walk of a unit's B lists below 2048 entries),
-    // 1024-list B chunks, and units of up to 128 entries left to single wavefronts (R-MAT scale
-    // 24, longest list 1761: 198 ms; 274 with 512-thread workgroups, 1024-entry table chunks and
-    // 256-list B chunks, two workgroups per compute unit; 206 with 512-list B chunks; 210 with
-    // units above 64 entries given to workgroups).  Shorter lists keep 256-thread workgroups
-    // (the 1M/20M power-law graph, longest list 480: 5.99 ms; 8.5-10.8 with 1024 threads).
+    // 1024-list B chunks, and units of up to 256 entries left to single wavefronts, taken 16 at a
+    // time (R-MAT scale 24, longest list 1761: 198 ms with units of up to 128 entries on
+    // wavefronts, 210 with up to 64; 274 with 512-thread workgroups, 1024-entry table chunks and
+    // 256-list B chunks, two workgroups per compute unit; 206 with 512-list B chunks.  With the
+    // four-slot heavy tables below: 179.9 ms at 128, 176.4 at 256, 175.6 at 256 with 16-unit
+    // light tiles).  Shorter lists keep 256-thread workgroups (the 1M/20M power-law graph,
+    // longest list 480: 5.99 ms; 8.5-10.8 with 1024 threads).
     const bool wide = !own_block_cap && block_cap >= 2048 && !(tu && tu->threads);
     const bool own_wave_cap = tu && tu->wave_cap;
-    uint32_t wave_cap = own_wave_cap ? tu->wave_cap : (wide ? 128u : 64u);
+    uint32_t wave_cap = own_wave_cap ? tu->wave_cap : (wide ? 256u : 64u);
     // units with long lists also have many lists to walk: bigger B chunks pay there, not on
     // shorter lists (the 1M/20M power-law graph: 6.64 ms at 128, 7.13 at 64, 7.41 at 256)
     uint32_t b_chunk = own_b_chunk ? tu->b_chunk : (wide ? 1024u : (block_cap >= 2048 ? 512u : 128u));
     const uint32_t threads = (tu && tu->threads) ? tu->threads : (wide ? 1024u : 256u);
-    const uint32_t light_tile = (tu && tu->light_tile) ? tu->light_tile : 8;
+    const uint32_t light_tile = (tu && tu->light_tile) ? tu->light_tile : (wide ? 16u : 8u);
     if (wave_cap < 8 || wave_cap > 256) return REPT_EINVAL;
     if (block_cap < 64 || block_cap > 4096) return REPT_EINVAL;
     if (b_chunk < 16 || b_chunk > 1024) return REPT_EINVAL;
