@@ -154,37 +154,39 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     // default (0): the light phase in a launch of its own, on a second stream
     const bool split = pl != 1;
     // A light launch of its own needs no heavy team area, and a heavy launch then needs no light
-    // areas.  The light launch keeps the heavy launch's workgroup size where its wavefronts' areas
-    // fit; beside 1024-thread heavy workgroups whose light areas do not (more than one hash
-    // group), it takes 256-thread ones, whose LDS holds four wavefronts' areas while the
-    // registers still allow 16 waves per CU (R-MAT scale 24, one group: 198 ms with 1024-thread
-    // light workgroups, which fit with two hash slots per key; 200 with 256-thread ones, four
-    // slots per key, three per CU; 205 with 512)
+    // areas.  It keeps the heavy launch's workgroup size, except with the wide shape below.
     uint32_t light_threads = threads;
     const uint32_t hist_c = c_max <= REPT_HIST_CAP ? c_max : 0;
     // the light phase's hash tables are sparser (fewer probes) where the LDS budget allows
     uint32_t light_table = 4, heavy_table = 2;
+    // a light wavefront stages its lists to walk in chunks of light_b (at most wave_cap)
+    uint32_t light_b = wave_cap;
+    // The wide shape's light launch (units of up to 256 entries): 256-thread workgroups with
+    // two-slot tables and 128-list chunks, so that three fit a CU (12 waves); four-slot tables
+    // and 256-list chunks fit two (R-MAT scale 24: 169.8 against 175.9 ms; 64-list chunks 170.3)
+    if (split && wide) {
+        light_threads = 256;
+        light_table = 2;
+        light_b = wave_cap < 128 ? wave_cap : 128u;
+    }
     auto heavy_lds = [&]() {  // the launch that runs the heavy phase (both phases if not split)
-        return rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table, heavy_table, eta,
-                              true, !split);
+        return rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table, heavy_table,
+                              light_b, eta, true, !split);
     };
     auto light_lds = [&]() {  // the light areas alone, in the launch that holds them
         return rept_count_lds(split ? light_threads : threads, wave_cap, block_cap, b_chunk, G_max, hist_c,
-                              light_table, heavy_table, eta, false, true);
+                              light_table, heavy_table, light_b, eta, false, true);
     };
     // Past the 160 KB of a CU (static LDS takes a few bytes more), the light areas shrink first
-    // (sparser tables, then smaller light workgroups, then a default wave cap halved down to 64),
-    // then the default heavy chunk sizes.  A shape the caller chose is never changed: it is
-    // refused if it does not fit.
+    // (sparser tables, then a default wave cap halved down to 64), then the default heavy chunk
+    // sizes.  A shape the caller chose is never changed: it is refused if it does not fit.
     const uint32_t cap = 160 * 1024 - 256;
     while (light_lds() > cap) {
         if (light_table == 4) {
             light_table = 2;
-        } else if (split && wide && light_threads > 256) {
-            light_threads = 256;
-            light_table = 4;
         } else if (!own_wave_cap && wave_cap > 64) {
             wave_cap >>= 1;
+            light_b = light_b < wave_cap ? light_b : wave_cap;
         } else {
             return REPT_EINVAL;
         }
@@ -233,6 +235,7 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     h->lds_bytes = lds;
     h->light_table = light_table;
     h->heavy_table = heavy_table;
+    h->light_b = light_b;
     h->any_zero = any_zero ? 1u : 0u;
     h->any_eta = eta ? 1u : 0u;
     h->zero_words = zero_words;

@@ -137,12 +137,12 @@ struct Layout {
     uint32_t union_off, total;
 };
 __host__ __device__ inline Layout count_layout(uint32_t nwaves, uint32_t DL, uint32_t DW, uint32_t DB,
-                                               uint32_t G, uint32_t HC, uint32_t LT, uint32_t HT, bool eta,
-                                               bool heavy, bool light) {
+                                               uint32_t G, uint32_t HC, uint32_t LT, uint32_t HT, uint32_t DLB,
+                                               bool eta, bool heavy, bool light) {
     Layout L;
     L.misc = misc_layout(HC);
     L.heavy = area_layout(DW, DB, G, HT, eta);
-    L.light = area_layout(DL, DL, G, LT, eta);
+    L.light = area_layout(DL, DLB, G, LT, eta);
     L.union_off = nwaves * L.misc.bytes;
     // a launch holds only the areas of the phases it runs
     const uint32_t hb = heavy ? L.heavy.bytes : 0u, lb = light ? nwaves * L.light.bytes : 0u;
@@ -1194,8 +1194,8 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const uint32_t DL = hdr->wave_cap, DW = hdr->block_cap, DB = hdr->b_chunk;
     const uint32_t GM = hdr->G_max, HC = hdr->hist_c, njobs = hdr->njobs;
-    const uint32_t LT = hdr->light_table, HT = hdr->heavy_table;
-    const Layout L = count_layout(nw, DL, DW, DB, GM, HC, LT, HT, ETA, (phases & 1u) != 0, (phases & 2u) != 0);
+    const uint32_t LT = hdr->light_table, HT = hdr->heavy_table, DLB = hdr->light_b;
+    const Layout L = count_layout(nw, DL, DW, DB, GM, HC, LT, HT, DLB, ETA, (phases & 1u) != 0, (phases & 2u) != 0);
     const WaveView V = wave_view(lds + wid * L.misc.bytes, L.misc);
     uint8_t* uni = lds + L.union_off;
     __shared__ uint32_t s_tile;
@@ -1232,7 +1232,7 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
 
     // phase 2: short lists, one apex per wavefront
     if (phases & 2u) {
-        const TeamView T = team_view(uni + wid * L.light.bytes, L.light, DL, DL, LT);
+        const TeamView T = team_view(uni + wid * L.light.bytes, L.light, DL, DLB, LT);
         const uint32_t total = hdr->light_total, tile_len = hdr->light_tile;
         uint32_t q = (blockIdx.x * nw + wid) % kQueues, left = kQueues;  // used by lane 0
         for (;;) {
@@ -1392,10 +1392,10 @@ hipError_t launch_common(uint8_t* ws, const BatchHeader& h, hipStream_t s) {
 }  // namespace
 
 uint32_t rept_count_lds(uint32_t threads, uint32_t wave_cap, uint32_t block_cap, uint32_t b_chunk, uint32_t G,
-                        uint32_t hist_c, uint32_t light_table, uint32_t heavy_table, bool eta, bool heavy,
-                        bool light) {
-    return count_layout(threads / 64, wave_cap, block_cap, b_chunk, G, hist_c, light_table, heavy_table, eta, heavy,
-                        light).total;
+                        uint32_t hist_c, uint32_t light_table, uint32_t heavy_table, uint32_t light_b, bool eta,
+                        bool heavy, bool light) {
+    return count_layout(threads / 64, wave_cap, block_cap, b_chunk, G, hist_c, light_table, heavy_table, light_b, eta,
+                        heavy, light).total;
 }
 
 uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes, bool eta) {
