@@ -176,7 +176,7 @@ struct IncState {
     uint32_t *ctim_a, *ctim_b;
     uint64_t* end;      // inclusive scan of the item lengths
     uint32_t* flags;    // validation word (RF_*)
-    void* temp;         // rocPRIM temporary storage
+    void* temp;         // temporary storage of the chunk sort and the scans
     size_t temp_bytes;
     uint32_t count_blocks;
 };

@@ -7,7 +7,8 @@
 // and the node offsets into it.  An append:
 //   1. turns the chunk into keys (both directions, times T .. T+W-1) and checks ids and
 //      self-loops;
-//   2. sorts the chunk's keys (rocPRIM radix sort);
+//   2. sorts the chunk's keys (a stable LSD radix sort of 8-bit digits over the key bits that can
+//      be set);
 //   3. checks for an unordered pair twice in the chunk or already in the adjacency (binary
 //      search in the node's sorted list), and finds each node's run in the sorted chunk;
 //   4. after the host has read the validation word (the one synchronisation), merges the chunk
@@ -21,9 +22,6 @@
 //      its shorter list), spread evenly over the grid through an inclusive scan of the lengths.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
-
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
 
 #include "common.h"
 #include "edge_hash.h"
@@ -261,19 +259,231 @@ uint32_t grid_of(uint64_t items, uint32_t cap) {
     return b ? (uint32_t)b : 1u;
 }
 
+// ---- scans: a tile of SC_TILE items per block (256 threads x 16), the tiles' sums scanned by one
+// block, then each tile scanned again from its base
+constexpr uint32_t SC_ITEMS = 16;
+constexpr uint32_t SC_TILE = kThreads * SC_ITEMS;
+
+template <typename T>
+__device__ T block_excl_scan(T v, T& total) {  // 256 threads
+    __shared__ T ws[kThreads / 64];
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const T o = __shfl_up(inc, d, 64);
+        if ((int)lane >= d) inc += o;
+    }
+    if (lane == 63) ws[w] = inc;
+    __syncthreads();
+    T base = 0, tot = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kThreads / 64; ++i) {
+        if (i < w) base += ws[i];
+        tot += ws[i];
+    }
+    __syncthreads();
+    total = tot;
+    return base + inc - v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_scan_sums(const T* __restrict__ in, uint64_t N, T* __restrict__ part) {
+    const uint64_t b0 = (uint64_t)blockIdx.x * SC_TILE;
+    T s = 0;
+    for (uint32_t r = 0; r < SC_ITEMS; ++r) {
+        const uint64_t i = b0 + (uint64_t)r * kThreads + threadIdx.x;
+        if (i < N) s += in[i];
+    }
+    T tot;
+    (void)block_excl_scan<T>(s, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// exclusive scan of the tiles' sums in place (one block)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_scan_parts(T* part, uint32_t nparts) {
+    __shared__ T carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t b = 0; b < nparts; b += kThreads) {
+        const uint32_t i = b + threadIdx.x;
+        const T v = i < nparts ? part[i] : 0;
+        T tot;
+        const T ex = block_excl_scan<T>(v, tot);
+        const T c = carry;
+        if (i < nparts) part[i] = c + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + tot;
+        __syncthreads();
+    }
+}
+
+// out[i] = sum of in[0..i] (INCL) or in[0..i) (exclusive), each thread 16 consecutive items
+template <typename T, bool INCL>
+__global__ void __launch_bounds__(kThreads) k_scan_items(const T* __restrict__ in, uint64_t N,
+                                                         const T* __restrict__ part, T* __restrict__ out) {
+    const uint64_t b0 = (uint64_t)blockIdx.x * SC_TILE + (uint64_t)threadIdx.x * SC_ITEMS;
+    T v[SC_ITEMS];
+    T s = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < SC_ITEMS; ++r) {
+        const uint64_t i = b0 + r;
+        v[r] = i < N ? in[i] : 0;
+        s += v[r];
+    }
+    T tot;
+    T run = block_excl_scan<T>(s, tot) + part[blockIdx.x];
+#pragma unroll
+    for (uint32_t r = 0; r < SC_ITEMS; ++r) {
+        const uint64_t i = b0 + r;
+        if (INCL) run += v[r];
+        if (i < N) out[i] = run;
+        if (!INCL) run += v[r];
+    }
+}
+
+template <typename T, bool INCL>
+hipError_t scan_items(const T* in, uint64_t N, T* part, T* out, hipStream_t s) {
+    const uint64_t nb = (N + SC_TILE - 1) / SC_TILE;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_sums<T>, dim3((uint32_t)nb), dim3(kThreads), 0, s, in, N, part);
+    hipLaunchKernelGGL(k_scan_parts<T>, dim3(1), dim3(kThreads), 0, s, part, (uint32_t)nb);
+    hipLaunchKernelGGL((k_scan_items<T, INCL>), dim3((uint32_t)nb), dim3(kThreads), 0, s, in, N, part, out);
+    return hipGetLastError();
+}
+
+// ---- stable LSD radix sort of (key, time) pairs: one 8-bit digit per pass.  A block takes a
+// tile of RS_TILE pairs, each of its four wavefronts a contiguous quarter; the pass counts the
+// digits per tile, scans the counts digit-major (all tiles' 0s, then all tiles' 1s, ...), and
+// scatters each tile stably: a wavefront ranks its lanes among the lanes of the same digit
+// (eight ballots) and keeps a running base per digit, seeded from the tile's base plus the
+// counts of the wavefronts before it.
+constexpr uint32_t RS_TILE = 4096;
+constexpr uint32_t RS_WAVE = RS_TILE / (kThreads / 64);
+
+__global__ void __launch_bounds__(kThreads) k_rs_hist(const uint64_t* __restrict__ keys, uint64_t N, uint32_t shift,
+                                                      uint32_t nb, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t b0 = (uint64_t)blockIdx.x * RS_TILE, b1 = (b0 + RS_TILE) < N ? (b0 + RS_TILE) : N;
+    for (uint64_t i = b0 + threadIdx.x; i < b1; i += kThreads) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                         uint64_t N, uint32_t shift, uint32_t nb,
+                                                         const uint32_t* __restrict__ offs, uint64_t* __restrict__ kout,
+                                                         uint32_t* __restrict__ vout) {
+    __shared__ uint32_t wc[kThreads / 64][256];  // per wavefront: digit counts, then running bases
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (uint32_t i = threadIdx.x; i < (kThreads / 64) * 256; i += kThreads) (&wc[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t t0 = (uint64_t)blockIdx.x * RS_TILE + (uint64_t)w * RS_WAVE;
+    const uint64_t t1 = (t0 + RS_WAVE) < N ? (t0 + RS_WAVE) : N;
+    for (uint64_t c0 = t0; c0 < t1; c0 += 64) {
+        const uint64_t i = c0 + lane;
+        if (i < t1) atomicAdd(&wc[w][(uint32_t)(kin[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    {  // thread d: the bases of digit d for the four wavefronts of this tile
+        const uint32_t d = threadIdx.x;
+        uint32_t run = offs[(uint64_t)d * nb + blockIdx.x];
+        for (uint32_t v = 0; v < kThreads / 64; ++v) {
+            const uint32_t c = wc[v][d];
+            wc[v][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (uint64_t c0 = t0; c0 < t1; c0 += 64) {
+        const uint64_t i = c0 + lane;
+        const bool valid = i < t1;
+        const uint64_t k = valid ? kin[i] : 0ull;
+        const uint32_t t = valid ? vin[i] : 0u;
+        const uint32_t dig = (uint32_t)(k >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t bb = __ballot(valid && ((dig >> bit) & 1u));
+            peers &= ((dig >> bit) & 1u) ? bb : ~bb;
+        }
+        const uint32_t pos = wc[w][dig] + (uint32_t)__popcll(peers & below);
+        if (valid) {
+            kout[pos] = k;
+            vout[pos] = t;
+            // the highest lane of the digit advances its base (after every lane has read it)
+            if ((int)lane == 63 - __clzll(peers)) wc[w][dig] += (uint32_t)__popcll(peers);
+        }
+    }
+}
+
+__global__ void k_copy_pairs(const uint64_t* __restrict__ ks, const uint32_t* __restrict__ vs, uint64_t N,
+                             uint64_t* __restrict__ kd, uint32_t* __restrict__ vd) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x) {
+        kd[i] = ks[i];
+        vd[i] = vs[i];
+    }
+}
+
+// temporary storage of the sort and the scans: the digit counts and their scan, then the scans'
+// tile sums
+struct SortTemp {
+    size_t hist, offs, part, total;
+};
+SortTemp sort_temp(uint64_t N) {
+    SortTemp T;
+    const uint64_t nb = (N + RS_TILE - 1) / RS_TILE;
+    const uint64_t nh = 256 * (nb ? nb : 1);
+    const uint64_t parts = (nh + SC_TILE - 1) / SC_TILE + (N + SC_TILE - 1) / SC_TILE + 2;
+    size_t p = 0;
+    T.hist = p; p = (p + 4 * nh + 255) & ~(size_t)255;
+    T.offs = p; p = (p + 4 * (nh + 1) + 255) & ~(size_t)255;
+    T.part = p; p = (p + 8 * parts + 255) & ~(size_t)255;
+    T.total = p;
+    return T;
+}
+
+// sorts (ka, ta) by the key bits below end_bit that can be set (ids below 2^(end_bit - 32) on
+// both halves), the result in (kb, tb); (ka, ta) is overwritten
+hipError_t radix_sort_keys(void* temp, uint64_t N, uint32_t end_bit, uint64_t* ka, uint32_t* ta, uint64_t* kb,
+                           uint32_t* tb, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    const SortTemp L = sort_temp(N);
+    uint32_t* hist = (uint32_t*)((uint8_t*)temp + L.hist);
+    uint32_t* offs = (uint32_t*)((uint8_t*)temp + L.offs);
+    uint32_t* part = (uint32_t*)((uint8_t*)temp + L.part);
+    const uint32_t nb = (uint32_t)((N + RS_TILE - 1) / RS_TILE);
+    const uint32_t id_bits = end_bit - 32;
+    uint64_t *src_k = ka, *dst_k = kb;
+    uint32_t *src_t = ta, *dst_t = tb;
+    for (uint32_t half = 0; half < 2; ++half) {  // y (bits 0..), then x (bits 32..)
+        for (uint32_t b = 0; b < id_bits; b += 8) {
+            const uint32_t shift = 32 * half + b;
+            hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kThreads), 0, s, src_k, N, shift, nb, hist);
+            hipError_t e = scan_items<uint32_t, false>(hist, (uint64_t)256 * nb, part, offs, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kThreads), 0, s, src_k, src_t, N, shift, nb, offs, dst_k,
+                               dst_t);
+            uint64_t* tk = src_k; src_k = dst_k; dst_k = tk;
+            uint32_t* tt = src_t; src_t = dst_t; dst_t = tt;
+        }
+    }
+    if (src_k != kb)
+        hipLaunchKernelGGL(k_copy_pairs, dim3(grid_of(N, 8192)), dim3(kThreads), 0, s, src_k, src_t, N, kb, tb);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------- launchers ----
 
 size_t rept_inc_sort_temp_bytes(uint64_t entries, uint32_t end_bit) {
-    size_t a = 0, b = 0;
-    uint64_t* kp = nullptr;
-    uint32_t* vp = nullptr;
-    uint64_t* lp = nullptr;
-    if (rocprim::radix_sort_pairs(nullptr, a, kp, kp, vp, vp, (size_t)entries, 0, end_bit) != hipSuccess) return 0;
-    if (rocprim::inclusive_scan(nullptr, b, lp, lp, (size_t)entries, rocprim::plus<uint64_t>()) != hipSuccess) return 0;
-    const size_t m = a > b ? a : b;
-    return m ? m : 1;
+    (void)end_bit;
+    return sort_temp(entries).total;
 }
 
 hipError_t rept_inc_zero64(void* p, uint64_t words, hipStream_t s) {
@@ -288,9 +498,7 @@ hipError_t rept_inc_prepare(const IncState& st, const uint32_t* edges, uint64_t 
     hipLaunchKernelGGL(k_inc_zero64, dim3(1), dim3(64), 0, s, (uint64_t*)st.flags, (uint64_t)1);
     hipLaunchKernelGGL(k_inc_keys, dim3(grid_of(W, 8192)), dim3(kThreads), 0, s, (const uint2*)edges, W, st.n,
                        (uint32_t)st.T, st.ckey_a, st.ctim_a, st.flags);
-    size_t tb = st.temp_bytes;
-    hipError_t e = rocprim::radix_sort_pairs(st.temp, tb, st.ckey_a, st.ckey_b, st.ctim_a, st.ctim_b, (size_t)N2, 0,
-                                             st.end_bit, s);
+    hipError_t e = radix_sort_keys(st.temp, N2, st.end_bit, st.ckey_a, st.ctim_a, st.ckey_b, st.ctim_b, s);
     if (e != hipSuccess) return e;
     const uint64_t* akey = st.key[st.cur];
     hipLaunchKernelGGL(k_inc_check, dim3(grid_of(N2, 8192)), dim3(kThreads), 0, s, st.ckey_b, N2, akey, st.off,
@@ -317,8 +525,7 @@ hipError_t rept_inc_commit(IncState& st, uint64_t W, const IncCount& base, hipSt
     // the count of the chunk's edges against the merged adjacency
     uint64_t* len = st.ckey_a;  // free after the sort
     hipLaunchKernelGGL(k_inc_lens, dim3(grid_of(N2, 8192)), dim3(kThreads), 0, s, st.ckey_b, N2, st.off, len);
-    size_t tb = st.temp_bytes;
-    e = rocprim::inclusive_scan(st.temp, tb, len, st.end, (size_t)N2, rocprim::plus<uint64_t>(), s);
+    e = scan_items<uint64_t, true>(len, N2, (uint64_t*)((uint8_t*)st.temp + sort_temp(N2).part), st.end, s);
     if (e != hipSuccess) return e;
     IncCount a = base;
     a.key = st.key[st.cur];
