@@ -115,8 +115,8 @@ uint32_t bit_length(uint32_t x) { return x ? 32u - (uint32_t)__builtin_clz(x) : 
 
 // Fill the launch shape for jobs of at most G_max groups, at most c_max processors and at most
 // max_out entries in an apex list.
-rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t max_out, uint64_t zero_words,
-                        bool any_zero, const rept_tuning* tu, BatchHeader* h, bool eta = false) {
+rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t gs_max, uint32_t c_max, uint32_t max_out,
+                        uint64_t zero_words, bool any_zero, const rept_tuning* tu, BatchHeader* h, bool eta = false) {
     memset(h, 0, sizeof(*h));
     const uint32_t cus = rept_num_cus() ? rept_num_cus() : 256;
     uint32_t fit = 64;
@@ -170,11 +170,11 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
         light_b = wave_cap < 128 ? wave_cap : 128u;
     }
     auto heavy_lds = [&]() {  // the launch that runs the heavy phase (both phases if not split)
-        return rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, hist_c, light_table, heavy_table,
-                              light_b, eta, true, !split);
+        return rept_count_lds(threads, wave_cap, block_cap, b_chunk, G_max, gs_max, hist_c, light_table,
+                              heavy_table, light_b, eta, true, !split);
     };
     auto light_lds = [&]() {  // the light areas alone, in the launch that holds them
-        return rept_count_lds(split ? light_threads : threads, wave_cap, block_cap, b_chunk, G_max, hist_c,
+        return rept_count_lds(split ? light_threads : threads, wave_cap, block_cap, b_chunk, G_max, gs_max, hist_c,
                               light_table, heavy_table, light_b, eta, false, true);
     };
     // Past the 160 KB of a CU (static LDS takes a few bytes more), the light areas shrink first
@@ -232,6 +232,7 @@ rept_status make_header(uint32_t njobs, uint32_t G_max, uint32_t c_max, uint32_t
     h->light_tile = light_tile;
     h->hist_c = hist_c;
     h->G_max = G_max;
+    h->gs_max = gs_max;
     h->lds_bytes = lds;
     h->light_table = light_table;
     h->heavy_table = heavy_table;
@@ -350,7 +351,7 @@ rept_status count_one(const rept_graph* graph, const rept_params* params, uint64
             if (st != REPT_OK) return st;
             group_params(params->seed, dq.G, dq.hp, k0);  // this pass's groups of the whole seed
             BatchHeader h;
-            st = make_header(1, dq.G, dq.c, graph->max_out, zw, !accumulate, tuning, &h);
+            st = make_header(1, dq.G, dq.gs, dq.c, graph->max_out, zw, !accumulate, tuning, &h);
             if (st != REPT_OK) return st;
             if (!check) continue;
             h.any_fill = 1;
@@ -713,7 +714,7 @@ rept_status rept_count_eta(const rept_graph* graph, const rept_params* params, i
             d.es = (uint32_t)graph->E;
             d.pairs = pairs;
             BatchHeader h;
-            st = make_header(1, d.G, d.c, graph->max_out, zw, true, tuning, &h, true);
+            st = make_header(1, d.G, d.gs, d.c, graph->max_out, zw, true, tuning, &h, true);
             if (st != REPT_OK) return st;
             if (!check) continue;
             h.any_fill = 1;
@@ -879,7 +880,7 @@ rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_
     uint8_t* host = (uint8_t*)slot->buf;
     memset(host, 0, bytes);
     JobDev* hj = (JobDev*)(host + sizeof(BatchHeader));
-    uint32_t G_max = 1, c_max = 1, max_out = 0;
+    uint32_t G_max = 1, gs_max = 1, c_max = 1, max_out = 0;
     uint64_t zero_words = 0;
     bool any_zero = false, any_fill = false;
     uint64_t fill_edges = 0;
@@ -888,6 +889,7 @@ rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_
         rept_status st = make_job(jobs[j], &hj[j], &zw);
         if (st != REPT_OK) return st;
         G_max = hj[j].G > G_max ? hj[j].G : G_max;
+        gs_max = hj[j].gs > gs_max ? hj[j].gs : gs_max;
         c_max = hj[j].c > c_max ? hj[j].c : c_max;
         max_out = jobs[j].graph->max_out > max_out ? jobs[j].graph->max_out : max_out;
         if (!hj[j].accumulate) {
@@ -900,7 +902,7 @@ rept_status rept_batch_prepare(const rept_job* jobs, uint32_t njobs, const rept_
         }
     }
     BatchHeader h;
-    rept_status st = make_header(njobs, G_max, c_max, max_out, zero_words, any_zero, tuning, &h);
+    rept_status st = make_header(njobs, G_max, gs_max, c_max, max_out, zero_words, any_zero, tuning, &h);
     if (st != REPT_OK) return st;
     h.any_fill = any_fill ? 1u : 0u;
     h.fill_edges = fill_edges > UINT32_MAX ? UINT32_MAX : (uint32_t)fill_edges;

@@ -120,6 +120,7 @@ struct alignas(128) BatchHeader {
     uint32_t split_streams;  // 1: that launch runs on a second stream, beside the heavy one
     uint32_t heavy_table;    // hash slots per key, at least, in the heavy phase (2 or 4)
     uint32_t light_b;        // neighbour lists staged per chunk by a light-phase wavefront
+    uint32_t gs_max;         // slots per staged row in LDS: the widest slot-table row over jobs
     uint32_t queues[kQueues * kQueueStride];  // sub-queue counters, reset by setup
 };
 
@@ -153,8 +154,8 @@ hipError_t rept_launch_slots(const uint64_t* hp, uint32_t G, uint32_t m, const u
 // heavy / light: the launch runs the heavy / light phase; a launch running both shares one LDS
 // region between the heavy team area and the wavefronts' light areas)
 uint32_t rept_count_lds(uint32_t threads, uint32_t wave_cap, uint32_t block_cap, uint32_t b_chunk, uint32_t G,
-                        uint32_t hist_c, uint32_t light_table, uint32_t heavy_table, uint32_t light_b, bool eta,
-                        bool heavy = true, bool light = true);
+                        uint32_t gs, uint32_t hist_c, uint32_t light_table, uint32_t heavy_table, uint32_t light_b,
+                        bool eta, bool heavy = true, bool light = true);
 // resident workgroups per CU of the counting kernel for a launch shape (0 if unknown)
 uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes, bool eta);
 uint32_t rept_num_cus();

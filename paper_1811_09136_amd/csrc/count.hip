@@ -94,7 +94,9 @@ struct Area {  // one team's staging area: W side (hash table of a's list) + B s
     uint32_t bytes;
 };
 // eta: the B side also keeps each staged pair's adjacency position (Algorithm 2's counters)
-__host__ __device__ inline Area area_layout(uint32_t DW, uint32_t DB, uint32_t G, uint32_t tf, bool eta) {
+// RW: slots per staged row (the widest slot-table row of the launch's jobs: the padded group
+// count, or one keep mask for parallel MASCOT); G: groups of per-entry counters
+__host__ __device__ inline Area area_layout(uint32_t DW, uint32_t DB, uint32_t G, uint32_t RW, uint32_t tf, bool eta) {
     Area A;
     const uint32_t H = pow2_at_least(tf * DW);
     uint32_t p = 0;
@@ -102,11 +104,11 @@ __host__ __device__ inline Area area_layout(uint32_t DW, uint32_t DB, uint32_t G
     A.hidx = p; p = up16(p + 2 * H);
     A.ew = p; p = up16(p + 4 * DW);
     A.et = p; p = up16(p + 4 * DW);
-    A.wslot = p; p = up16(p + 2 * slot_width(G) * DW);
+    A.wslot = p; p = up16(p + 2 * RW * DW);
     A.cntw = p; p = up16(p + 4 * G * DW);
     A.eb = p; p = up16(p + 4 * DB);
     A.etb = p; p = up16(p + 4 * DB);
-    A.bslot = p; p = up16(p + 2 * slot_width(G) * DB);
+    A.bslot = p; p = up16(p + 2 * RW * DB);
     A.cntb = p; p = up16(p + 4 * G * DB);
     A.bpos = p; p = up16(p + 8 * (DB + 1));  // (list offset, first item) per staged list
     A.epos = p; p = eta ? up16(p + 4 * DB) : p;  // position of the pair {a, b} in the adjacency
@@ -137,12 +139,12 @@ struct Layout {
     uint32_t union_off, total;
 };
 __host__ __device__ inline Layout count_layout(uint32_t nwaves, uint32_t DL, uint32_t DW, uint32_t DB,
-                                               uint32_t G, uint32_t HC, uint32_t LT, uint32_t HT, uint32_t DLB,
-                                               bool eta, bool heavy, bool light) {
+                                               uint32_t G, uint32_t RW, uint32_t HC, uint32_t LT, uint32_t HT,
+                                               uint32_t DLB, bool eta, bool heavy, bool light) {
     Layout L;
     L.misc = misc_layout(HC);
-    L.heavy = area_layout(DW, DB, G, HT, eta);
-    L.light = area_layout(DL, DLB, G, LT, eta);
+    L.heavy = area_layout(DW, DB, G, RW, HT, eta);
+    L.light = area_layout(DL, DLB, G, RW, LT, eta);
     L.union_off = nwaves * L.misc.bytes;
     // a launch holds only the areas of the phases it runs
     const uint32_t hb = heavy ? L.heavy.bytes : 0u, lb = light ? nwaves * L.light.bytes : 0u;
@@ -1194,8 +1196,9 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const uint32_t DL = hdr->wave_cap, DW = hdr->block_cap, DB = hdr->b_chunk;
     const uint32_t GM = hdr->G_max, HC = hdr->hist_c, njobs = hdr->njobs;
-    const uint32_t LT = hdr->light_table, HT = hdr->heavy_table, DLB = hdr->light_b;
-    const Layout L = count_layout(nw, DL, DW, DB, GM, HC, LT, HT, DLB, ETA, (phases & 1u) != 0, (phases & 2u) != 0);
+    const uint32_t LT = hdr->light_table, HT = hdr->heavy_table, DLB = hdr->light_b, RW = hdr->gs_max;
+    const Layout L =
+        count_layout(nw, DL, DW, DB, GM, RW, HC, LT, HT, DLB, ETA, (phases & 1u) != 0, (phases & 2u) != 0);
     const WaveView V = wave_view(lds + wid * L.misc.bytes, L.misc);
     uint8_t* uni = lds + L.union_off;
     __shared__ uint32_t s_tile;
@@ -1392,10 +1395,10 @@ hipError_t launch_common(uint8_t* ws, const BatchHeader& h, hipStream_t s) {
 }  // namespace
 
 uint32_t rept_count_lds(uint32_t threads, uint32_t wave_cap, uint32_t block_cap, uint32_t b_chunk, uint32_t G,
-                        uint32_t hist_c, uint32_t light_table, uint32_t heavy_table, uint32_t light_b, bool eta,
-                        bool heavy, bool light) {
-    return count_layout(threads / 64, wave_cap, block_cap, b_chunk, G, hist_c, light_table, heavy_table, light_b, eta,
-                        heavy, light).total;
+                        uint32_t gs, uint32_t hist_c, uint32_t light_table, uint32_t heavy_table, uint32_t light_b,
+                        bool eta, bool heavy, bool light) {
+    return count_layout(threads / 64, wave_cap, block_cap, b_chunk, G, gs, hist_c, light_table, heavy_table, light_b,
+                        eta, heavy, light).total;
 }
 
 uint32_t rept_count_blocks_per_cu(uint32_t threads, uint32_t lds_bytes, bool eta) {
