@@ -411,7 +411,10 @@ class Server:
                 # nothing moved: wait for the event that comes first
                 if inflight and (active or draining):
                     tok = inflight[0]
-                    if pending:
+                    # the last launch of the one request in service: a newcomer arriving meanwhile
+                    # would be held until it completes, so block on it as the plain loop does
+                    lone = self.hold_lone_newcomer and len(draining) == 1 and not (active or building or waiting)
+                    if pending and not lone:
                         # the oldest launch, or the next arrival if it comes first
                         while not ready(tok) and now() < pending[0].arrival_s:
                             sleep(0)
