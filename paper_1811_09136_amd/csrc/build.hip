@@ -454,6 +454,7 @@ __global__ void k_slice_base(uint32_t* __restrict__ scount, const uint32_t* __re
     }
 }
 
+constexpr uint32_t PLACE_UNROLL = 4;
 // place the slice's entries in their segments (as k_scatter below, with LDS cursors); with
 // `rcnt`, also count the reverse pairs per target shard (the shard path of the reverse lists)
 constexpr uint32_t REV_BIT = 0x80000000u;
@@ -473,15 +474,33 @@ __global__ void __launch_bounds__(1024) k_slice_place(const uint4* __restrict__ 
     for (uint32_t i = threadIdx.x; i < span; i += blockDim.x) cur[i] = base[i];
     __syncthreads();
     unsigned long long work = 0;
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const uint4 e = opart[i];
-        const uint32_t pos = atomicAdd(&cur[e.x - v0], 1u);
-        const uint32_t da = dout[e.x], db = dout[e.y];
-        // the counting pass walks the shorter out-list of the pair (see emit_rev)
-        const bool rev = da < db;
-        packed[pos] = ((unsigned long long)e.y << 32) | (rev ? REV_BIT : 0u) | e.z;
-        work += db <= da ? db : da;
-        if (rev && rcnt) atomicAdd(&rcnt[(uint64_t)e.y * REV_SHARDS + (e.x % REV_SHARDS)], 1u);
+    // PLACE_UNROLL entries per thread per step, one block stride apart: their loads, cursor
+    // atomics and scattered stores are in flight together
+    const uint64_t stride = blockDim.x;
+    for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += PLACE_UNROLL * stride) {
+        uint4 e[PLACE_UNROLL];
+        uint32_t pos[PLACE_UNROLL], da[PLACE_UNROLL], db[PLACE_UNROLL];
+#pragma unroll
+        for (uint32_t u = 0; u < PLACE_UNROLL; ++u) {
+            const uint64_t i = i0 + u * stride;
+            e[u] = i < hi ? opart[i] : make_uint4(v0, v0, 0u, 0u);
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < PLACE_UNROLL; ++u) {
+            const bool ok = i0 + u * stride < hi;
+            pos[u] = ok ? atomicAdd(&cur[e[u].x - v0], 1u) : 0u;
+            da[u] = ok ? dout[e[u].x] : 0u;
+            db[u] = ok ? dout[e[u].y] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < PLACE_UNROLL; ++u) {
+            if (i0 + u * stride >= hi) continue;
+            // the counting pass walks the shorter out-list of the pair (see emit_rev)
+            const bool rev = da[u] < db[u];
+            packed[pos[u]] = ((unsigned long long)e[u].y << 32) | (rev ? REV_BIT : 0u) | e[u].z;
+            work += db[u] <= da[u] ? db[u] : da[u];
+            if (rev && rcnt) atomicAdd(&rcnt[(uint64_t)e[u].y * REV_SHARDS + (e[u].x % REV_SHARDS)], 1u);
+        }
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) work += __shfl_xor(work, d, 64);
@@ -545,12 +564,28 @@ __global__ void __launch_bounds__(1024) k_rev_place(const uint4* __restrict__ rp
     const uint32_t* base = sbase + (uint64_t)blockIdx.x * span;
     for (uint32_t i = threadIdx.x; i < span; i += blockDim.x) cur[i] = base[i];
     __syncthreads();
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const uint4 e = rpart[i];
-        const uint32_t q = atomicAdd(&cur[e.x - v0], 1u);
-        const uint32_t s = off[e.y];
-        rrec[q] = make_uint4(e.y, e.z, s, off[e.y + 1] - s);
-        rpos[q] = e.w;
+    const uint64_t stride = blockDim.x;
+    for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += PLACE_UNROLL * stride) {
+        uint4 e[PLACE_UNROLL];
+        uint32_t q[PLACE_UNROLL], s[PLACE_UNROLL], d[PLACE_UNROLL];
+#pragma unroll
+        for (uint32_t u = 0; u < PLACE_UNROLL; ++u) {
+            const uint64_t i = i0 + u * stride;
+            e[u] = i < hi ? rpart[i] : make_uint4(v0, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < PLACE_UNROLL; ++u) {
+            const bool ok = i0 + u * stride < hi;
+            q[u] = ok ? atomicAdd(&cur[e[u].x - v0], 1u) : 0u;
+            s[u] = ok ? off[e[u].y] : 0u;
+            d[u] = ok ? off[e[u].y + 1] - s[u] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < PLACE_UNROLL; ++u) {
+            if (i0 + u * stride >= hi) continue;
+            rrec[q[u]] = make_uint4(e[u].y, e[u].z, s[u], d[u]);
+            rpos[q[u]] = e[u].w;
+        }
     }
 }
 
