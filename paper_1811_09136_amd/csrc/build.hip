@@ -264,8 +264,9 @@ __global__ void __launch_bounds__(1024) k_deg_count(const uint32_t* __restrict__
     }
 }
 
-// Reverse-list counters per target: REV_SHARDS shards (by source mod REV_SHARDS), so a hub's
-// increments spread over that many addresses.
+// Reverse-list counters per target on the shard path (graphs whose buckets are wider than
+// DEG_SUB ids): REV_SHARDS shards (by source mod REV_SHARDS), so a hub's increments spread over
+// that many addresses.
 constexpr uint32_t REV_SHARDS = 8;
 
 // an invalid edge's orientation
@@ -635,11 +636,12 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scatter(const uint2* __restric
 
 // Reverse lists.  The counting pass finds a triangle from its lowest-ranked oriented pair
 // a -> b by walking the shorter of out(a), out(b) against a hash of the other.  Pairs with
-// out(a) shorter are counted at b: rev(b) lists them, cut into REV_SHARDS shards.  k_scatter
-// counts each shard, a scan gives the shard starts, and the segment sorts, which know each
-// entry's final position, write the records (emit_rev).  A record carries what the counting
-// pass stages for the pair -- a, the arrival time of a-b, the offset and length of a's list --
-// and the position of b in a's list.
+// out(a) shorter are counted at b: rev(b) lists them.  A record carries what the counting pass
+// stages for the pair -- a, the arrival time of a-b, the offset and length of a's list -- and
+// the position of b in a's list.  They are built by the bucketed transpose (k_rev_hist,
+// k_rev_part, k_rev_place) or, on the shard path, cut into REV_SHARDS shards per target:
+// k_scatter counts each shard, a scan gives the shard starts, and the segment sorts, which know
+// each entry's final position, write the records (emit_rev).
 
 // roff[b] = start of b's first shard (roff[n] = the number of pairs)
 __global__ void k_rev_roff(const uint32_t* __restrict__ sofs, uint32_t n, uint32_t* __restrict__ roff,
@@ -1108,8 +1110,12 @@ ScratchLayout scratch_layout(uint32_t n, uint64_t E) {
     ScratchLayout S;
     size_t p = 0;
     const DegPlan D = deg_plan(n, E);
-    const size_t nhist = (size_t)D.NB * D.nblk, nshard = (size_t)n * REV_SHARDS;
-    const size_t scan_max = (nhist > nshard ? nhist : nshard) + 1;
+    // per-target shard counters of the reverse pairs only where the reverse lists are built
+    // with shard cursors (buckets wider than DEG_SUB ids); the transpose needs none
+    const bool sliced = D.shift <= 13;
+    const size_t nhist = (size_t)D.NB * D.nblk, nshard = sliced ? 0 : (size_t)n * REV_SHARDS;
+    size_t scan_max = nhist > nshard ? nhist : nshard;
+    scan_max = (scan_max > (size_t)n ? scan_max : (size_t)n) + 1;  // the scans over nodes too
     const size_t nparts = (scan_max + SCAN_TILE - 1) / SCAN_TILE + 1;
     S.stats = p;
     p += align256(sizeof(BuildStats));
@@ -1133,7 +1139,6 @@ ScratchLayout scratch_layout(uint32_t n, uint64_t E) {
     p += align256((size_t)E * 16);
     // placement slices (bucket spans of at most DEG_SUB ids): their offsets per bucket and their
     // per-node counts, then bases
-    const bool sliced = D.shift <= 13;
     const uint64_t smax = sliced ? (E + SLICE_ENTRIES - 1) / SLICE_ENTRIES + D.NB : 0;
     S.slice_off = p;
     p += align256(((size_t)D.NB + 1) * 4);
