@@ -272,6 +272,15 @@ constexpr uint32_t REV_SHARDS = 8;
 // an invalid edge's orientation
 constexpr uint32_t NO_EDGE = 0xffffffffu;
 
+// an oriented entry in the partition by the bucket of its lower endpoint: (a, b, t), 12 bytes
+struct OEntry {
+    uint32_t a, b, t;
+};
+// the node by whose bucket a partition entry is placed: a of an oriented entry, the target b
+// (first word) of a reverse pair
+__device__ __forceinline__ uint32_t entry_key(const OEntry& e) { return e.a; }
+__device__ __forceinline__ uint32_t entry_key(const uint4& e) { return e.x; }
+
 __global__ void k_copy_u32(const uint32_t* __restrict__ src, uint64_t count, uint32_t* __restrict__ dst) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
@@ -312,7 +321,7 @@ __global__ void __launch_bounds__(1024) k_orient_hist(const uint2* __restrict__ 
 // the oriented entries (a, b, t) in bucket order of a (order within a bucket is free)
 __global__ void __launch_bounds__(1024) k_orient_part(const uint2* __restrict__ ab, uint64_t E, uint32_t shift,
                                                       uint32_t NB, uint64_t per_block,
-                                                      const uint32_t* __restrict__ boff, uint4* __restrict__ opart) {
+                                                      const uint32_t* __restrict__ boff, OEntry* __restrict__ opart) {
     __shared__ uint32_t base[DEG_BUCKETS];
     for (uint32_t b = threadIdx.x; b < NB; b += blockDim.x) base[b] = boff[(uint64_t)b * gridDim.x + blockIdx.x];
     __syncthreads();
@@ -321,13 +330,13 @@ __global__ void __launch_bounds__(1024) k_orient_part(const uint2* __restrict__ 
     for (uint64_t t = e0 + threadIdx.x; t < e1; t += blockDim.x) {
         const uint2 e = ab[t];
         if (e.x == NO_EDGE) continue;
-        opart[atomicAdd(&base[e.x >> shift], 1u)] = make_uint4(e.x, e.y, (uint32_t)t, 0u);
+        opart[atomicAdd(&base[e.x >> shift], 1u)] = OEntry{e.x, e.y, (uint32_t)t};
     }
 }
 
 // out-degrees: workgroups take fixed slices of the partition and count each bucket's part of
 // the slice in LDS, one atomic per distinct node (`dout` zero on entry)
-__global__ void __launch_bounds__(1024) k_out_count(const uint4* __restrict__ opart,
+__global__ void __launch_bounds__(1024) k_out_count(const OEntry* __restrict__ opart,
                                                     const uint32_t* __restrict__ boff, uint32_t nblk, uint32_t NB,
                                                     uint32_t shift, uint32_t n, uint32_t* __restrict__ dout) {
     __shared__ uint32_t cnt[DEG_SUB];
@@ -335,7 +344,7 @@ __global__ void __launch_bounds__(1024) k_out_count(const uint4* __restrict__ op
     const uint64_t span = (uint64_t)1 << shift;
     for (uint64_t s0 = (uint64_t)blockIdx.x * DEG_SLICE; s0 < total; s0 += (uint64_t)gridDim.x * DEG_SLICE) {
         const uint64_t s1 = (s0 + DEG_SLICE) < total ? (s0 + DEG_SLICE) : total;
-        const uint32_t b_first = opart[s0].x >> shift, b_last = opart[s1 - 1].x >> shift;
+        const uint32_t b_first = opart[s0].a >> shift, b_last = opart[s1 - 1].a >> shift;
         for (uint32_t b = b_first; b <= b_last; ++b) {
             const uint64_t start = boff[(uint64_t)b * nblk];
             const uint64_t end = (b + 1 < NB) ? boff[(uint64_t)(b + 1) * nblk] : total;
@@ -346,7 +355,7 @@ __global__ void __launch_bounds__(1024) k_out_count(const uint4* __restrict__ op
                 for (uint32_t i = threadIdx.x; i < DEG_SUB; i += blockDim.x) cnt[i] = 0;
                 __syncthreads();
                 for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-                    const uint64_t x = (uint64_t)opart[i].x - v0 - r0;
+                    const uint64_t x = (uint64_t)opart[i].a - v0 - r0;
                     if (x < DEG_SUB) atomicAdd(&cnt[x], 1u);
                 }
                 __syncthreads();
@@ -412,7 +421,8 @@ __device__ __forceinline__ bool slice_of(uint32_t s, const uint32_t* __restrict_
 }
 
 // per slice, its entries per node of its bucket: scnt[s][i] for node (b << shift) + i
-__global__ void __launch_bounds__(1024) k_slice_count(const uint4* __restrict__ opart,
+template <typename T>
+__global__ void __launch_bounds__(1024) k_slice_count(const T* __restrict__ opart,
                                                       const uint32_t* __restrict__ boff, uint32_t nblk, uint32_t NB,
                                                       uint32_t shift, const uint32_t* __restrict__ slice_off,
                                                       uint32_t* __restrict__ scount) {
@@ -423,7 +433,7 @@ __global__ void __launch_bounds__(1024) k_slice_count(const uint4* __restrict__ 
     const uint32_t span = 1u << shift, v0 = b << shift;
     for (uint32_t i = threadIdx.x; i < span; i += blockDim.x) cnt[i] = 0;
     __syncthreads();
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&cnt[opart[i].x - v0], 1u);
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&cnt[entry_key(opart[i]) - v0], 1u);
     __syncthreads();
     uint32_t* out = scount + (uint64_t)blockIdx.x * span;
     for (uint32_t i = threadIdx.x; i < span; i += blockDim.x) out[i] = cnt[i];
@@ -459,7 +469,7 @@ constexpr uint32_t PLACE_UNROLL = 4;
 // place the slice's entries in their segments (as k_scatter below, with LDS cursors); with
 // `rcnt`, also count the reverse pairs per target shard (the shard path of the reverse lists)
 constexpr uint32_t REV_BIT = 0x80000000u;
-__global__ void __launch_bounds__(1024) k_slice_place(const uint4* __restrict__ opart,
+__global__ void __launch_bounds__(1024) k_slice_place(const OEntry* __restrict__ opart,
                                                       const uint32_t* __restrict__ boff, uint32_t nblk, uint32_t NB,
                                                       uint32_t shift, const uint32_t* __restrict__ slice_off,
                                                       const uint32_t* __restrict__ sbase,
@@ -479,28 +489,28 @@ __global__ void __launch_bounds__(1024) k_slice_place(const uint4* __restrict__ 
     // atomics and scattered stores are in flight together
     const uint64_t stride = blockDim.x;
     for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += PLACE_UNROLL * stride) {
-        uint4 e[PLACE_UNROLL];
+        OEntry e[PLACE_UNROLL];
         uint32_t pos[PLACE_UNROLL], da[PLACE_UNROLL], db[PLACE_UNROLL];
 #pragma unroll
         for (uint32_t u = 0; u < PLACE_UNROLL; ++u) {
             const uint64_t i = i0 + u * stride;
-            e[u] = i < hi ? opart[i] : make_uint4(v0, v0, 0u, 0u);
+            e[u] = i < hi ? opart[i] : OEntry{v0, v0, 0u};
         }
 #pragma unroll
         for (uint32_t u = 0; u < PLACE_UNROLL; ++u) {
             const bool ok = i0 + u * stride < hi;
-            pos[u] = ok ? atomicAdd(&cur[e[u].x - v0], 1u) : 0u;
-            da[u] = ok ? dout[e[u].x] : 0u;
-            db[u] = ok ? dout[e[u].y] : 0u;
+            pos[u] = ok ? atomicAdd(&cur[e[u].a - v0], 1u) : 0u;
+            da[u] = ok ? dout[e[u].a] : 0u;
+            db[u] = ok ? dout[e[u].b] : 0u;
         }
 #pragma unroll
         for (uint32_t u = 0; u < PLACE_UNROLL; ++u) {
             if (i0 + u * stride >= hi) continue;
             // the counting pass walks the shorter out-list of the pair (see emit_rev)
             const bool rev = da[u] < db[u];
-            packed[pos[u]] = ((unsigned long long)e[u].y << 32) | (rev ? REV_BIT : 0u) | e[u].z;
+            packed[pos[u]] = ((unsigned long long)e[u].b << 32) | (rev ? REV_BIT : 0u) | e[u].t;
             work += db[u] <= da[u] ? db[u] : da[u];
-            if (rev && rcnt) atomicAdd(&rcnt[(uint64_t)e[u].y * REV_SHARDS + (e[u].x % REV_SHARDS)], 1u);
+            if (rev && rcnt) atomicAdd(&rcnt[(uint64_t)e[u].b * REV_SHARDS + (e[u].a % REV_SHARDS)], 1u);
         }
     }
 #pragma unroll
@@ -1135,7 +1145,8 @@ ScratchLayout scratch_layout(uint32_t n, uint64_t E) {
     p += align256((size_t)E * 8);
     S.alt = p;
     p += align256((size_t)E * 8);
-    S.opart = p;  // oriented entries (a, b, t) partitioned by the bucket of a
+    S.opart = p;  // oriented entries (a, b, t), 12 bytes, partitioned by the bucket of a; later the
+                  // reverse marks (4 bytes per edge)
     p += align256((size_t)E * 16);
     // placement slices (bucket spans of at most DEG_SUB ids): their offsets per bucket and their
     // per-node counts, then bases
@@ -1212,7 +1223,7 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     uint32_t* part = (uint32_t*)(X + S.part);
     unsigned long long* packed = (unsigned long long*)(X + S.packed);
     unsigned long long* alt = (unsigned long long*)(X + S.alt);
-    uint4* opart = (uint4*)(X + S.opart);
+    OEntry* opart = (OEntry*)(X + S.opart);
     uint32_t* slice_off = (uint32_t*)(X + S.slice_off);
     uint32_t* scount = (uint32_t*)(X + S.scount);
     uint32_t* medium = (uint32_t*)(X + S.medium);
@@ -1287,7 +1298,8 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
     const uint64_t smax = (E + SLICE_ENTRIES - 1) / SLICE_ENTRIES + D.NB;
     if (sliced) {  // placement by slices of the partition, LDS cursors
         hipLaunchKernelGGL(k_slice_plan, dim3(1), dim3(1024), 0, s, bscan, D.nblk, D.NB, slice_off);
-        hipLaunchKernelGGL(k_slice_count, dim3((uint32_t)smax), dim3(1024), 0, s, opart, bscan, D.nblk, D.NB,
+        hipLaunchKernelGGL(k_slice_count<OEntry>, dim3((uint32_t)smax), dim3(1024), 0, s, (const OEntry*)opart, bscan,
+                           D.nblk, D.NB,
                            D.shift, slice_off, scount);
         hipLaunchKernelGGL(k_slice_dout, dim3(gN), dim3(256), 0, s, scount, slice_off, D.shift, n, dout);
         if (scan_u32(dout, n, part, off, s) != hipSuccess) return REPT_EDEVICE;
@@ -1337,7 +1349,7 @@ rept_status rept_build_impl(uint32_t n, const uint32_t* edges, uint64_t E, void*
         hipLaunchKernelGGL(k_rev_part, dim3(D.nblk), dim3(1024), 0, s, rsrc, nbr, tim, off, n, D.shift, D.NB,
                            D.per_block, bscan, rpart);
         hipLaunchKernelGGL(k_slice_plan, dim3(1), dim3(1024), 0, s, bscan, D.nblk, D.NB, slice_off);
-        hipLaunchKernelGGL(k_slice_count, dim3((uint32_t)smax), dim3(1024), 0, s, (const uint4*)rpart, bscan,
+        hipLaunchKernelGGL(k_slice_count<uint4>, dim3((uint32_t)smax), dim3(1024), 0, s, (const uint4*)rpart, bscan,
                            D.nblk, D.NB, D.shift, slice_off, scount);
         hipLaunchKernelGGL(k_slice_dout, dim3(gN), dim3(256), 0, s, scount, slice_off, D.shift, n, rcnt);
         if (scan_u32(rcnt, n, part, roff, s) != hipSuccess) return REPT_EDEVICE;
