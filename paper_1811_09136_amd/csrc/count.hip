@@ -53,6 +53,17 @@ __device__ __forceinline__ void team_sync() {
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
 
+// A value that is the same in every active lane, in a scalar register.  The compiler cannot
+// see that a value read from LDS or exchanged between lanes is uniform; in a scalar register,
+// the loops and branches on it take scalar instructions instead of exec-mask control flow.
+// (Applied only where it was measured to pay: scalar registers are scarce in k_count, and
+// their spills cost vector instructions.)
+__device__ __forceinline__ uint32_t wave_uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+// lane u's value (u uniform), in a scalar register
+__device__ __forceinline__ uint32_t lane_val(uint32_t v, uint32_t u) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)u);
+}
+
 // Inclusive prefix sum over the 64 lanes with DPP: shifts by 1, 2, 4, 8 within rows of 16
 // lanes, then row 0's and row 2's last lanes broadcast into rows 1 and 3 (row_bcast:15), then
 // lane 31 into rows 2 and 3 (row_bcast:31).  Lanes without a source add zero.
@@ -373,12 +384,13 @@ __device__ __forceinline__ void hash_insert(uint32_t* hkey, uint16_t* hidx, uint
     }
 }
 
-// largest i in [0, cnt) with bpos[i].y <= it, given bpos[0].y <= it < bpos[cnt].y
+// largest i in [0, cnt) with bpos[i].y <= it, given bpos[0].y <= it < bpos[cnt].y (cnt and it
+// the same in every lane: the search runs in scalar registers)
 __device__ __forceinline__ uint32_t find_seg(const uint2* bpos, uint32_t cnt, uint32_t it) {
     uint32_t lo = 0, hi = cnt;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (bpos[mid].y <= it) lo = mid; else hi = mid;
+        if (wave_uni(bpos[mid].y) <= it) lo = mid; else hi = mid;
     }
     return lo;
 }
@@ -399,7 +411,7 @@ template <bool BLOCK>
 __device__ __forceinline__ uint32_t team_excl_scan(uint32_t v, uint32_t* red, uint32_t& total) {
     const uint32_t inc = wave_incl_scan(v);
     if (!BLOCK) {
-        total = __shfl(inc, 63, 64);
+        total = lane_val(inc, 63);
         return inc - v;
     }
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -412,7 +424,7 @@ __device__ __forceinline__ uint32_t team_excl_scan(uint32_t v, uint32_t* red, ui
         tot += x;
     }
     __syncthreads();
-    total = tot;
+    total = wave_uni(tot);
     return pre + inc - v;
 }
 
@@ -606,8 +618,11 @@ __device__ void walk_items(const JobRegs& J, const TeamView& T, const WaveView& 
     const uint32_t lane = lane_id();
     const uint32_t bmask = (1u << kbits) - 1u;
     uint32_t qn = 0;
+    it_begin = wave_uni(it_begin);
+    it_end = wave_uni(it_end);
+    bn = wave_uni(bn);
     if (it_begin >= it_end) return;
-    uint32_t i0 = find_seg(T.bpos, bn, it_begin);  // owner of the first item (uniform)
+    uint32_t i0 = wave_uni(find_seg(T.bpos, bn, it_begin));  // owner of the first item
     for (uint32_t base = it_begin; base < it_end; base += R) {
         uint32_t own[kWalk], p[kWalk], w[kWalk];
         bool valid[kWalk];
@@ -1241,7 +1256,7 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
         for (;;) {
             uint32_t tile = 0;
             if (lane == 0) tile = claim_tile(hdr->queues + kLightQueue, total, q, left);
-            tile = __shfl(tile, 0, 64);
+            tile = lane_val(tile, 0);
             if (tile >= total) break;
             const uint32_t j = find_job(jobs, njobs, tile, false);
             if ((int)j != cur) {
@@ -1253,7 +1268,8 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
             const JobDev& JD = jobs[j];
             const uint32_t ub = JD.unit0 + JD.n_heavy + (tile - JD.light_prefix) * tile_len;
             const uint32_t ue = (ub + tile_len) < JD.unit1 ? (ub + tile_len) : JD.unit1;
-            // the tile's apexes and their list bounds, loaded together (lane i: unit ub + i)
+            // the tile's apexes and their list bounds, loaded together (lane i: unit ub + i), then
+            // handed to the unit loop in scalar registers
             uint32_t ta = 0, ts = 0, td = 0, tr = 0, trn = 0;
             if (ub + lane < ue) {
                 ta = ldg(J.apex + ub + lane);
@@ -1263,8 +1279,8 @@ __global__ void __launch_bounds__(1024) k_count(BatchHeader* hdr, const JobDev* 
                 trn = ldg(J.roff + ta + 1) - tr;
             }
             for (uint32_t u = 0; u < ue - ub; ++u)
-                count_apex<false, ETA>(J, T, V, __shfl(ta, u, 64), __shfl(ts, u, 64), __shfl(td, u, 64), __shfl(tr, u, 64),
-                                  __shfl(trn, u, 64));
+                count_apex<false, ETA>(J, T, V, lane_val(ta, u), lane_val(ts, u), lane_val(td, u), lane_val(tr, u),
+                                       lane_val(trn, u));
         }
     }
     flush_hist(J, V, cur);
