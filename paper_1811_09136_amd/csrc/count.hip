@@ -428,11 +428,18 @@ __device__ __forceinline__ uint32_t team_excl_scan(uint32_t v, uint32_t* red, ui
     return pre + inc - v;
 }
 
-// sum over the team, 64-bit (the per-thread parts may exceed 32 bits together)
+// sum over the team, 64-bit (the per-thread parts may exceed 32 bits together).  Within a
+// wavefront the part is summed with the DPP scan, which needs no LDS permutes (unlike lane
+// shuffles): in one 32-bit pass if the caller knows the wavefront's sum is below 2^32
+// (`narrow`), else in three pieces of 26, 26 and 12 bits, whose 64-lane sums stay below 2^32
+// and so are exact in 32 bits.
 template <bool BLOCK>
-__device__ __forceinline__ uint64_t team_sum64(uint64_t v, uint32_t* red) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+__device__ __forceinline__ uint64_t team_sum64(uint64_t v, uint32_t* red, bool narrow) {
+    if (narrow)
+        v = wave_sum((uint32_t)v);
+    else
+        v = (uint64_t)wave_sum((uint32_t)v & 0x3ffffffu) + ((uint64_t)wave_sum((uint32_t)(v >> 26) & 0x3ffffffu) << 26) +
+            ((uint64_t)wave_sum((uint32_t)(v >> 52)) << 52);
     if (!BLOCK) return v;
     const uint32_t lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     uint64_t* red64 = (uint64_t*)(red + 16);  // words 16..47: up to 16 wavefronts
@@ -893,7 +900,10 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
             team_sync<BLOCK>();
         }
         if (!J.per_proc) {
-            // flush the w-side counts; their sum per group is a's own count for this chunk
+            // flush the w-side counts; their sum per group is a's own count for this chunk.  A W
+            // entry gains at most one per list walked against it, so that sum is at most
+            // wn * nbtot: below 2^32 (every light unit) one 32-bit pass sums it
+            const bool narrow = (uint64_t)wn * nbtot < (1ull << 32);
             for (uint32_t g = 0; g < G; ++g) {
                 uint64_t part = 0;
                 for (uint32_t i = tid; i < wn; i += nt) {
@@ -903,7 +913,7 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
                         part += v;
                     }
                 }
-                const uint64_t tot = team_sum64<BLOCK>(part, T.red);
+                const uint64_t tot = team_sum64<BLOCK>(part, T.red, narrow);
                 if (tid == 0 && tot) add64(J.local + (uint64_t)g * J.n + a, tot);
             }
         }
