@@ -902,8 +902,10 @@ __device__ void count_apex(const JobRegs& J, const TeamView& T, const WaveView& 
         if (!J.per_proc) {
             // flush the w-side counts; their sum per group is a's own count for this chunk.  A W
             // entry gains at most one per list walked against it, so that sum is at most
-            // wn * nbtot: below 2^32 (every light unit) one 32-bit pass sums it
-            const bool narrow = (uint64_t)wn * nbtot < (1ull << 32);
+            // wn * nbtot: a light unit's is below 2^32 and one 32-bit pass sums it.  A team of a
+            // heavy unit always takes the three-piece sum (a few instructions per unit there), so
+            // every graph with heavy and light units runs both forms.
+            const bool narrow = !BLOCK && (uint64_t)wn * nbtot < (1ull << 32);
             for (uint32_t g = 0; g < G; ++g) {
                 uint64_t part = 0;
                 for (uint32_t i = tid; i < wn; i += nt) {

@@ -10,9 +10,9 @@ stream's exact tau is 10,286,644,549).  The bounds, read from the kernel sources
   before the items since the last flush would pass 2^31, with at most kRun items per run;
 * a staged entry's local counter gains at most one per list walked against it (fewer than
   2 * 2^31 lists: streams hold fewer than 2^31 edges) or per entry of its table chunk (<= 4096),
-  and a unit's own count is summed in 64 bits: in one 32-bit pass only when the chunk's W
-  entries times the unit's lists is below 2^32 (each W entry gains at most one per list), else in
-  pieces of 26, 26 and 12 bits whose 64-lane sums stay below 2^32.
+  and a unit's own count is summed in 64 bits: for a light unit in one 32-bit pass when the
+  chunk's W entries times the unit's lists is below 2^32 (each W entry gains at most one per
+  list), else in pieces of 26, 26 and 12 bits whose 64-lane sums stay below 2^32.
 """
 import os
 import re
@@ -55,7 +55,7 @@ def test_incremental_histogram_bound():
 def test_unit_total_is_64_bit():
     s = _src("count.hip")
     assert "const uint64_t tot = team_sum64<BLOCK>(part, T.red, narrow);" in s
-    assert "const bool narrow = (uint64_t)wn * nbtot < (1ull << 32);" in s
+    assert "const bool narrow = !BLOCK && (uint64_t)wn * nbtot < (1ull << 32);" in s
     assert "uint32_t team_sum(" not in s
     # the wide path's pieces: 26, 26 and 12 bits of a 64-bit part, each summed over 64 lanes in 32 bits
     assert "wave_sum((uint32_t)v & 0x3ffffffu)" in s
