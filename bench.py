@@ -221,8 +221,10 @@ def bench_mascot(dev, edges, n: int, m: int, c: int = 8, reps: int = 3):
 
 def bench_incremental(dev, edges, n: int, m: int, c: int, ref_glob, chunks: int = 10):
     """The same stream appended in `chunks` equal chunks (rept_stream_append: validate, merge,
-    count each chunk's edges against the earlier ones); per-append latency and whole-stream
-    throughput, and the final counters must equal the one-shot count's."""
+    count the chunk's edges by the default policy, which picks per append between counting edge
+    by edge against the earlier edges and a windowed recount of the prefix); per-append latency
+    and whole-stream throughput, and the same with every append counted edge by edge.  The final
+    counters must equal the one-shot count's."""
     import numpy as np
     import torch
     from paper_1811_09136_amd import rept
@@ -231,24 +233,34 @@ def bench_incremental(dev, edges, n: int, m: int, c: int, ref_glob, chunks: int 
     d_edges = rept.to_device_edges(edges, dev)
     params = rept.Params(m, c, HASH_SEED)
     res = {"chunks": chunks, "chunk_edges": step}
-    for rep in range(2):  # the first pass warms the code objects
-        inc = rept.IncrementalStream(n, E, step, params, dev)
-        torch.cuda.synchronize()
-        lat = []
-        t0 = time.perf_counter()
-        for a in range(0, E, step):
-            ta = time.perf_counter()
-            inc.append(d_edges[a:a + step])
+
+    def run(policy):
+        for rep in range(2):  # the first pass warms the code objects
+            inc = rept.IncrementalStream(n, E, step, params, dev, policy=policy)
             torch.cuda.synchronize()
-            lat.append(1e3 * (time.perf_counter() - ta))
-        total = time.perf_counter() - t0
-        same = bool(np.array_equal(inc.counts[0].cpu().numpy(), ref_glob))
-        inc.close()
-        del inc
-    if not same:
-        raise RuntimeError("incremental counters disagree with the one-shot count")
+            lat = []
+            t0 = time.perf_counter()
+            for a in range(0, E, step):
+                ta = time.perf_counter()
+                inc.append(d_edges[a:a + step])
+                torch.cuda.synchronize()
+                lat.append(1e3 * (time.perf_counter() - ta))
+            total = time.perf_counter() - t0
+            same = bool(np.array_equal(inc.counts[0].cpu().numpy(), ref_glob))
+            paths = inc.paths()
+            inc.close()
+            del inc
+        if not same:
+            raise RuntimeError(f"incremental counters ({policy}) disagree with the one-shot count")
+        return total, lat, same, paths
+
+    total, lat, same, paths = run("auto")
     res.update({"total_ms": 1e3 * total, "edges_per_s": E / total, "append_ms_first": lat[0],
-                "append_ms_last": lat[-1], "append_ms_median": float(np.median(lat)), "equal_to_one_shot": same})
+                "append_ms_last": lat[-1], "append_ms_median": float(np.median(lat)), "equal_to_one_shot": same,
+                "appends_per_edge": paths[0], "appends_recount": paths[1]})
+    total_pe, lat_pe, _, _ = run("per_edge")
+    res.update({"per_edge_total_ms": 1e3 * total_pe, "per_edge_append_ms_first": lat_pe[0],
+                "per_edge_append_ms_last": lat_pe[-1]})
     return res
 
 

@@ -310,18 +310,27 @@ rept_status rept_hash_slots(const rept_params* params, const uint32_t* edges, ui
  * on the stream appended so far.
  *
  * The device keeps the whole adjacency of the edges seen so far (both directions, sorted by
- * neighbour, arrival time beside each entry).  An append sorts and validates the chunk, merges
- * it into the adjacency in one pass, and counts each chunk edge against the edges that arrived
- * before it (one work item per entry of its endpoints' shorter list).  The cost of an append is
- * linear in the edges so far plus the chunk's intersection work.
+ * neighbour, arrival time beside each entry) and the stream in arrival order.  An append sorts
+ * and validates the chunk and merges it into the adjacency in one pass.  It then counts the
+ * chunk's edges in one of two ways, with equal results:
+ *   - edge by edge: each chunk edge against the edges that arrived before it, one work item (a
+ *     binary search) per entry of its endpoints' shorter list;
+ *   - by a windowed recount: rept_build of the whole stream so far, then rept_count_range over
+ *     the chunk's times (a triangle's updates belong to the time of its last edge).
+ * By default (REPT_STREAM_AUTO) an append recounts when its work items exceed 10 per edge so far,
+ * the ratio of the two costs measured on a 20M-edge power-law stream; rept_stream_set_policy
+ * fixes either way.  A recount needs one more stream synchronisation (the build's) and the
+ * build's regions of the buffer.
  */
 typedef struct rept_stream rept_stream; /* opaque host-side handle */
 
 /* Device bytes for a stream of up to `capacity` edges over n nodes, appended in chunks of at
- * most `max_chunk` edges: 48 bytes per edge of capacity, 64 per edge of chunk, 8 per node, and
- * the sort's temporary storage, whose size depends on the device (queried from the current
- * device; no device work).  EINVAL if n == 0, n > 2^29, capacity == 0, capacity >= 2^31,
- * max_chunk == 0 or max_chunk > capacity; EDEVICE if the device cannot be queried. */
+ * most `max_chunk` edges: 48 bytes per edge of capacity, 64 per edge of chunk, 8 per node, the
+ * sort's temporary storage, and for the windowed recount 24 bytes per edge of capacity (the
+ * stream in arrival order and a slot table of up to 8 groups) plus rept_query_sizes(n,
+ * capacity)'s persistent and scratch bytes.  Host only, no device work.  EINVAL if n == 0,
+ * n > 2^29, capacity == 0, capacity >= 2^31, max_chunk == 0 or max_chunk > capacity; EDEVICE if
+ * the sizes cannot be formed. */
 rept_status rept_stream_query_sizes(uint32_t n, uint64_t capacity, uint64_t max_chunk, size_t* bytes);
 
 /*
@@ -352,6 +361,18 @@ rept_status rept_stream_append(rept_stream* s, const uint32_t* edges, uint64_t n
 
 /* Edges appended so far (host only). */
 rept_status rept_stream_num_edges(const rept_stream* s, uint64_t* num_edges);
+
+/* How later appends count their edges (host only; results are equal either way):
+ * REPT_STREAM_AUTO (default) chooses per append by its work, REPT_STREAM_PER_EDGE always counts
+ * edge by edge, REPT_STREAM_RECOUNT always recounts the window (falling back to edge by edge for
+ * a prefix that would not fit the buffer's build regions).  EINVAL for a bad handle or policy. */
+#define REPT_STREAM_AUTO 0u
+#define REPT_STREAM_PER_EDGE 1u
+#define REPT_STREAM_RECOUNT 2u
+rept_status rept_stream_set_policy(rept_stream* s, uint32_t policy);
+
+/* Appends counted so far edge by edge and by a windowed recount (host only). */
+rept_status rept_stream_paths(const rept_stream* s, uint64_t* per_edge, uint64_t* recount);
 
 /* Release the handle (not the caller's buffers). */
 void rept_stream_destroy(rept_stream* s);

@@ -82,12 +82,49 @@ struct rept_stream {
     uint64_t capacity, max_chunk;
     IncState st;
     IncCount base;  // parameters of the per-edge count (pointers filled per append)
+    // the windowed recount: the stream in arrival order, and the regions a build of the prefix
+    // and its count use (sized for `capacity` edges)
+    uint32_t* eall;
+    void *gpers, *gscr, *gws;
+    size_t gpers_bytes, gscr_bytes, gws_bytes;
+    uint32_t policy;
+    uint64_t n_per_edge, n_recount;  // appends counted by each path
 };
 namespace {
 bool valid_stream(const rept_stream* s) { return s && s->magic == REPT_STREAM_MAGIC; }
 
+// The per-edge count of an append costs about one binary search per work item (the chunk's total
+// of min(d_u, d_v) over its edges at the chunk's end); the windowed recount, a build and a count
+// of the whole prefix.  On the 1M/20M power-law stream in ten appends the first took 4.4e-11 s
+// per item and the second 4.5e-10 s per prefix edge, so the recount is taken when the items
+// exceed 10 per prefix edge.
+constexpr uint64_t kRecountItemsPerEdge = 10;
+
+// Count the edges at times [t0, t1) of the stream appended so far by the one-shot path: build
+// the prefix [0, t1) into the handle's reserved regions, then add the window's per-edge updates
+// to the handle's counters (rept_count_range: a triangle belongs to the window of its last edge,
+// so this equals Algorithm 1's updates of those edges).  ENOMEM if the prefix needs more than was
+// reserved (the caller then counts edge by edge).
+rept_status recount_window(rept_stream* h, uint64_t t0, uint64_t t1, hipStream_t s) {
+    size_t pb = 0, sb = 0;
+    rept_status st = rept_query_sizes(h->st.n, t1, &pb, &sb);
+    if (st != REPT_OK) return st;
+    if (pb > h->gpers_bytes || sb > h->gscr_bytes) return REPT_ENOMEM;
+    rept_graph* g = nullptr;
+    st = rept_build(h->st.n, h->eall, t1, h->gpers, h->gpers_bytes, h->gscr, h->gscr_bytes, s, &g);
+    if (st != REPT_OK) return st;
+    size_t wb = 0;
+    st = rept_count_workspace_size(g, &h->params, &wb);
+    if (st == REPT_OK && wb > h->gws_bytes) st = REPT_ENOMEM;
+    if (st == REPT_OK)
+        st = rept_count_range(g, &h->params, t0, t1, h->base.global, h->base.local, h->gws, h->gws_bytes, s);
+    rept_destroy(g);
+    return st;
+}
+
 struct IncLayout {
     size_t key[2], tim[2], off, coff, ckey_a, ckey_b, ctim_a, ctim_b, end, flags, temp, total, temp_bytes;
+    size_t eall, gpers, gscr, gws, gpers_bytes, gscr_bytes, gws_bytes;
 };
 size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 IncLayout inc_layout(uint32_t n, uint64_t cap, uint64_t maxc) {
@@ -108,6 +145,15 @@ IncLayout inc_layout(uint32_t n, uint64_t cap, uint64_t maxc) {
     L.flags = p; p = up256(p + 8);
     L.temp_bytes = rept_inc_sort_temp_bytes(C2, 64);
     L.temp = p; p = up256(p + L.temp_bytes);
+    // the windowed recount: the stream in arrival order, a built graph of up to `cap` edges with
+    // its build scratch, and the slot table of its count (at most 8 groups: 16 bytes per edge)
+    L.gpers_bytes = L.gscr_bytes = 0;
+    if (rept_query_sizes(n, cap, &L.gpers_bytes, &L.gscr_bytes) != REPT_OK) L.temp_bytes = 0;  // reported as EDEVICE
+    L.gws_bytes = up256(16 * (size_t)cap);
+    L.eall = p; p = up256(p + 8 * (size_t)cap);
+    L.gpers = p; p = up256(p + L.gpers_bytes);
+    L.gscr = p; p = up256(p + L.gscr_bytes);
+    L.gws = p; p = up256(p + L.gws_bytes);
     L.total = p;
     return L;
 }
@@ -984,6 +1030,14 @@ rept_status rept_stream_create(uint32_t n, uint64_t capacity, uint64_t max_chunk
     S.flags = (uint32_t*)(B + L.flags);
     S.temp = B + L.temp;
     S.temp_bytes = L.temp_bytes;
+    h->eall = (uint32_t*)(B + L.eall);
+    h->gpers = B + L.gpers;
+    h->gscr = B + L.gscr;
+    h->gws = B + L.gws;
+    h->gpers_bytes = L.gpers_bytes;
+    h->gscr_bytes = L.gscr_bytes;
+    h->gws_bytes = L.gws_bytes;
+    h->policy = REPT_STREAM_AUTO;
     const uint32_t cus = rept_num_cus() ? rept_num_cus() : 256;
     S.count_blocks = 8 * cus;
     IncCount& a = h->base;
@@ -1035,7 +1089,42 @@ rept_status rept_stream_append(rept_stream* h, const uint32_t* edges, uint64_t n
     if (flags & RF_RANGE) return REPT_ERANGE;
     if (flags & RF_SELFLOOP) return REPT_ESELFLOOP;
     if (flags & RF_DUP) return REPT_EDUP;
-    if (rept_inc_commit(h->st, num_edges, h->base, s) != hipSuccess) return REPT_EDEVICE;
+    const uint64_t t0 = h->st.T;
+    if (hipMemcpyAsync(h->eall + 2 * t0, edges, 8 * num_edges, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        rept_inc_merge(h->st, num_edges, s) != hipSuccess)
+        return REPT_EDEVICE;
+    bool recount = h->policy == REPT_STREAM_RECOUNT;
+    if (h->policy == REPT_STREAM_AUTO) {
+        uint64_t items = 0;
+        if (hipMemcpyAsync(&items, h->st.end + 2 * num_edges - 1, sizeof(items), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return REPT_EDEVICE;
+        recount = items > kRecountItemsPerEdge * h->st.T;
+    }
+    if (recount) {
+        const rept_status st = recount_window(h, t0, h->st.T, s);
+        if (st == REPT_OK) {
+            ++h->n_recount;
+            return REPT_OK;
+        }
+        if (st != REPT_ENOMEM) return st;  // ENOMEM: the prefix outgrew the reserved regions
+    }
+    if (rept_inc_count(h->st, num_edges, h->base, s) != hipSuccess) return REPT_EDEVICE;
+    ++h->n_per_edge;
+    return REPT_OK;
+}
+
+rept_status rept_stream_set_policy(rept_stream* h, uint32_t policy) {
+    if (!valid_stream(h) || policy > REPT_STREAM_RECOUNT) return REPT_EINVAL;
+    h->policy = policy;
+    return REPT_OK;
+}
+
+rept_status rept_stream_paths(const rept_stream* h, uint64_t* per_edge, uint64_t* recount) {
+    if (!valid_stream(h) || !per_edge || !recount) return REPT_EINVAL;
+    *per_edge = h->n_per_edge;
+    *recount = h->n_recount;
     return REPT_OK;
 }
 

@@ -196,11 +196,15 @@ struct IncCount {
     uint32_t ck_full, last_ck, pstride, per_proc;  // processor map as in JobDev
     uint64_t hp[4 * REPT_GMAX];
 };
-// rocPRIM temporary bytes for sorting `entries` keys of end_bit bits and scanning as many lengths
-// (queries the current device; 0 on failure)
+// temporary bytes for sorting `entries` keys of end_bit bits and scanning as many lengths (the
+// library's own radix sort and scans; 0 on failure)
 size_t rept_inc_sort_temp_bytes(uint64_t entries, uint32_t end_bit);
 hipError_t rept_inc_zero64(void* p, uint64_t words, hipStream_t stream);
 // steps 1-3 of an append (keys, sort, validation, chunk runs); the state is not changed
 hipError_t rept_inc_prepare(const IncState& st, const uint32_t* edges, uint64_t W, hipStream_t stream);
-// steps 4-5 (merge, count); advances st.cur and st.T
-hipError_t rept_inc_commit(IncState& st, uint64_t W, const IncCount& base, hipStream_t stream);
+// step 4: merge the chunk into the adjacency and scan the chunk's work items (one per entry of
+// the shorter list of each chunk edge's endpoints; the total is st.end[2W - 1]); advances st.cur
+// and st.T
+hipError_t rept_inc_merge(IncState& st, uint64_t W, hipStream_t stream);
+// step 5: count each chunk edge against the edges that arrived before it (after rept_inc_merge)
+hipError_t rept_inc_count(const IncState& st, uint64_t W, const IncCount& base, hipStream_t stream);

@@ -508,7 +508,7 @@ hipError_t rept_inc_prepare(const IncState& st, const uint32_t* edges, uint64_t 
     return hipGetLastError();
 }
 
-hipError_t rept_inc_commit(IncState& st, uint64_t W, const IncCount& base, hipStream_t s) {
+hipError_t rept_inc_merge(IncState& st, uint64_t W, hipStream_t s) {
     (void)hipGetLastError();
     const uint64_t N2 = 2 * W, N = 2 * st.T;
     const int nxt = st.cur ^ 1;
@@ -522,11 +522,15 @@ hipError_t rept_inc_commit(IncState& st, uint64_t W, const IncCount& base, hipSt
     if (e != hipSuccess) return e;
     st.cur = nxt;
     st.T += W;
-    // the count of the chunk's edges against the merged adjacency
+    // the chunk's work items: one per entry of the shorter endpoint list of each chunk edge
     uint64_t* len = st.ckey_a;  // free after the sort
     hipLaunchKernelGGL(k_inc_lens, dim3(grid_of(N2, 8192)), dim3(kThreads), 0, s, st.ckey_b, N2, st.off, len);
-    e = scan_items<uint64_t, true>(len, N2, (uint64_t*)((uint8_t*)st.temp + sort_temp(N2).part), st.end, s);
-    if (e != hipSuccess) return e;
+    return scan_items<uint64_t, true>(len, N2, (uint64_t*)((uint8_t*)st.temp + sort_temp(N2).part), st.end, s);
+}
+
+hipError_t rept_inc_count(const IncState& st, uint64_t W, const IncCount& base, hipStream_t s) {
+    (void)hipGetLastError();
+    const uint64_t N2 = 2 * W;
     IncCount a = base;
     a.key = st.key[st.cur];
     a.tim = st.tim[st.cur];

@@ -90,6 +90,8 @@ def lib() -> ctypes.CDLL:
             "rept_stream_create": ([u32, u64, u64, P(rept_params), vp, sz, vp, vp, vp, P(vp)], i32),
             "rept_stream_append": ([vp, vp, u64, vp], i32),
             "rept_stream_num_edges": ([vp, P(u64)], i32),
+            "rept_stream_set_policy": ([vp, u32], i32),
+            "rept_stream_paths": ([vp, P(u64), P(u64)], i32),
             "rept_stream_destroy": ([vp], None),
             "rept_reduce_local": ([vp, u32, u32, vp, vp], i32),
             "rept_hash_slots": ([P(rept_params), vp, u64, vp, vp], i32),
@@ -113,7 +115,8 @@ EXPORTED = ["rept_local_rows", "rept_query_sizes", "rept_build", "rept_build_hos
             "rept_count_workspace_size", "rept_count", "rept_count_noalloc",
             "rept_count_range", "rept_estimate", "rept_estimate_sums", "rept_count_eta_workspace_size",
             "rept_count_eta", "rept_estimate_combined", "rept_stream_query_sizes", "rept_stream_create",
-            "rept_stream_append", "rept_stream_num_edges", "rept_stream_destroy", "rept_reduce_local", "rept_hash_slots", "rept_batch_workspace_size",
+            "rept_stream_append", "rept_stream_num_edges", "rept_stream_set_policy", "rept_stream_paths",
+            "rept_stream_destroy", "rept_reduce_local", "rept_hash_slots", "rept_batch_workspace_size",
             "rept_batch_prepare", "rept_batch_launch", "rept_batch_count", "rept_destroy", "rept_status_str",
             "rept_device_cus"]
 
@@ -333,6 +336,20 @@ def rept_stream_num_edges(handle: int) -> int:
     return v.value
 
 
+REPT_STREAM_AUTO, REPT_STREAM_PER_EDGE, REPT_STREAM_RECOUNT = 0, 1, 2
+STREAM_POLICIES = {"auto": REPT_STREAM_AUTO, "per_edge": REPT_STREAM_PER_EDGE, "recount": REPT_STREAM_RECOUNT}
+
+
+def rept_stream_set_policy(handle: int, policy: int):
+    _check(lib().rept_stream_set_policy(handle, policy), "rept_stream_set_policy")
+
+
+def rept_stream_paths(handle: int) -> tuple[int, int]:
+    a, b = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(lib().rept_stream_paths(handle, ctypes.byref(a), ctypes.byref(b)), "rept_stream_paths")
+    return a.value, b.value
+
+
 def rept_stream_destroy(handle: int):
     lib().rept_stream_destroy(handle)
 
@@ -481,7 +498,9 @@ class IncrementalStream:
     """A stream appended chunk by chunk on the device; `counts` (global int64[c], local
     int64[rows][n]) always hold Algorithm 1's updates of every edge appended so far."""
 
-    def __init__(self, n: int, capacity: int, max_chunk: int, params: Params, device="cuda", stream=None):
+    def __init__(self, n: int, capacity: int, max_chunk: int, params: Params, device="cuda", stream=None,
+                 policy: str = "auto"):
+        """policy: how appends count their edges ("auto", "per_edge" or "recount"; equal results)."""
         import torch
         self.n, self.params, self.device = int(n), params, torch.device(device)
         nbytes = rept_stream_query_sizes(self.n, capacity, max_chunk)
@@ -490,6 +509,7 @@ class IncrementalStream:
                        torch.empty((params.rows, self.n), dtype=torch.int64, device=self.device))
         self.handle = rept_stream_create(self.n, capacity, max_chunk, params, self.buffer.data_ptr(), nbytes,
                                          self.counts[0].data_ptr(), self.counts[1].data_ptr(), _stream_ptr(stream))
+        rept_stream_set_policy(self.handle, STREAM_POLICIES[policy])
 
     def append(self, edges_dev, stream=None):
         """Append a device [W, 2] chunk (int32 bits of uint32 ids).  Raises ReptError (state
@@ -504,6 +524,10 @@ class IncrementalStream:
     @property
     def num_edges(self) -> int:
         return rept_stream_num_edges(self.handle)
+
+    def paths(self) -> tuple[int, int]:
+        """(appends counted edge by edge, appends counted by a windowed recount)."""
+        return rept_stream_paths(self.handle)
 
     def estimate(self):
         """(tau_hat, tau_v_hat) of the stream so far (synchronises)."""

@@ -1,6 +1,7 @@
 """Incremental streams on the device: after every appended chunk the counters equal the
 oracle's replay of the stream so far (bit for bit), for REPT (all group layouts) and parallel
-MASCOT; invalid chunks are refused and leave the state unchanged.
+MASCOT, whether appends count edge by edge or by a windowed recount of the prefix; invalid
+chunks are refused and leave the state unchanged.
 
 Each case prints its name and shape before touching the GPU."""
 import numpy as np
@@ -31,35 +32,48 @@ def _check(inc, edges_so_far, n, p):
     assert inc.num_edges == len(edges_so_far)
 
 
+def _paths_follow(inc, policy, appends):
+    per_edge, recount = inc.paths()
+    assert per_edge + recount == appends
+    if policy == "per_edge":
+        assert recount == 0
+    elif policy == "recount":
+        assert per_edge == 0
+
+
+@pytest.mark.parametrize("policy", ["per_edge", "recount"])
 @pytest.mark.parametrize("m,c,per_proc,mascot", [(3, 7, False, False), (1, 1, False, False), (10, 40, False, False),
                                                  (4, 4, True, False), (2, 5, False, True), (5, 3, False, False)])
-def test_chunks_equal_oracle_prefixes(cuda, m, c, per_proc, mascot):
+def test_chunks_equal_oracle_prefixes(cuda, m, c, per_proc, mascot, policy):
     from paper_1811_09136_amd import rept
     e = synth.er(300, 3000, 7 + m, 8 + c)
     p = rept.Params(m, c, 40 + m * c, per_proc, mascot)
-    _say(f"stream ER n=300 E=3000 m={m} c={c} per_proc={per_proc} mascot={mascot}")
-    inc = rept.IncrementalStream(300, 3000, 1200, p, cuda)
+    _say(f"stream ER n=300 E=3000 m={m} c={c} per_proc={per_proc} mascot={mascot} policy={policy}")
+    inc = rept.IncrementalStream(300, 3000, 1200, p, cuda, policy=policy)
     cuts = [0, 1, 8, 9, 1000, 1700, 2900, 3000]
     for a, b in zip(cuts[:-1], cuts[1:]):
         inc.append(rept.to_device_edges(e[a:b], cuda))
         _check(inc, e[:b], 300, p)
+    _paths_follow(inc, policy, len(cuts) - 1)
     inc.close()
 
 
-def test_hub_stream_and_estimates(cuda):
+@pytest.mark.parametrize("policy", ["auto", "per_edge", "recount"])
+def test_hub_stream_and_estimates(cuda, policy):
     """A power-law stream with hub lists in uneven chunks; the estimates after each chunk
     equal the oracle's estimates of the prefix (0 ulp)."""
     from paper_1811_09136_amd import rept
     e, n = synth.scaled_chung_lu(200_000, 19)
     p = rept.Params(10, 40, 3)
-    _say(f"stream Chung-Lu n={n} E={len(e)} m=10 c=40")
-    inc = rept.IncrementalStream(n, len(e), 90_000, p, cuda)
+    _say(f"stream Chung-Lu n={n} E={len(e)} m=10 c=40 policy={policy}")
+    inc = rept.IncrementalStream(n, len(e), 90_000, p, cuda, policy=policy)
     for a, b in [(0, 50_000), (50_000, 50_001), (50_001, 140_000), (140_000, 200_000)]:
         inc.append(rept.to_device_edges(e[a:b], cuda))
         og, ol = oracle.rept(e[:b], n, 10, 40, 3)
         th, tv = inc.estimate()
         oth, otv = oracle.estimate(n, 10, 40, og, ol)
         assert th == oth and np.array_equal(tv.view(np.uint64), otv.view(np.uint64))
+    _paths_follow(inc, policy, 4)
     inc.close()
 
 
@@ -70,13 +84,14 @@ def test_equals_count_on_the_whole_stream(cuda):
     e, n = synth.scaled_chung_lu(300_000, 23)
     p = rept.Params(10, 15, 8)
     _say(f"stream vs rept_count Chung-Lu n={n} E={len(e)} m=10 c=15")
-    inc = rept.IncrementalStream(n, len(e), 100_000, p, cuda)
+    inc = rept.IncrementalStream(n, len(e), 100_000, p, cuda, policy="recount")
     for a in range(0, len(e), 100_000):
         inc.append(rept.to_device_edges(e[a:a + 100_000], cuda))
     g = rept.Graph(rept.to_device_edges(e, cuda), n)
     glob, loc = g.count(p)
     torch.cuda.synchronize()
     assert torch.equal(inc.counts[0], glob) and torch.equal(inc.counts[1], loc)
+    _paths_follow(inc, "recount", 3)
     g.close()
     inc.close()
 
