@@ -45,6 +45,24 @@ def test_host_only_calls():
     assert lib.rept_local_rows(ctypes.byref(p)) == 0
 
 
+@pytest.mark.parametrize("n,cap,chunk", [(300, 3000, 1200), (1_000_000, 20_000_000, 2_000_000), (1 << 29, 1, 1)])
+def test_stream_buffer_size(n, cap, chunk):
+    """rept_stream_query_sizes (host only) as its declaration states it: 48 bytes per edge of
+    capacity, 64 per edge of chunk, 8 per node and the sort's temporary storage for the appends;
+    24 bytes per edge of capacity and a build's persistent and scratch bytes for the recount.
+    Regions are 256-byte aligned, so the total exceeds the sum by less than 256 per region plus
+    the sort storage (a few tile counters per 4096 entries)."""
+    from paper_1811_09136_amd import rept
+    total = rept.rept_stream_query_sizes(n, cap, chunk)
+    pb, sb = rept.rept_query_sizes(n, cap)
+    floor = 48 * cap + 64 * chunk + 8 * (n + 1) + 24 * cap + pb + sb
+    assert floor <= total <= floor + 20 * 256 + 4 * (2 * chunk) + (1 << 20)
+    for bad in [(0, 10, 1), (1 << 30, 10, 1), (10, 0, 1), (10, 1 << 31, 1), (10, 10, 0), (10, 10, 11)]:
+        with pytest.raises(rept.ReptError) as ei:
+            rept.rept_stream_query_sizes(*bad)
+        assert ei.value.code == rept.REPT_EINVAL
+
+
 @pytest.mark.parametrize("m,c", [(1, 1), (10, 10), (10, 40), (7, 3), (100, 400), (3, 1)])
 def test_estimate_zero_ulp_against_oracle(m, c):
     from paper_1811_09136_amd import rept
