@@ -183,3 +183,28 @@ def test_arena_first_fit_and_coalescing():
     a.release(*x)
     a.release(*z)
     assert a.free == [(0, 4096)]
+
+
+def test_lone_newcomer_is_held_until_the_last_launch_completes():
+    """One request in service with its remaining units in one launch, and one newcomer: with the
+    hold rule the newcomer is admitted only when that launch has completed and the request is
+    retired; without it, at once.  Results are exact either way."""
+    def run(hold):
+        clk = FakeClock()
+        ex = FakeExecutor(clk)
+        a = Request(0, 0.0, synth.er(200, 1250, 5, 6), 200, 3, 3, 11)  # 25 units: launches of 10, 10, 5
+        b = Request(1, 0.0015, synth.er(150, 600, 7, 8), 150, 2, 4, 12)  # arrives after A's second launch
+        srv = Server(ex, budget_bytes=10**9, max_active=4, chunk_units=10, build_workers=1,
+                     hold_lone_newcomer=hold)
+        res = srv.run([a, b], clock=clk, sleep=clk.sleep)
+        for r, q in zip(res, [a, b]):
+            g, l = oracle.rept(q.edges, q.n, q.m, q.c, q.seed)
+            assert r.status == "ok" and np.array_equal(r.glob, g) and np.array_equal(r.loc, l)
+        spans_a = [(u0, u1) for L in ex.launches for rid, u0, u1 in L if rid == 0]
+        assert spans_a == [(0, 10), (10, 20), (20, 25)]
+        return res
+
+    ra, rb = run(True)
+    assert rb.admitted_s >= ra.done_s  # held: admitted once A's last launch completed
+    ra, rb = run(False)
+    assert rb.admitted_s < ra.done_s  # admitted while A's last units were still to run
